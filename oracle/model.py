@@ -1,0 +1,174 @@
+"""Discrete model of the flat-layer problem (oracle; test infrastructure only).
+
+Follows the paper's Section 1 (eq. 1-4), Section 2 (eq. 5) and Section 5
+(discretization on uniform grids; G~ and U~0 from the FFT of sampled
+functions). Conventions of this build, each a reading of a passage the paper
+leaves open:
+
+* X cells are centred: x_i = (i + 1/2) h, z'_l = (l + 1/2) h, quadrature
+  weight h per direction (midpoint rule for the mu_kl of Section 5.2).
+* The horizontal plane is a Px x Py torus; X's nx x ny window sits at offset
+  o = ((Px - nx) // 2, (Py - ny) // 2). Horizontal distances use the minimum
+  image, so for points inside the window the torus sum equals the infinite
+  layer sum as long as Px >= 2 nx - 1.
+* The 2D transform is the unnormalized DFT with exp(-i ...) (Section 2 prints
+  exp(+i(Omega1 x + Omega1 y)); the sign flip leaves xi unchanged, a pinned
+  invariant); the inverse carries 1/(Px Py).
+* Ĝ_zeta[m] = h^2 * DFT(G sampled on the torus at height zeta) (Section 5:
+  the discrete G~ comes from the FFT of sampled G).
+* A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu = h).
+* The in-X volume potential of eq. (4)/(9) is the linear convolution of v
+  with kappa[d] = h^3 G(h |d|), d != 0, and at d = 0 the integral of G over
+  the ball of volume h^3 (the paper is silent on the self cell).
+
+Parity: every function here is pinned (brute-force direct sums, numerical
+quadrature, closed forms) by tests/test_oracle_model.py.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def green(rho, k0):
+    """G(rho) = -exp(i k0 rho) / (4 pi rho) (Section 1, Green function of
+    the Helmholtz operator with k0 = omega / c0)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    return -np.exp(1j * k0 * rho) / (4.0 * np.pi * rho)
+
+
+def min_image(n: int) -> np.ndarray:
+    """Signed torus offsets 0, 1, ..., n/2, -(n/2 - 1), ..., -1 (n/2 kept
+    positive; G is radial so its sign is immaterial)."""
+    i = np.arange(n)
+    return np.where(i <= n // 2, i, i - n)
+
+
+def window_offset(p):
+    return ((p.px - p.nx) // 2, (p.py - p.ny) // 2)
+
+
+def z_cells(p) -> np.ndarray:
+    return (np.arange(p.nz) + 0.5) * p.h
+
+
+def k0_of(p, f: int) -> float:
+    return float(p.omegas[f]) / float(p.c0)
+
+
+def horizontal_rho2(p) -> np.ndarray:
+    """Squared horizontal minimum-image distances on the torus, (py, px)."""
+    dx = p.h * min_image(p.px)
+    dy = p.h * min_image(p.py)
+    return dy[:, None] ** 2 + dx[None, :] ** 2
+
+
+def plane_kernel_hat(p, k0: float, zeta: float) -> np.ndarray:
+    """Ĝ_zeta[my, mx] = h^2 * sum_p G(sqrt(rho_p^2 + zeta^2)) e^{-2 pi i p.m/P}
+    for one height difference zeta != 0 (Section 5, FFT of sampled G)."""
+    g = green(np.sqrt(horizontal_rho2(p) + zeta * zeta), k0)
+    return p.h * p.h * np.fft.fft2(g)
+
+
+def zeta_index(p):
+    """Distinct height differences z_j - z'_l and the map (j, l) -> index.
+
+    Returns (zetas, idx) with idx shaped (nd, nz). When the data planes lie
+    on X's z-lattice there are nd + nz - 1 distinct values."""
+    zeta = np.asarray(p.planes, np.float64)[:, None] - z_cells(p)[None, :]
+    key = np.round(zeta / (p.h * 1e-9)).astype(np.int64)
+    uniq, inv = np.unique(key, return_inverse=True)
+    zetas = np.empty(len(uniq))
+    zetas[inv.ravel()] = zeta.ravel()
+    return zetas, inv.reshape(zeta.shape)
+
+
+def system_table(p, f: int):
+    """Ĝ for every distinct zeta at frequency f: (n_zeta, py, px), plus the
+    (nd, nz) index map of zeta_index."""
+    k0 = k0_of(p, f)
+    zetas, idx = zeta_index(p)
+    tab = np.stack([plane_kernel_hat(p, k0, z) for z in zetas])
+    return tab, idx
+
+
+def system_matrices(p, f: int, tab, idx, ms) -> np.ndarray:
+    """A_m for the flat system indices ms (m = my*px + mx): (len(ms), nd, nz).
+
+    A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = h)."""
+    om = float(p.omegas[f])
+    ms = np.asarray(ms)
+    flat = tab.reshape(tab.shape[0], -1)          # (n_zeta, py*px)
+    return (om * om * p.h) * flat[idx][:, :, ms].transpose(2, 0, 1)
+
+
+def embed(p, vX: np.ndarray) -> np.ndarray:
+    """Place a field on X's window, (nz, ny, nx), into the (nz, py, px) torus."""
+    ox, oy = window_offset(p)
+    out = np.zeros((vX.shape[0], p.py, p.px), np.complex128)
+    out[:, oy:oy + p.ny, ox:ox + p.nx] = vX
+    return out
+
+
+def crop(p, v: np.ndarray) -> np.ndarray:
+    """Restrict a torus field (..., py, px) to X's window (..., ny, nx)."""
+    ox, oy = window_offset(p)
+    return v[..., oy:oy + p.ny, ox:ox + p.nx]
+
+
+def data_operator(p, f: int, vX: np.ndarray, tab=None, idx=None) -> np.ndarray:
+    """W[j] = omega^2 * int_X G(|x - x'|) v(x') dx' on the data planes
+    (eq. 3; eq. 7 second line after the 2D transform), discretized on the
+    torus. vX: (nz, ny, nx) -> W: (nd, py, px)."""
+    if tab is None:
+        tab, idx = system_table(p, f)
+    om = float(p.omegas[f])
+    V = np.fft.fft2(embed(p, vX))                  # (nz, py, px)
+    What = np.zeros((p.nd, p.py, p.px), np.complex128)
+    for j in range(p.nd):
+        for l in range(p.nz):
+            What[j] += tab[idx[j, l]] * V[l]
+    return (om * om * p.h) * np.fft.ifft2(What)
+
+
+def self_cell(k0: float, h: float) -> complex:
+    """Integral of G over the ball of volume h^3 centred at the singularity:
+    a = h (3/(4 pi))^(1/3), S = (1 - (1 - i k0 a) e^{i k0 a}) / k0^2."""
+    a = h * (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+    ika = 1j * k0 * a
+    return complex((1.0 - (1.0 - ika) * np.exp(ika)) / (k0 * k0))
+
+
+def conv_kernel(p, k0: float) -> np.ndarray:
+    """kappa on the zero-padded (2nz, 2ny, 2nx) torus with minimum-image
+    offsets: h^3 G(h|d|) for d != 0 and the self-cell integral at d = 0."""
+    dz = min_image(2 * p.nz)
+    dy = min_image(2 * p.ny)
+    dx = min_image(2 * p.nx)
+    r = p.h * np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2
+                      + dx[None, None, :] ** 2)
+    r[0, 0, 0] = 1.0
+    kap = p.h ** 3 * green(r, k0)
+    kap[0, 0, 0] = self_cell(k0, p.h)
+    return kap
+
+
+def volume_potential(p, f: int, vX: np.ndarray) -> np.ndarray:
+    """omega^2 * int_X G(|x - x'|) v(x') dx' for x in X (eq. 4 / eq. 9), as a
+    zero-padded 3D FFT linear convolution. vX: (nz, ny, nx)."""
+    k0 = k0_of(p, f)
+    om = float(p.omegas[f])
+    shape = (2 * p.nz, 2 * p.ny, 2 * p.nx)
+    K = np.fft.fftn(conv_kernel(p, k0))
+    Vp = np.zeros(shape, np.complex128)
+    Vp[:p.nz, :p.ny, :p.nx] = vX
+    out = np.fft.ifftn(K * np.fft.fftn(Vp))
+    return (om * om) * out[:p.nz, :p.ny, :p.nx]
+
+
+def closed_form_ghat(kx, ky, zeta, k0):
+    """Continuous 2D transform of G at height difference zeta:
+    -i exp(i gamma |zeta|) / (2 gamma), gamma = sqrt(k0^2 - |k|^2), Im gamma >= 0
+    (Weyl expansion of the point-source field). Used by pins only."""
+    g = np.sqrt(np.asarray(k0 * k0 - kx * kx - ky * ky, np.complex128))
+    g = np.where(g.imag < 0, -g, g)
+    return -1j * np.exp(1j * g * abs(zeta)) / (2.0 * g)

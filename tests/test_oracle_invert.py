@@ -1,0 +1,102 @@
+"""Pins of the oracle's Algorithm 2 pipeline (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import forward, invert, model
+from paper_1911_10487_amd import synth
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = synth.workload("small")[0]
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, U, V, info = forward.synthesize(p, xi, u0)
+    return p, xi, u0, W, U, V
+
+
+def test_items_2_and_3_return_the_truth_from_the_true_current(small):
+    # Fed the exact v = xi * u of the forward solve, eq. (9) rebuilds u and
+    # item 3 returns xi (BiCGSTAB tolerance 1e-12).
+    p, xi, u0, W, U, V = small
+    u = u0[0] + model.volume_potential(p, 0, V[0])
+    assert np.linalg.norm(u - U[0]) <= 1e-10 * np.linalg.norm(U[0])
+    x = invert.combine_lsq(u[None], V[0][None])
+    assert np.linalg.norm(x - xi) <= 1e-10 * np.linalg.norm(xi)
+
+
+def test_item_1_sees_the_data_operator(small):
+    # the transformed data of every wavenumber is A_m applied to V^_m
+    p, xi, u0, W, U, V = small
+    What = np.fft.fft2(W[0]).reshape(p.nd, -1)
+    Vh = np.fft.fft2(model.embed(p, V[0])).reshape(p.nz, -1)
+    tab, idx = model.system_table(p, 0)
+    ms = np.arange(0, p.px * p.py, 37)
+    A = model.system_matrices(p, 0, tab, idx, ms)
+    lhs = np.einsum("mjl,lm->jm", A, Vh[:, ms])
+    assert np.linalg.norm(lhs - What[:, ms]) <= 1e-12 * np.linalg.norm(What[:, ms])
+
+
+def test_flipping_the_transform_sign_leaves_xi_unchanged(small, monkeypatch):
+    # Section 2 prints exp(+i ...); this build uses exp(-i ...). G is radial,
+    # so the two conventions give the same xi.
+    p, xi, u0, W, U, V = small
+    Wd = synth.add_noise(p, W, 0.01)
+    ref = invert.invert(p, Wd, u0, 0.01)
+    f2, if2 = np.fft.fft2, np.fft.ifft2
+    monkeypatch.setattr(np.fft, "fft2", lambda x, *a, **k: np.conj(f2(np.conj(x), *a, **k)))
+    monkeypatch.setattr(np.fft, "ifft2", lambda x, *a, **k: np.conj(if2(np.conj(x), *a, **k)))
+    flipped = invert.invert(p, Wd, u0, 0.01)
+    assert np.linalg.norm(flipped - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_mirror_symmetry(small):
+    # Mirroring x about X's centre (data, incident field) mirrors xi.
+    p, xi, u0, W, U, V = small
+    Wd = synth.add_noise(p, W, 0.01)
+    ref = invert.invert(p, Wd, u0, 0.01)
+    ox, _ = model.window_offset(p)
+    perm = (2 * ox + p.nx - 1 - np.arange(p.px)) % p.px
+    Wm = Wd[..., perm]
+    um = u0[..., ::-1]
+    got = invert.invert(p, Wm, um, 0.01)
+    assert np.linalg.norm(got - ref[..., ::-1]) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_one_frequency_least_squares_is_the_quotient():
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((1, 4, 5)) + 1j * rng.standard_normal((1, 4, 5))
+    v = rng.standard_normal((1, 4, 5)) + 1j * rng.standard_normal((1, 4, 5))
+    assert np.allclose(invert.combine_lsq(u, v), v[0] / u[0], rtol=1e-15, atol=0)
+    u[0, 0, 0] = 0
+    assert invert.combine_lsq(u, v)[0, 0] == 0
+
+
+def test_duplicated_frequency_gives_the_same_xi(small):
+    p, xi, u0, W, U, V = small
+    Wd = synth.add_noise(p, W, 0.01)
+    ref = invert.invert(p, Wd, u0, 0.01)
+    p2 = synth.make_problem("dup", p.nx, p.ny, p.nz, [p.omegas[0]] * 2, 3, (0, 0))
+    got = invert.invert(p2, np.concatenate([Wd, Wd]), np.concatenate([u0, u0]), 0.01)
+    assert np.linalg.norm(got - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+def test_noise_level_by_parseval(small):
+    p, xi, u0, W, U, V = small
+    Wd = synth.add_noise(p, W, 0.01)
+    What = np.fft.fft2(Wd[0])
+    a = invert.system_noise_level(Wd[0], 0.01)
+    b = invert.system_noise_level_hat(What, 0.01, p.px * p.py)
+    assert abs(a - b) <= 1e-14 * a
+
+
+def test_reconstruction_is_meaningful(small):
+    # Not a parity gate (the problem is severely ill-posed, Section 6): the
+    # reconstruction still carries the blobs.
+    p, xi, u0, W, U, V = small
+    x0, st = invert.invert(p, W, u0, 0.0, stages=True)
+    assert np.all(st["branch"] == 1)
+    assert np.linalg.norm(x0.real - xi) < 0.5 * np.linalg.norm(xi)
+    x1, st = invert.invert(p, synth.add_noise(p, W, 0.01), u0, 0.01, stages=True)
+    assert np.linalg.norm(x1.real - xi) < 0.8 * np.linalg.norm(xi)
+    assert (st["branch"] == 0).mean() > 0.5

@@ -1,0 +1,181 @@
+"""Pins of the oracle's discrete model against brute force, quadrature and
+closed forms (no GPU)."""
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import model
+from paper_1911_10487_amd import synth
+
+
+def _brute_data(p, f, vX):
+    """W[j, py, px] = omega^2 h^3 sum_{l, window q} G(|x_p,j - x_q,l|) v[l, q]
+    with minimum-image horizontal distances: eq. (3) with the midpoint rule,
+    written as a direct sum."""
+    om = p.omegas[f]
+    k0 = om / p.c0
+    ox, oy = model.window_offset(p)
+    zx = (np.arange(p.nz) + 0.5) * p.h
+    W = np.zeros((p.nd, p.py, p.px), complex)
+    for j in range(p.nd):
+        for py in range(p.py):
+            for px in range(p.px):
+                acc = 0j
+                for l in range(p.nz):
+                    for iy in range(p.ny):
+                        for ix in range(p.nx):
+                            dx = (px - (ix + ox)) % p.px
+                            dy = (py - (iy + oy)) % p.py
+                            dx = dx if dx <= p.px // 2 else dx - p.px
+                            dy = dy if dy <= p.py // 2 else dy - p.py
+                            r = np.sqrt((dx * p.h) ** 2 + (dy * p.h) ** 2
+                                        + (p.planes[j] - zx[l]) ** 2)
+                            acc += -np.exp(1j * k0 * r) / (4 * np.pi * r) * vX[l, iy, ix]
+                W[j, py, px] = om * om * p.h ** 3 * acc
+    return W
+
+
+def test_data_operator_matches_direct_sum():
+    # non-square window and torus so that an x/y swap cannot pass
+    p = synth.tiny_problem(nx=3, ny=2, nz=2, nd=3, px=8, py=6)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 1))
+    W = model.data_operator(p, 0, vX)
+    Wb = _brute_data(p, 0, vX)
+    assert np.linalg.norm(W - Wb) <= 1e-13 * np.linalg.norm(Wb)
+
+
+def test_system_matrix_is_the_data_operator_per_wavenumber():
+    p = synth.tiny_problem(nx=3, ny=2, nz=2, nd=3, px=8, py=6)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 2))
+    W = model.data_operator(p, 0, vX)
+    What = np.fft.fft2(W).reshape(p.nd, -1)
+    V = np.fft.fft2(model.embed(p, vX)).reshape(p.nz, -1)
+    tab, idx = model.system_table(p, 0)
+    ms = np.arange(p.px * p.py)
+    A = model.system_matrices(p, 0, tab, idx, ms)
+    lhs = np.einsum("mjl,lm->jm", A, V)
+    assert np.linalg.norm(lhs - What) <= 1e-13 * np.linalg.norm(What)
+    # on-lattice planes: nd + nz - 1 distinct heights, Toeplitz systems
+    assert tab.shape[0] == p.nd + p.nz - 1
+    assert np.allclose(A[:, 1:, 1:], A[:, :-1, :-1], rtol=0, atol=0)
+
+
+def _brute_volume(p, f, vX):
+    om = p.omegas[f]
+    k0 = om / p.c0
+    S = model.self_cell(k0, p.h)
+    out = np.zeros_like(vX)
+    idx = [(l, iy, ix) for l in range(p.nz) for iy in range(p.ny) for ix in range(p.nx)]
+    for a in idx:
+        acc = 0j
+        for b in idx:
+            d = np.array(a) - np.array(b)
+            if not d.any():
+                acc += S * vX[b]
+            else:
+                r = p.h * np.linalg.norm(d)
+                acc += p.h ** 3 * (-np.exp(1j * k0 * r) / (4 * np.pi * r)) * vX[b]
+        out[a] = om * om * acc
+    return out
+
+
+def test_volume_potential_matches_direct_sum():
+    p = synth.tiny_problem(nx=3, ny=4, nz=2)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 3))
+    u = model.volume_potential(p, 0, vX)
+    ub = _brute_volume(p, 0, vX)
+    assert np.linalg.norm(u - ub) <= 1e-13 * np.linalg.norm(ub)
+
+
+@pytest.mark.parametrize("k0", [0.7, 2 * np.pi, 5 * np.pi])
+def test_self_cell_is_the_ball_integral(k0):
+    h = 0.125
+    a = h * (3 / (4 * np.pi)) ** (1 / 3)
+    # int_ball G dV = int_0^a 4 pi r^2 G(r) dr, evaluated numerically
+    re = integrate.quad(lambda r: (-r * np.exp(1j * k0 * r)).real, 0, a, epsabs=1e-22, epsrel=1e-13)[0]
+    im = integrate.quad(lambda r: (-r * np.exp(1j * k0 * r)).imag, 0, a, epsabs=1e-22, epsrel=1e-13)[0]
+    S = model.self_cell(k0, h)
+    assert abs(S - (re + 1j * im)) <= 1e-12 * abs(S)
+    # the ball has the cell's volume
+    assert abs(4 / 3 * np.pi * a ** 3 - h ** 3) < 1e-15
+
+
+def test_self_cell_low_frequency_series():
+    # -int_0^a r e^{ikr} dr = -a^2/2 - i k a^3/3 + k^2 a^4/8 + O(k^3 a^5)
+    h = 0.125
+    a = h * (3 / (4 * np.pi)) ** (1 / 3)
+    k = 1e-2
+    series = -a * a / 2 - 1j * k * a ** 3 / 3 + k * k * a ** 4 / 8
+    assert abs(model.self_cell(k, h) - series) < 1e-8 * a * a
+
+
+def test_green_solves_helmholtz_away_from_source():
+    k0 = 2 * np.pi
+    x0 = np.array([0.31, -0.22, 0.47])
+    e = 1e-3
+    g = lambda x: model.green(np.linalg.norm(x), k0)
+    lap = sum(g(x0 + e * ei) + g(x0 - e * ei) - 2 * g(x0) for ei in np.eye(3)) / e ** 2
+    assert abs(lap + k0 * k0 * g(x0)) < 1e-4 * abs(k0 * k0 * g(x0))
+
+
+def test_green_unit_flux():
+    # Delta G = delta: the flux of grad G through a small sphere tends to 1
+    k0 = 2 * np.pi
+    r, e = 1e-4, 1e-8
+    dGdr = (model.green(r + e, k0) - model.green(r - e, k0)) / (2 * e)
+    assert abs(4 * np.pi * r * r * dGdr - 1) < 1e-3
+
+
+@pytest.mark.parametrize("kx,ky", [(1.0, 0.5), (3.0, -2.0), (8.0, 1.0)])
+def test_closed_form_ghat_against_hankel_quadrature(kx, ky):
+    # 2D transform of the (slightly damped) point-source field as the Hankel
+    # integral 2 pi int_0^inf G(sqrt(rho^2 + zeta^2)) J0(|k| rho) rho drho
+    k0 = 2 * np.pi * (1 + 0.05j)
+    zeta = 0.3
+    kk = np.hypot(kx, ky)
+    def integrand(r, part):
+        R = np.sqrt(r * r + zeta * zeta)
+        val = 2 * np.pi * (-np.exp(1j * k0 * R) / (4 * np.pi * R)) * special.j0(kk * r) * r
+        return val.real if part == 0 else val.imag
+    edges = np.linspace(0, 120, 1201)
+    tot = 0j
+    for a, b in zip(edges[:-1], edges[1:]):
+        tot += integrate.quad(integrand, a, b, args=(0,), epsabs=1e-15, epsrel=1e-13)[0]
+        tot += 1j * integrate.quad(integrand, a, b, args=(1,), epsabs=1e-15, epsrel=1e-13)[0]
+    ref = model.closed_form_ghat(kx, ky, zeta, k0)
+    assert abs(tot - ref) <= 1e-8 * abs(ref)
+
+
+def test_sampled_table_converges_to_the_continuous_transform():
+    # With damping (k0 -> k0 (1 + 0.3 i)) the sampled field decays within the
+    # torus, and h^2 * DFT(sampled G) converges to the continuous 2D transform
+    # -i e^{i gamma |zeta|} / (2 gamma) as h -> 0 at fixed torus length: this
+    # pins the h^2 weight, the DFT sign and the minimum-image layout.
+    k0 = 2 * np.pi * (1 + 0.3j)
+    zeta = 0.5
+    L = 32.0
+    errs = []
+    for n in (64, 128, 256):
+        h = L / n
+        p = synth.make_problem("t", n // 2, n // 2, 2, [1.0], 1, (0, 0), h=h)
+        g = model.plane_kernel_hat(p, k0, zeta)
+        for (my, mx) in ((0, 8), (3, 5)):
+            kx = 2 * np.pi * mx / (p.px * h)
+            ky = 2 * np.pi * my / (p.py * h)
+            ref = model.closed_form_ghat(kx, ky, zeta, k0)
+            errs.append(abs(g[my, mx] - ref) / abs(ref))
+    assert errs[0] > errs[2] > errs[4] and errs[1] > errs[3] > errs[5]
+    assert max(errs[4], errs[5]) < 1e-9
+
+
+def test_noise_has_exact_relative_level_and_parseval():
+    p = synth.tiny_problem(nx=4, ny=4, nz=3, px=8, py=8)
+    W = synth.random_field((1, p.nd, p.py, p.px), (6, 0))
+    for d in (1e-3, 0.05):
+        Wd = synth.add_noise(p, W, d)
+        assert abs(np.linalg.norm(Wd - W) / np.linalg.norm(W) - d) < 1e-14
+    # sum_m ||e^_m||^2 = N ||e||^2 for the unnormalized transform
+    e = synth.noise_direction(p, 0)
+    eh = np.fft.fft2(e)
+    N = p.px * p.py
+    assert abs(np.sum(abs(eh) ** 2) - N * np.sum(abs(e) ** 2)) < 1e-12 * N
