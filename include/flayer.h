@@ -1,0 +1,200 @@
+/*
+ * flayer: flat-layer inversion of the 3D multi-frequency scalar Helmholtz
+ * coefficient problem on one AMD MI355X (gfx950).
+ *
+ * The method is Algorithm 2 of Bakushinsky & Leonov, "To the numerical
+ * solution of the inverse multi-frequency scalar acoustics problem"
+ * (Section 4, eq. 8 and 9, with the discretization of Section 5.2):
+ *
+ *   (a) 2D FFT of the scattered field W on every data plane z_j of Y;
+ *   (b) for every frequency omega and horizontal wavenumber m, the first-kind
+ *       system A_m v_m = w_m with A_m[j][l] = omega^2 h G^(z_j - z'_l, m)
+ *       solved by Tikhonov regularization, the parameter chosen per system by
+ *       the discrepancy principle (the paper leaves the regularizing
+ *       algorithm's parameter rule open; see fl_opts);
+ *   (c) inverse FFT of v^ to v on X, then u = u0 + omega^2 G * v in X as a
+ *       zero-padded 3D FFT convolution (eq. 4 / 9);
+ *   (d) xi = v / u, combined over frequencies by least squares (Section 4,
+ *       item 3; Section 5.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Geometry: X is the box [0, nx h] x [0, ny h] x [0, nz h] sampled at cell
+ *   centres ((i + 1/2) h). The data planes z_j (j < nd) lie outside
+ *   [0, nz h] and are spaced exactly h apart (z_j = z_0 + j h), so that
+ *   z_j - z'_l depends on j - l only and every A_m is Toeplitz. The
+ *   horizontal plane is a px x py torus (default 2 nx x 2 ny); X's window
+ *   sits at offset ((px - nx) / 2, (py - ny) / 2) of it.
+ * Arrays: complex values are interleaved (re, im), C order, contiguous.
+ *   W       [n_omega][nd][py][px]   data on the torus of every data plane
+ *   u0      [n_omega][nz][ny][nx]   incident field in X
+ *   xi      [nz][ny][nx]            complex128; the physical contrast
+ *                                   c0^-2 - c^-2 is its real part
+ *   Element type of W and u0: complex128 (input_dtype 0) or complex64 (1).
+ * Memory: array arguments of fl_invert / fl_forward / fl_invert_* are DEVICE
+ *   pointers owned by the caller; planes and omegas are HOST pointers read
+ *   during fl_plan_create only. The plan owns every table and workspace it
+ *   allocates and frees them in fl_plan_destroy.
+ * Execution: calls are enqueued on opts.stream (a hipStream_t; NULL = the
+ *   null stream) and return before the device work ends; outputs are valid
+ *   after the stream is synchronized. A plan is not safe for concurrent use.
+ * Errors: every call returns an fl_status; nothing throws across the ABI. On
+ *   a non-OK status the outputs are untouched unless the status is
+ *   FL_EDEVICE, and fl_last_error() (thread-local) explains.
+ */
+#ifndef FLAYER_H
+#define FLAYER_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_plan fl_plan;
+
+typedef enum {
+  FL_OK = 0,
+  FL_EINVAL = 1,       /* an argument is out of range or inconsistent */
+  FL_ENOMEM = 2,       /* a device allocation failed */
+  FL_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+  FL_ENOCONV = 4,      /* an iterative solve did not reach its tolerance */
+  FL_ENUMERIC = 5,     /* non-finite value met where a finite one is needed */
+  FL_EUNSUPPORTED = 6  /* a valid request this build does not implement */
+} fl_status;
+
+/* Options. Zero-initialize and call fl_opts_default, then override. */
+typedef struct {
+  int px, py;          /* horizontal torus; 0 => 2 nx, 2 ny; need px >= 2 nx - 1,
+                          py >= 2 ny - 1, and px, py of the form 2^a 3^b 5^c */
+  int precision;       /* 0 = FP64 throughout; 1 = mixed: FP32 FFTs and
+                          convolution, FP64 regularized solve and division */
+  double tau;          /* discrepancy factor: ||A v - w|| = tau delta_m; default 1.5 */
+  double eta;          /* alpha >= eta ||A_m||_F^2; default 1e-10; also the
+                          parameter used for noise-free data (delta = 0) */
+  int combine;         /* 0 = least squares over frequencies (default);
+                          1 = one xi per frequency: xi_out is [n_omega][nz][ny][nx] */
+  int input_dtype;     /* 0 = complex128 W and u0 (default); 1 = complex64 */
+  void *stream;        /* hipStream_t for every call on this plan */
+} fl_opts;
+
+void fl_opts_default(fl_opts *opts);
+
+/*
+ * Build a plan: validate the geometry, build the per-frequency tables
+ * (the FFT of G sampled on the torus at every height difference, Section 5:
+ * "calculated ... from the known values ... using the FFT"; and the 3D FFT of
+ * the in-X volume kernel with the self-cell integral of G over the ball of
+ * volume h^3), and allocate workspaces.
+ *   nx, ny, nz   X grid (>= 1); nd data planes (must equal nz in this build)
+ *   h            cell size (> 0); planes: nd heights (host); omegas: n_omega
+ *                angular frequencies (host, > 0); c0 > 0 background speed
+ *   opts         NULL => defaults
+ *   out          receives the plan (library-owned; free with fl_plan_destroy)
+ * Errors: FL_EINVAL (sizes, planes inside X or off the h lattice, torus too
+ * small, omega or c0 or h not positive), FL_EUNSUPPORTED (nd != nz, torus
+ * sizes with prime factors other than 2, 3, 5, or above 1024), FL_ENOMEM,
+ * FL_EDEVICE.
+ */
+fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h,
+                         const double *planes, const double *omegas, double c0,
+                         int n_omega, const fl_opts *opts, fl_plan **out);
+
+/*
+ * W -> xi (Algorithm 2). delta >= 0 is the relative data error of every
+ * frequency, ||W^delta - W|| <= delta ||W|| (Section 5.1); the per-system
+ * noise level is delta_m = delta ||W^delta_f||_2 (Parseval). Systems with
+ * ||w_m|| <= tau delta_m get v_m = 0; delta = 0 uses alpha = eta ||A_m||_F^2.
+ * W, u0, xi_out: device pointers (layouts above). Asynchronous on the plan's
+ * stream. Errors: FL_EINVAL (NULL pointers, delta < 0 or not finite),
+ * FL_EDEVICE.
+ */
+fl_status fl_invert(fl_plan *plan, const void *W, const void *u0, double delta,
+                    void *xi_out);
+
+/*
+ * Synthetic data (the role of Algorithm 1, Section 3): v = xi u in X, then
+ * W = omega^2 G * v on the data planes (eq. 7, second line) over the torus.
+ * maxit = 0 takes u = u0 (Born data); maxit > 0 is reserved for the
+ * Lippmann-Schwinger solve and returns FL_EUNSUPPORTED in this build.
+ *   xi     [nz][ny][nx] real float64, device; u0 as in fl_invert (device)
+ *   W_out  [n_omega][nd][py][px] complex128, device
+ */
+fl_status fl_forward(fl_plan *plan, const double *xi, const void *u0, double tol,
+                     int maxit, void *W_out);
+
+/* Read-only facts about a plan. */
+typedef struct {
+  int nx, ny, nz, nd, px, py, n_omega, precision;
+  size_t device_bytes;     /* tables + workspaces held by the plan */
+  int last_active;         /* systems solved by the last fl_invert (all
+                              frequencies); valid after the stream syncs and
+                              a call to fl_plan_refresh_info */
+} fl_plan_info_t;
+
+fl_status fl_plan_info(const fl_plan *plan, fl_plan_info_t *info);
+
+/* Copy the active-system count of the last fl_invert into the info block
+ * (synchronizes the plan's stream). */
+fl_status fl_plan_refresh_info(fl_plan *plan);
+
+/*
+ * Diagnostics: copy an internal array of the last fl_invert (or of the plan's
+ * tables) into a HOST buffer of `bytes` bytes; synchronizes the stream.
+ *   FL_TAP_WHAT    [n_omega][nd][py][px] complex (FFT of W, unnormalized)
+ *   FL_TAP_VHAT    [n_omega][nz][py][px] complex (regularized v^)
+ *   FL_TAP_V       [n_omega][nz][ny][nx] complex (v in X)
+ *   FL_TAP_U       [n_omega][nz][ny][nx] complex (u in X)
+ *   FL_TAP_ALPHA   [n_omega][py][px] float64 (inf where v^ = 0)
+ *   FL_TAP_BRANCH  [n_omega][py][px] int8 (0 zero, 1 floor, 2 root)
+ *   FL_TAP_GTAB    [n_omega][nd+nz-1][py][px] complex: omega^2 h^3 DFT(G
+ *                  sampled at height difference zeta_d), d = j - l + nz - 1
+ *   FL_TAP_KTAB    [n_omega][2nz][py][px] complex: omega^2 / (2 nz px py)
+ *                  times the 3D DFT of the volume kernel
+ * Complex elements are complex128 when precision = 0, complex64 otherwise
+ * for WHAT, VHAT, GTAB, KTAB (V and U are always complex128).
+ * Errors: FL_EINVAL for an unknown tap or a size mismatch.
+ */
+enum {
+  FL_TAP_WHAT = 1, FL_TAP_VHAT = 2, FL_TAP_V = 3, FL_TAP_U = 4,
+  FL_TAP_ALPHA = 5, FL_TAP_BRANCH = 6, FL_TAP_GTAB = 7, FL_TAP_KTAB = 8
+};
+fl_status fl_debug_read(fl_plan *plan, int tap, void *dst_host, size_t bytes);
+
+/*
+ * Stage timing (tracing): while enabled, every fl_invert records a HIP event
+ * on the plan's stream at the start of each stage and at its end.
+ * fl_profile_read synchronizes the stream, returns per-stage sums (ms) and
+ * launch counts over all calls since the previous read, and clears them.
+ * Stages: */
+enum {
+  FL_STAGE_NORM = 0,      /* ||W_f||^2 and the per-frequency thresholds */
+  FL_STAGE_FFT_ROWS,      /* (a) FFT of W along x */
+  FL_STAGE_FFT_COLS,      /* (a) FFT along y */
+  FL_STAGE_CLASSIFY,      /* (b) ||w_m||, zero test, compaction, v^ := 0 */
+  FL_STAGE_BIDIAG,        /* (b) Householder bidiagonalization */
+  FL_STAGE_DP,            /* (b) discrepancy root and bidiagonal Tikhonov solve */
+  FL_STAGE_BACK,          /* (b) back-transform v^ = V y */
+  FL_STAGE_IFFT_COLS,     /* (c) inverse FFT along y, rows of X's window */
+  FL_STAGE_CROP_PAD,      /* (c) inverse FFT along x, crop, pad, FFT along x */
+  FL_STAGE_CONV_COLS,     /* (c) FFT along y of the padded v */
+  FL_STAGE_CONV_Z,        /* (c) FFT along z, kernel product, inverse along z */
+  FL_STAGE_CONV_ICOLS,    /* (c) inverse FFT along y */
+  FL_STAGE_CONV_IROWS,    /* (c) inverse FFT along x, + u0 */
+  FL_STAGE_XI,            /* (d) xi */
+  FL_N_STAGES
+};
+fl_status fl_profile_enable(fl_plan *plan, int on);
+fl_status fl_profile_read(fl_plan *plan, double *ms /*[FL_N_STAGES]*/,
+                          int *launches /*[FL_N_STAGES]*/);
+
+/* Free a plan and everything it owns (NULL is a no-op). */
+void fl_plan_destroy(fl_plan *plan);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char *fl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLAYER_H */

@@ -97,8 +97,8 @@ def system_matrices(p, f: int, tab, idx, ms) -> np.ndarray:
     A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = h)."""
     om = float(p.omegas[f])
     ms = np.asarray(ms)
-    flat = tab.reshape(tab.shape[0], -1)          # (n_zeta, py*px)
-    return (om * om * p.h) * flat[idx][:, :, ms].transpose(2, 0, 1)
+    flat = tab.reshape(tab.shape[0], -1)[:, ms]   # (n_zeta, len(ms))
+    return (om * om * p.h) * flat[idx].transpose(2, 0, 1)
 
 
 def embed(p, vX: np.ndarray) -> np.ndarray:

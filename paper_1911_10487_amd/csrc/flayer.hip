@@ -1,0 +1,730 @@
+// Host side of the flat-layer inversion library: plan construction, argument
+// validation, table building and the launch sequence of Algorithm 2 on one
+// HIP stream. The C ABI is declared in include/flayer.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/flayer.h"
+#include "fft.hpp"
+#include "pointwise.hpp"
+#include "solver.hpp"
+
+using namespace fl;
+
+namespace {
+
+thread_local std::string g_err;
+
+fl_status fail(fl_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fl_status fail(fl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(e_ == hipErrorOutOfMemory ? FL_ENOMEM : FL_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+#define LAUNCHCHK()                                                                   \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(FL_EDEVICE, "kernel launch: %s (%s:%d)", hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+bool smooth235(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+struct fl_plan {
+  int nx, ny, nz, nd, px, py, F;
+  double h, c0;
+  std::vector<double> planes, omegas;
+  fl_opts opts;
+  hipStream_t st;
+  long N;
+  int nzeta, TP, ox, oy, n;
+  // tables (FP64 in this build)
+  z64 *tw_x = nullptr, *tw_y = nullptr, *tw_z = nullptr;
+  z64* gtab = nullptr;  // [F][nzeta][N]
+  z64* gsys = nullptr;  // [F][N][TP]
+  z64* ktab = nullptr;  // [F][2nz][N]
+  // workspaces
+  z64 *What = nullptr, *Vh = nullptr, *w1 = nullptr, *w2 = nullptr;
+  z64 *vX = nullptr, *u = nullptr, *u0w = nullptr, *Ww = nullptr;
+  double *wn2 = nullptr, *partial = nullptr, *thr2 = nullptr, *norm2 = nullptr;
+  int *flag = nullptr, *cnt = nullptr, *list = nullptr, *count = nullptr;
+  int nb_scan = 0;
+  // solver chunk
+  int C = 0;
+  z64 *dg = nullptr, *sp = nullptr, *q = nullptr, *refl = nullptr;
+  double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
+  double *d = nullptr, *e = nullptr, *rho = nullptr, *off = nullptr;
+  z64 *qr = nullptr, *dr = nullptr, *rr = nullptr, *y = nullptr;
+  double* alpha = nullptr;
+  signed char* branch = nullptr;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  int last_active = -1;
+  // stage tracing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, hipEvent_t>> marks;
+};
+
+namespace {
+
+template <typename P>
+fl_status dalloc(fl_plan* p, P** ptr, size_t count) {
+  size_t b = count * sizeof(P);
+  if (b == 0) b = 16;
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, b);
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? FL_ENOMEM : FL_EDEVICE, "hipMalloc(%zu): %s", b,
+                hipGetErrorString(e));
+  p->allocs.push_back(v);
+  p->bytes += b;
+  *ptr = (P*)v;
+  return FL_OK;
+}
+
+#define ALLOC(ptr, cnt)                          \
+  do {                                           \
+    fl_status s_ = dalloc(p, &(ptr), (size_t)(cnt)); \
+    if (s_ != FL_OK) return s_;                  \
+  } while (0)
+
+fl_status make_twiddles(fl_plan* p, z64** out, int L) {
+  std::vector<z64> h(L);
+  for (int i = 0; i < L; ++i) {
+    // exp(-2 pi i i / L), argument reduced by symmetry for accuracy
+    long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)i / (long double)L;
+    h[i] = mk((double)cosl(a), (double)sinl(a));
+  }
+  ALLOC(*out, L);
+  HIPCHK(hipMemcpy(*out, h.data(), L * sizeof(z64), hipMemcpyHostToDevice));
+  return FL_OK;
+}
+
+int pick_cb(int L, size_t esz) {
+  long cb = 65536 / (2L * (L + 1) * (long)esz);
+  int r = 1;
+  while (r * 2 <= cb && r < 16) r *= 2;
+  return r;
+}
+
+template <typename TI, typename T, typename TO, int DIR>
+fl_status run_fft(const FftArgs& g, hipStream_t st) {
+  int CB = pick_cb(g.L, sizeof(cx<T>));
+  size_t lds = 2 * (size_t)CB * (g.L + 1) * sizeof(cx<T>);
+  dim3 grid(nblk(g.B, CB), g.planes);
+  hipLaunchKernelGGL((k_fft<TI, T, TO, DIR>), grid, dim3(256), lds, st, g, CB);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
+#define RUN(expr)                \
+  do {                           \
+    fl_status s_ = (expr);       \
+    if (s_ != FL_OK) return s_;  \
+  } while (0)
+
+FftArgs rows_args(const void* in, void* out, const void* tw, int L, long rows) {
+  FftArgs g{};
+  g.in = in;
+  g.out = out;
+  g.tw = tw;
+  g.L = L;
+  g.lin = L;
+  g.lout = L;
+  g.in_sk = 1;
+  g.in_sb = L;
+  g.out_sk = 1;
+  g.out_sb = L;
+  g.B = (int)rows;
+  g.planes = 1;
+  g.in_kfast = 1;
+  g.out_kfast = 1;
+  g.scale = 1.0;
+  return g;
+}
+
+// columns of planes laid out [plane][L][width] (unit stride across columns)
+FftArgs cols_args(const void* in, void* out, const void* tw, int L, int width, int planes) {
+  FftArgs g{};
+  g.in = in;
+  g.out = out;
+  g.tw = tw;
+  g.L = L;
+  g.lin = L;
+  g.lout = L;
+  g.in_sk = width;
+  g.in_sb = 1;
+  g.in_sp = (long)L * width;
+  g.out_sk = width;
+  g.out_sb = 1;
+  g.out_sp = (long)L * width;
+  g.B = width;
+  g.planes = planes;
+  g.in_kfast = 0;
+  g.out_kfast = 0;
+  g.scale = 1.0;
+  return g;
+}
+
+fl_status build_tables(fl_plan* p) {
+  const long N = p->N;
+  const int F = p->F;
+  for (int f = 0; f < F; ++f) {
+    const double om = p->omegas[f];
+    const double k0 = om / p->c0;
+    // sampled omega^2 h^3 G on every height plane, then FFT2 -> A's entries
+    const double zeta0 = p->planes[0] - 0.5 * p->h - (p->nz - 1) * p->h;
+    z64* gt = p->gtab + (long)f * p->nzeta * N;
+    hipLaunchKernelGGL((k_gplanes<double>), dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt,
+                       p->nzeta, p->px, p->py, p->h, zeta0, k0, om * om * p->h * p->h * p->h);
+    LAUNCHCHK();
+    RUN((run_fft<double, double, double, -1>(rows_args(gt, gt, p->tw_x, p->px, (long)p->nzeta * p->py),
+                                             p->st)));
+    RUN((run_fft<double, double, double, -1>(cols_args(gt, gt, p->tw_y, p->py, p->px, p->nzeta),
+                                             p->st)));
+    // volume kernel on (2nz, py, px), scaled by omega^2 / (2 nz px py): the
+    // inverse transforms of the convolution are unnormalized
+    const int nz2 = 2 * p->nz;
+    z64* kt = p->ktab + (long)f * nz2 * N;
+    hipLaunchKernelGGL((k_kappa<double>), dim3(nblk(N * nz2, 256)), dim3(256), 0, p->st, kt, nz2,
+                       p->px, p->py, p->h, k0, om * om / ((double)nz2 * (double)N));
+    LAUNCHCHK();
+    RUN((run_fft<double, double, double, -1>(rows_args(kt, kt, p->tw_x, p->px, (long)nz2 * p->py),
+                                             p->st)));
+    RUN((run_fft<double, double, double, -1>(cols_args(kt, kt, p->tw_y, p->py, p->px, nz2), p->st)));
+    {
+      FftArgs g{};
+      g.in = kt;
+      g.out = kt;
+      g.tw = p->tw_z;
+      g.L = nz2;
+      g.lin = nz2;
+      g.lout = nz2;
+      g.in_sk = N;
+      g.in_sb = 1;
+      g.out_sk = N;
+      g.out_sb = 1;
+      g.B = (int)N;
+      g.planes = 1;
+      g.scale = 1.0;
+      RUN((run_fft<double, double, double, -1>(g, p->st)));
+    }
+  }
+  hipLaunchKernelGGL((k_to_sys<double>), dim3(nblk(N * p->nzeta, 256), F), dim3(256), 0, p->st,
+                     p->gtab, p->gsys, p->nzeta, N, p->TP);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(p->st));
+  return FL_OK;
+}
+
+// Record the start of stage `s` (s < 0: end of the call) when tracing.
+fl_status mark(fl_plan* p, int s) {
+  if (!p->prof) return FL_OK;
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    p->ev_pool.push_back(e);
+  }
+  hipEvent_t e = p->ev_pool[p->ev_used++];
+  HIPCHK(hipEventRecord(e, p->st));
+  p->marks.emplace_back(s, e);
+  return FL_OK;
+}
+
+fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
+  const int n = p->n;
+  const z64* What = p->What;
+#define BD(TR, TC, NA, NB)                                                                   \
+  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB>), dim3(grid), dim3(TR * TC), 0, p->st, p->gsys, \
+                     p->TP, What, p->N, p->list, p->count, chunk0, p->C, o)
+  switch (n) {
+    case 16: BD(16, 4, 1, 4); break;
+    case 32: BD(16, 8, 2, 4); break;
+    case 48: BD(16, 16, 3, 3); break;
+    case 64: BD(16, 16, 4, 4); break;
+    case 80: BD(16, 16, 5, 5); break;
+    case 96: BD(16, 16, 6, 6); break;
+    case 128: BD(32, 16, 4, 8); break;
+    default: return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
+  }
+#undef BD
+  LAUNCHCHK();
+  return FL_OK;
+}
+
+fl_status solve_systems(fl_plan* p, double delta) {
+  const long FN = (long)p->F * p->N;
+  const int n = p->n;
+  hipStream_t st = p->st;
+  RUN(mark(p, FL_STAGE_CLASSIFY));
+  hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, p->What, p->nd, p->N,
+                     p->F, p->thr2, p->wn2, p->flag);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->count);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt, p->list);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(FN * p->nz, 256)), dim3(256), 0, st, p->Vh,
+                     FN * p->nz);
+  LAUNCHCHK();
+  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam};
+  DpArgs a{};
+  a.dg = p->dg;
+  a.sp = p->sp;
+  a.q = p->q;
+  a.fro = p->fro;
+  a.wn2 = p->wnc;
+  a.list = p->list;
+  a.count = p->count;
+  a.C = p->C;
+  a.n = n;
+  a.N = p->N;
+  a.thr2 = p->thr2;
+  a.eta = p->opts.eta;
+  a.d = p->d;
+  a.e = p->e;
+  a.qr = p->qr;
+  a.dr = p->dr;
+  a.rho = p->rho;
+  a.off = p->off;
+  a.rr = p->rr;
+  a.y = p->y;
+  a.alpha = p->alpha;
+  a.branch = p->branch;
+  const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
+  for (long c0 = 0; c0 < FN; c0 += p->C) {
+    RUN(mark(p, FL_STAGE_BIDIAG));
+    RUN(launch_bidiag(p, (int)c0, gb, o));
+    a.chunk0 = (int)c0;
+    RUN(mark(p, FL_STAGE_DP));
+    hipLaunchKernelGGL(k_dp, dim3(nblk(p->C, 64)), dim3(64), 0, st, a);
+    LAUNCHCHK();
+    RUN(mark(p, FL_STAGE_BACK));
+    hipLaunchKernelGGL(k_backtransform<double>, dim3(nblk(p->C, 4)), dim3(256), 0, st, p->y, p->refl,
+                       p->gam, p->list, p->count, (int)c0, p->C, n, p->N, p->Vh);
+    LAUNCHCHK();
+  }
+  return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fl_opts_default(fl_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->tau = 1.5;
+  o->eta = 1e-10;
+}
+
+const char* fl_last_error(void) { return g_err.c_str(); }
+
+fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double* planes,
+                         const double* omegas, double c0, int n_omega, const fl_opts* opts,
+                         fl_plan** out) {
+  g_err.clear();
+  if (!out) return fail(FL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1 || nd < 1 || n_omega < 1)
+    return fail(FL_EINVAL, "sizes must be >= 1 (nx=%d ny=%d nz=%d nd=%d n_omega=%d)", nx, ny, nz, nd,
+                n_omega);
+  if (!(h > 0) || !std::isfinite(h)) return fail(FL_EINVAL, "h must be positive and finite");
+  if (!(c0 > 0) || !std::isfinite(c0)) return fail(FL_EINVAL, "c0 must be positive and finite");
+  if (!planes || !omegas) return fail(FL_EINVAL, "planes and omegas must be host arrays");
+  for (int f = 0; f < n_omega; ++f)
+    if (!(omegas[f] > 0) || !std::isfinite(omegas[f]))
+      return fail(FL_EINVAL, "omegas[%d] = %g must be positive and finite", f, omegas[f]);
+  fl_opts o;
+  fl_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tau > 0)) o.tau = 1.5;
+  if (!(o.eta > 0)) o.eta = 1e-10;
+  const int px = o.px > 0 ? o.px : 2 * nx;
+  const int py = o.py > 0 ? o.py : 2 * ny;
+  if (px < 2 * nx - 1 || py < 2 * ny - 1)
+    return fail(FL_EINVAL, "torus %dx%d too small for window %dx%d (need >= 2n-1)", px, py, nx, ny);
+  const double top = nz * h;
+  for (int j = 0; j < nd; ++j) {
+    if (!std::isfinite(planes[j])) return fail(FL_EINVAL, "planes[%d] not finite", j);
+    if (planes[j] >= 0.0 && planes[j] <= top)
+      return fail(FL_EINVAL, "data plane %d at z=%g lies inside X = [0, %g]", j, planes[j], top);
+    if (std::fabs(planes[j] - (planes[0] + j * h)) > 1e-9 * h)
+      return fail(FL_EINVAL, "data planes must be spaced h apart (plane %d)", j);
+  }
+  if (planes[0] < 0.0 && planes[nd - 1] > 0.0)
+    return fail(FL_EINVAL, "data planes straddle X");
+  if (nd != nz) return fail(FL_EUNSUPPORTED, "nd (%d) != nz (%d) is not supported", nd, nz);
+  if (!smooth235(px) || !smooth235(py) || !smooth235(2 * nz) || px > 1024 || py > 1024 ||
+      2 * nz > 1024)
+    return fail(FL_EUNSUPPORTED, "FFT sizes %d, %d, %d need factors 2, 3, 5 only and <= 1024", px,
+                py, 2 * nz);
+  if (!(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
+    return fail(FL_EUNSUPPORTED, "nz = %d: this build solves nz in {16,32,48,64,80,96,128}", nz);
+  if (o.precision != 0) return fail(FL_EUNSUPPORTED, "only precision 0 (FP64) in this build");
+  if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
+  if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
+
+  fl_plan* p = new fl_plan();
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->nd = nd;
+  p->px = px;
+  p->py = py;
+  p->F = n_omega;
+  p->h = h;
+  p->c0 = c0;
+  p->planes.assign(planes, planes + nd);
+  p->omegas.assign(omegas, omegas + n_omega);
+  p->opts = o;
+  p->opts.px = px;
+  p->opts.py = py;
+  p->st = (hipStream_t)o.stream;
+  p->N = (long)px * py;
+  p->nzeta = nd + nz - 1;
+  p->TP = 2 * nz;
+  p->ox = (px - nx) / 2;
+  p->oy = (py - ny) / 2;
+  p->n = nz;
+  auto bail = [&](fl_status s) {
+    fl_plan_destroy(p);
+    return s;
+  };
+#define PALLOC(ptr, cnt)                              \
+  do {                                                \
+    fl_status s_ = dalloc(p, &(ptr), (size_t)(cnt));  \
+    if (s_ != FL_OK) return bail(s_);                 \
+  } while (0)
+  const long N = p->N, F = p->F;
+  const long FN = F * N;
+  {
+    fl_status s;
+    if ((s = make_twiddles(p, &p->tw_x, px)) != FL_OK) return bail(s);
+    if ((s = make_twiddles(p, &p->tw_y, py)) != FL_OK) return bail(s);
+    if ((s = make_twiddles(p, &p->tw_z, 2 * nz)) != FL_OK) return bail(s);
+  }
+  PALLOC(p->gtab, F * p->nzeta * N);
+  PALLOC(p->gsys, FN * p->TP);
+  PALLOC(p->ktab, F * 2 * nz * N);
+  const long big = F * std::max(nd, nz) * N;
+  PALLOC(p->What, F * nd * N);
+  PALLOC(p->Vh, F * nz * N);
+  PALLOC(p->w1, big);
+  PALLOC(p->w2, big);
+  const long nvox = (long)nx * ny * nz;
+  PALLOC(p->vX, F * nvox);
+  PALLOC(p->u, F * nvox);
+  PALLOC(p->u0w, F * nvox);
+  PALLOC(p->Ww, F * nd * N);
+  PALLOC(p->wn2, FN);
+  PALLOC(p->flag, FN);
+  p->nb_scan = (int)nblk(FN, 1024);
+  PALLOC(p->cnt, p->nb_scan);
+  PALLOC(p->list, FN);
+  PALLOC(p->count, 1);
+  PALLOC(p->partial, F * 256);
+  PALLOC(p->thr2, F);
+  PALLOC(p->norm2, F);
+  const long cap = nz <= 64 ? 32768 : 16384;
+  p->C = (int)std::min<long>(FN, cap);
+  const long C = p->C;
+  PALLOC(p->dg, C * nz);
+  PALLOC(p->sp, C * nz);
+  PALLOC(p->q, C * nz);
+  PALLOC(p->fro, C);
+  PALLOC(p->wnc, C);
+  PALLOC(p->refl, C * nz * nz);
+  PALLOC(p->gam, C * nz);
+  PALLOC(p->d, C * nz);
+  PALLOC(p->e, C * nz);
+  PALLOC(p->qr, C * nz);
+  PALLOC(p->dr, C * nz);
+  PALLOC(p->rho, C * nz);
+  PALLOC(p->off, C * nz);
+  PALLOC(p->rr, C * nz);
+  PALLOC(p->y, C * nz);
+  PALLOC(p->alpha, FN);
+  PALLOC(p->branch, FN);
+#undef PALLOC
+  fl_status s = build_tables(p);
+  if (s != FL_OK) return bail(s);
+  *out = p;
+  return FL_OK;
+}
+
+fl_status fl_profile_enable(fl_plan* p, int on) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  p->prof = on != 0;
+  return FL_OK;
+}
+
+fl_status fl_profile_read(fl_plan* p, double* ms, int* launches) {
+  if (!p || !ms || !launches) return fail(FL_EINVAL, "NULL argument");
+  HIPCHK(hipStreamSynchronize(p->st));
+  for (int i = 0; i < FL_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (size_t i = 0; i + 1 < p->marks.size(); ++i) {
+    int s = p->marks[i].first;
+    if (s < 0) continue;
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, p->marks[i].second, p->marks[i + 1].second));
+    ms[s] += t;
+    launches[s] += 1;
+  }
+  p->marks.clear();
+  p->ev_used = 0;
+  return FL_OK;
+}
+
+void fl_plan_destroy(fl_plan* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->st);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  for (void* v : p->allocs) (void)hipFree(v);
+  delete p;
+}
+
+fl_status fl_plan_info(const fl_plan* p, fl_plan_info_t* info) {
+  if (!p || !info) return fail(FL_EINVAL, "NULL argument");
+  info->nx = p->nx;
+  info->ny = p->ny;
+  info->nz = p->nz;
+  info->nd = p->nd;
+  info->px = p->px;
+  info->py = p->py;
+  info->n_omega = p->F;
+  info->precision = p->opts.precision;
+  info->device_bytes = p->bytes;
+  info->last_active = p->last_active;
+  return FL_OK;
+}
+
+fl_status fl_plan_refresh_info(fl_plan* p) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  int c = 0;
+  HIPCHK(hipMemcpyAsync(&c, p->count, sizeof(int), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  p->last_active = c;
+  return FL_OK;
+}
+
+fl_status fl_invert(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!W || !u0 || !xi_out) return fail(FL_EINVAL, "NULL array argument");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  hipStream_t st = p->st;
+  const long N = p->N;
+  const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  const long nvox = (long)nx * ny * nz;
+  RUN(mark(p, FL_STAGE_NORM));
+  // noise thresholds: thr2[f] = (tau delta ||W_f||)^2
+  {
+    dim3 g(256, F);
+    if (p->opts.input_dtype == 0)
+      hipLaunchKernelGGL(k_sumsq<double>, g, dim3(256), 0, st, (const z64*)W, (long)nd * N, p->partial);
+    else
+      hipLaunchKernelGGL(k_sumsq<float>, g, dim3(256), 0, st, (const z32*)W, (long)nd * N, p->partial);
+    LAUNCHCHK();
+    double td = p->opts.tau * delta;
+    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
+                       p->norm2);
+    LAUNCHCHK();
+  }
+  const z64* u0d = (const z64*)u0;
+  if (p->opts.input_dtype == 1) {
+    hipLaunchKernelGGL(k_widen<float>, dim3(nblk(F * nvox, 256)), dim3(256), 0, st, (const z32*)u0,
+                       p->u0w, (long)F * nvox);
+    LAUNCHCHK();
+    u0d = p->u0w;
+  }
+  // (a) FFT2 of W: rows, then columns -> W^ plane-major [F][nd][py][px]
+  {
+    RUN(mark(p, FL_STAGE_FFT_ROWS));
+    FftArgs g = rows_args(W, p->w1, p->tw_x, px, (long)F * nd * py);
+    if (p->opts.input_dtype == 0)
+      RUN((run_fft<double, double, double, -1>(g, st)));
+    else
+      RUN((run_fft<float, double, double, -1>(g, st)));
+    RUN(mark(p, FL_STAGE_FFT_COLS));
+    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
+  }
+  // (b) regularized solves of the active systems -> v^ plane-major
+  RUN(solve_systems(p, delta));
+  // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
+  {
+    RUN(mark(p, FL_STAGE_IFFT_COLS));
+    FftArgs g = cols_args(p->Vh, p->w1, p->tw_y, py, px, F * nz);
+    g.lout = ny;
+    g.out_off = p->oy;
+    g.out_sp = (long)ny * px;
+    RUN((run_fft<double, double, double, 1>(g, st)));
+    int CB = pick_cb(px, sizeof(z64));
+    long rows = (long)F * nz * ny;
+    size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(z64);
+    RUN(mark(p, FL_STAGE_CROP_PAD));
+    hipLaunchKernelGGL(k_rows_crop_pad<double>, dim3(nblk(rows, CB)), dim3(256), lds, st, p->w1, p->vX,
+                       p->w2, p->tw_x, px, nx, p->ox, (int)rows, 1.0 / (double)N, CB);
+    LAUNCHCHK();
+    FftArgs c = cols_args(p->w2, p->w1, p->tw_y, py, px, F * nz);
+    c.lin = ny;
+    c.in_sp = (long)ny * px;
+    RUN(mark(p, FL_STAGE_CONV_COLS));
+    RUN((run_fft<double, double, double, -1>(c, st)));
+    FftArgs z{};
+    z.in = p->w1;
+    z.out = p->w1;
+    z.tw = p->tw_z;
+    z.L = 2 * nz;
+    z.lin = nz;
+    z.lout = nz;
+    z.in_sk = N;
+    z.in_sb = 1;
+    z.in_sp = (long)nz * N;
+    z.out_sk = N;
+    z.out_sb = 1;
+    z.out_sp = (long)nz * N;
+    z.B = (int)N;
+    z.planes = F;
+    z.scale = 1.0;
+    int CBz = pick_cb(2 * nz, sizeof(z64));
+    size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(z64);
+    RUN(mark(p, FL_STAGE_CONV_Z));
+    hipLaunchKernelGGL(k_fft_conv<double>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, p->ktab,
+                       (long)N, (long)2 * nz * N, CBz);
+    LAUNCHCHK();
+    FftArgs b = cols_args(p->w1, p->w2, p->tw_y, py, px, F * nz);
+    b.lout = ny;
+    b.out_sp = (long)ny * px;
+    RUN(mark(p, FL_STAGE_CONV_ICOLS));
+    RUN((run_fft<double, double, double, 1>(b, st)));
+    FftArgs r = rows_args(p->w2, p->u, p->tw_x, px, rows);
+    r.lout = nx;
+    r.out_sb = nx;
+    r.add = u0d;
+    RUN(mark(p, FL_STAGE_CONV_IROWS));
+    RUN((run_fft<double, double, double, 1>(r, st)));
+  }
+  // (d) xi
+  RUN(mark(p, FL_STAGE_XI));
+  hipLaunchKernelGGL(k_xi, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->u, p->vX, nvox, F,
+                     p->opts.combine, (z64*)xi_out);
+  LAUNCHCHK();
+  RUN(mark(p, -1));
+  return FL_OK;
+}
+
+fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, int maxit,
+                     void* W_out) {
+  (void)tol;
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!xi || !u0 || !W_out) return fail(FL_EINVAL, "NULL array argument");
+  if (maxit < 0) return fail(FL_EINVAL, "maxit must be >= 0");
+  if (maxit > 0) return fail(FL_EUNSUPPORTED, "the Lippmann-Schwinger solve is not in this build");
+  hipStream_t st = p->st;
+  const long N = p->N;
+  const int F = p->F, nd = p->nd, nz = p->nz, px = p->px, py = p->py;
+  const long nvox = (long)p->nx * p->ny * nz;
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk((long)F * nz * N, 256)), dim3(256), 0, st, p->w1,
+                     (long)F * nz * N);
+  LAUNCHCHK();
+  if (p->opts.input_dtype == 0)
+    hipLaunchKernelGGL((k_current<double, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
+                       (const z64*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, p->w1);
+  else
+    hipLaunchKernelGGL((k_current<float, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
+                       (const z32*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, p->w1);
+  LAUNCHCHK();
+  RUN((run_fft<double, double, double, -1>(rows_args(p->w1, p->w1, p->tw_x, px, (long)F * nz * py), st)));
+  RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->w1, p->tw_y, py, px, F * nz), st)));
+  hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
+                     p->w1, nd, nz, N, F, p->w2);
+  LAUNCHCHK();
+  FftArgs c = cols_args(p->w2, p->w2, p->tw_y, py, px, F * nd);
+  RUN((run_fft<double, double, double, 1>(c, st)));
+  FftArgs r = rows_args(p->w2, W_out, p->tw_x, px, (long)F * nd * py);
+  r.scale = 1.0 / (double)N;
+  RUN((run_fft<double, double, double, 1>(r, st)));
+  return FL_OK;
+}
+
+fl_status fl_debug_read(fl_plan* p, int tap, void* dst, size_t bytes) {
+  if (!p || !dst) return fail(FL_EINVAL, "NULL argument");
+  const long N = p->N, F = p->F;
+  const long nvox = (long)p->nx * p->ny * p->nz;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (tap) {
+    case FL_TAP_WHAT: src = p->What; need = F * p->nd * N * sizeof(z64); break;
+    case FL_TAP_VHAT: src = p->Vh; need = F * p->nz * N * sizeof(z64); break;
+    case FL_TAP_V: src = p->vX; need = F * nvox * sizeof(z64); break;
+    case FL_TAP_U: src = p->u; need = F * nvox * sizeof(z64); break;
+    case FL_TAP_ALPHA: src = p->alpha; need = F * N * sizeof(double); break;
+    case FL_TAP_BRANCH: src = p->branch; need = F * N; break;
+    case FL_TAP_GTAB: src = p->gtab; need = F * p->nzeta * N * sizeof(z64); break;
+    case FL_TAP_KTAB: src = p->ktab; need = F * 2 * p->nz * N * sizeof(z64); break;
+    default: return fail(FL_EINVAL, "unknown tap %d", tap);
+  }
+  if (bytes != need) return fail(FL_EINVAL, "tap %d needs %zu bytes, got %zu", tap, need, bytes);
+  HIPCHK(hipStreamSynchronize(p->st));
+  if (tap == FL_TAP_ALPHA || tap == FL_TAP_BRANCH) {
+    // entries of systems that were not solved keep their zero-branch values
+    int c = 0;
+    HIPCHK(hipMemcpy(&c, p->count, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<int> flag(F * N);
+    HIPCHK(hipMemcpy(flag.data(), p->flag, F * N * sizeof(int), hipMemcpyDeviceToHost));
+    if (tap == FL_TAP_ALPHA) {
+      std::vector<double> a(F * N);
+      HIPCHK(hipMemcpy(a.data(), p->alpha, need, hipMemcpyDeviceToHost));
+      for (long i = 0; i < F * N; ++i)
+        if (!flag[i]) a[i] = INFINITY;
+      std::memcpy(dst, a.data(), need);
+    } else {
+      std::vector<signed char> b(F * N);
+      HIPCHK(hipMemcpy(b.data(), p->branch, need, hipMemcpyDeviceToHost));
+      for (long i = 0; i < F * N; ++i)
+        if (!flag[i]) b[i] = 0;
+      std::memcpy(dst, b.data(), need);
+    }
+    return FL_OK;
+  }
+  HIPCHK(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+  return FL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Table builders and pointwise kernels of the inversion path.
+#pragma once
+#include "common.hpp"
+
+namespace fl {
+
+__device__ __forceinline__ int min_image(int p, int P) { return p <= P / 2 ? p : p - P; }
+
+// omega^2 h^3 G(r) on the torus for every height difference zeta_d:
+// out[d][py][px], G(r) = -exp(i k0 r) / (4 pi r) (Section 1), r the distance
+// with minimum-image horizontal offsets. zeta_d = zeta0 + d h.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nzeta, int px, int py,
+                                                 double h, double zeta0, double k0, double wgt) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long N = (long)px * py;
+  if (idx >= N * nzeta) return;
+  int d = (int)(idx / N);
+  long p = idx - (long)d * N;
+  int iy = (int)(p / px), ix = (int)(p - (long)iy * px);
+  double dx = h * min_image(ix, px), dy = h * min_image(iy, py);
+  double z = zeta0 + d * h;
+  double r = sqrt(dx * dx + dy * dy + z * z);
+  double s, c;
+  sincos(k0 * r, &s, &c);
+  double a = -wgt / (4.0 * M_PI * r);
+  out[idx] = mk((T)(a * c), (T)(a * s));
+}
+
+// Volume kernel on the (2nz) x py x px torus with minimum-image offsets:
+// h^3 G(h |d|) for d != 0 and the integral of G over the ball of volume h^3 at
+// d = 0, all times wgt.
+template <typename T>
+__global__ __launch_bounds__(256) void k_kappa(cx<T>* __restrict__ out, int nz2, int px, int py,
+                                               double h, double k0, double wgt) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long N = (long)px * py;
+  if (idx >= N * nz2) return;
+  int kz = (int)(idx / N);
+  long p = idx - (long)kz * N;
+  int iy = (int)(p / px), ix = (int)(p - (long)iy * px);
+  double dz = min_image(kz, nz2), dy = min_image(iy, py), dx = min_image(ix, px);
+  double re, im;
+  if (kz == 0 && iy == 0 && ix == 0) {
+    // (1 - (1 - i k0 a) e^{i k0 a}) / k0^2, a = h (3 / (4 pi))^(1/3)
+    double a = h * cbrt(3.0 / (4.0 * M_PI));
+    double s, c;
+    sincos(k0 * a, &s, &c);
+    double ka = k0 * a;
+    // (1 - i ka)(c + i s) = c + ka s + i (s - ka c)
+    re = (1.0 - (c + ka * s)) / (k0 * k0);
+    im = -(s - ka * c) / (k0 * k0);
+  } else {
+    double r = h * sqrt(dx * dx + dy * dy + dz * dz);
+    double s, c;
+    sincos(k0 * r, &s, &c);
+    double a = -h * h * h / (4.0 * M_PI * r);
+    re = a * c;
+    im = a * s;
+  }
+  out[idx] = mk((T)(wgt * re), (T)(wgt * im));
+}
+
+// plane-major [F][nzeta][N] -> system-major [F][N][pitch]
+template <typename T>
+__global__ __launch_bounds__(256) void k_to_sys(const cx<T>* __restrict__ in, z64* __restrict__ out,
+                                                int nzeta, long N, int pitch) {
+  long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  int f = blockIdx.y;
+  if (idx >= N * nzeta) return;
+  int d = (int)(idx / N);
+  long m = idx - (long)d * N;
+  cx<T> v = in[((long)f * nzeta + d) * N + m];
+  out[((long)f * N + m) * pitch + d] = cast<double>(v);
+}
+
+// per-frequency partial sums of |W|^2: grid (nb, F), partial[f * nb + b]
+template <typename TI>
+__global__ __launch_bounds__(256) void k_sumsq(const cx<TI>* __restrict__ W, long per_f,
+                                               double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int f = blockIdx.y, nb = gridDim.x;
+  const cx<TI>* w = W + (long)f * per_f;
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per_f; i += (long)nb * blockDim.x) {
+    cx<TI> v = w[i];
+    s = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, s));
+  }
+  s = group_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[f * nb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// thr2[f] = (tau delta)^2 ||W_f||^2, or -1 for noise-free data
+__global__ void k_thresholds(const double* __restrict__ partial, int nb, int F, double td2,
+                             double* __restrict__ thr2, double* __restrict__ norm2) {
+  for (int f = threadIdx.x; f < F; f += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[f * nb + b];
+    norm2[f] = s;
+    thr2[f] = td2 > 0.0 ? td2 * s : -1.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(cx<T>* __restrict__ p, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = mk((T)0, (T)0);
+}
+
+template <typename TI>
+__global__ __launch_bounds__(256) void k_widen(const cx<TI>* __restrict__ in, z64* __restrict__ out,
+                                               long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cast<double>(in[i]);
+}
+
+// item 3: xi = sum_f conj(u_f) v_f / sum_f |u_f|^2 (0 where the denominator
+// vanishes); per_f != 0 writes one quotient per frequency instead.
+__global__ __launch_bounds__(256) void k_xi(const z64* __restrict__ u, const z64* __restrict__ v,
+                                            long nvox, int F, int per_f, z64* __restrict__ xi) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox) return;
+  if (per_f) {
+    for (int f = 0; f < F; ++f) {
+      z64 uu = u[(long)f * nvox + i], vv = v[(long)f * nvox + i];
+      double dn = nrm2(uu);
+      z64 nm = cmulc(uu, vv);
+      xi[(long)f * nvox + i] = dn > 0.0 ? mk(nm.x / dn, nm.y / dn) : mk(0.0, 0.0);
+    }
+    return;
+  }
+  z64 num = mk(0.0, 0.0);
+  double den = 0.0;
+  for (int f = 0; f < F; ++f) {
+    z64 uu = u[(long)f * nvox + i], vv = v[(long)f * nvox + i];
+    num = cfmac(num, uu, vv);
+    den += nrm2(uu);
+  }
+  xi[i] = den > 0.0 ? mk(num.x / den, num.y / den) : mk(0.0, 0.0);
+}
+
+// v = xi * u on X (real xi), written into the torus-embedded array
+// out[f][l][py][px] (zeros outside the window must be set beforehand).
+template <typename TI, typename T>
+__global__ __launch_bounds__(256) void k_current(const double* __restrict__ xi,
+                                                 const cx<TI>* __restrict__ u, int nx, int ny,
+                                                 int nz, int F, int px, int py, int ox, int oy,
+                                                 cx<T>* __restrict__ out) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long nvox = (long)nx * ny * nz;
+  if (i >= nvox * F) return;
+  int f = (int)(i / nvox);
+  long v = i - (long)f * nvox;
+  int l = (int)(v / ((long)nx * ny));
+  long r = v - (long)l * nx * ny;
+  int iy = (int)(r / nx), ix = (int)(r - (long)iy * nx);
+  cx<TI> uu = u[i];
+  double x = xi[v];
+  out[(((long)f * nz + l) * py + iy + oy) * px + ix + ox] = mk((T)(x * uu.x), (T)(x * uu.y));
+}
+
+// W^[f][j][m] = sum_l gtab[f][j - l + nz - 1][m] V^[f][l][m] (every m)
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_systems(const cx<T>* __restrict__ gtab,
+                                                       const cx<T>* __restrict__ Vh, int nd, int nz,
+                                                       long N, int F, cx<T>* __restrict__ Wh) {
+  long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (fm >= (long)F * N) return;
+  int f = (int)(fm / N);
+  long m = fm - (long)f * N;
+  const int nzeta = nd + nz - 1;
+  const cx<T>* g = gtab + (long)f * nzeta * N + m;
+  const cx<T>* v = Vh + (long)f * nz * N + m;
+  for (int j = 0; j < nd; ++j) {
+    z64 acc = mk(0.0, 0.0);
+    for (int l = 0; l < nz; ++l)
+      acc = cfma(acc, cast<double>(g[(long)(j - l + nz - 1) * N]), cast<double>(v[(long)l * N]));
+    Wh[((long)f * nd + j) * N + m] = cast<T>(acc);
+  }
+}
+
+}  // namespace fl

@@ -1,0 +1,199 @@
+"""Python binding of the flayer C ABI (include/flayer.h).
+
+Argument marshalling only: device arrays are PyTorch tensors on the GPU
+(torch is used for device memory and the current HIP stream); every step of
+the inversion runs in the library's HIP kernels. There is no CPU fallback:
+if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libflayer.so")
+
+FL_OK, FL_EINVAL, FL_ENOMEM, FL_EDEVICE, FL_ENOCONV, FL_ENUMERIC, FL_EUNSUPPORTED = range(7)
+STATUS_NAMES = {0: "FL_OK", 1: "FL_EINVAL", 2: "FL_ENOMEM", 3: "FL_EDEVICE", 4: "FL_ENOCONV",
+                5: "FL_ENUMERIC", 6: "FL_EUNSUPPORTED"}
+TAP_WHAT, TAP_VHAT, TAP_V, TAP_U, TAP_ALPHA, TAP_BRANCH, TAP_GTAB, TAP_KTAB = range(1, 9)
+STAGES = ["norm", "fft_rows", "fft_cols", "classify", "bidiag", "dp", "backtransform",
+          "ifft_cols", "crop_pad", "conv_cols", "conv_z", "conv_icols", "conv_irows", "xi"]
+
+
+class FlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class FlOpts(ctypes.Structure):
+    _fields_ = [
+        ("px", ctypes.c_int), ("py", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("tau", ctypes.c_double), ("eta", ctypes.c_double),
+        ("combine", ctypes.c_int), ("input_dtype", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class FlPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("nd", ctypes.c_int),
+        ("px", ctypes.c_int), ("py", ctypes.c_int), ("n_omega", ctypes.c_int),
+        ("precision", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
+        ("last_active", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(
+            f"{LIB_PATH} is missing: build it with python -m paper_1911_10487_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    L.fl_opts_default.argtypes = [ctypes.POINTER(FlOpts)]
+    L.fl_opts_default.restype = None
+    L.fl_last_error.argtypes = []
+    L.fl_last_error.restype = ctypes.c_char_p
+    L.fl_plan_create.argtypes = [I, I, I, I, D, ctypes.POINTER(D), ctypes.POINTER(D), D, I,
+                                 ctypes.POINTER(FlOpts), ctypes.POINTER(P)]
+    L.fl_plan_create.restype = I
+    L.fl_invert.argtypes = [P, P, P, D, P]
+    L.fl_invert.restype = I
+    L.fl_forward.argtypes = [P, P, P, D, I, P]
+    L.fl_forward.restype = I
+    L.fl_plan_info.argtypes = [P, ctypes.POINTER(FlPlanInfo)]
+    L.fl_plan_info.restype = I
+    L.fl_plan_refresh_info.argtypes = [P]
+    L.fl_plan_refresh_info.restype = I
+    L.fl_debug_read.argtypes = [P, I, P, ctypes.c_size_t]
+    L.fl_debug_read.restype = I
+    L.fl_profile_enable.argtypes = [P, I]
+    L.fl_profile_enable.restype = I
+    L.fl_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I)]
+    L.fl_profile_read.restype = I
+    L.fl_plan_destroy.argtypes = [P]
+    L.fl_plan_destroy.restype = None
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != FL_OK:
+        raise FlError(status, lib().fl_last_error().decode())
+
+
+def default_opts() -> FlOpts:
+    o = FlOpts()
+    lib().fl_opts_default(ctypes.byref(o))
+    return o
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A flayer plan for one geometry and frequency set (owns device tables)."""
+
+    def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
+                 tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None):
+        o = default_opts()
+        o.px, o.py, o.precision = px, py, precision
+        o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
+        o.stream = stream if stream is not None else _stream_handle()
+        planes = np.ascontiguousarray(planes, np.float64)
+        omegas = np.ascontiguousarray(omegas, np.float64)
+        h_ = ctypes.c_void_p()
+        _check(lib().fl_plan_create(
+            nx, ny, nz, nd, h,
+            planes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            omegas.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            c0, len(omegas), ctypes.byref(o), ctypes.byref(h_)))
+        self._h = h_
+        self.nx, self.ny, self.nz, self.nd = nx, ny, nz, nd
+        self.n_omega = len(omegas)
+        self.combine = combine
+        info = self.info()
+        self.px, self.py = info.px, info.py
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        return cls(p.nx, p.ny, p.nz, p.nd, p.h, p.planes, p.omegas, p.c0, p.px, p.py, **kw)
+
+    def info(self) -> FlPlanInfo:
+        i = FlPlanInfo()
+        _check(lib().fl_plan_info(self._h, ctypes.byref(i)))
+        return i
+
+    def active_systems(self) -> int:
+        _check(lib().fl_plan_refresh_info(self._h))
+        return self.info().last_active
+
+    def invert(self, W, u0, delta, xi_out=None):
+        """W (n_omega, nd, py, px) and u0 (n_omega, nz, ny, nx): complex
+        tensors on the GPU. Returns xi (nz, ny, nx) complex128 on the GPU."""
+        import torch
+        if xi_out is None:
+            shape = (self.nz, self.ny, self.nx)
+            if self.combine == 1:
+                shape = (self.n_omega,) + shape
+            xi_out = torch.empty(shape, dtype=torch.complex128, device=W.device)
+        for t in (W, u0, xi_out):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("arrays must be contiguous GPU tensors")
+        _check(lib().fl_invert(self._h, ctypes.c_void_p(W.data_ptr()),
+                               ctypes.c_void_p(u0.data_ptr()), float(delta),
+                               ctypes.c_void_p(xi_out.data_ptr())))
+        return xi_out
+
+    def forward(self, xi, u0, W_out=None):
+        """Born data: W = omega^2 G * (xi u0) on the data planes' torus."""
+        import torch
+        if W_out is None:
+            W_out = torch.empty((self.n_omega, self.nd, self.py, self.px), dtype=torch.complex128,
+                                device=u0.device)
+        _check(lib().fl_forward(self._h, ctypes.c_void_p(xi.data_ptr()),
+                                ctypes.c_void_p(u0.data_ptr()), 0.0, 0,
+                                ctypes.c_void_p(W_out.data_ptr())))
+        return W_out
+
+    def tap(self, which, dtype, shape):
+        out = np.empty(shape, dtype)
+        _check(lib().fl_debug_read(self._h, which, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def profile(self, on=True):
+        _check(lib().fl_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """{stage: (ms summed since the last read, launches)}"""
+        n = len(STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(lib().fl_profile_read(self._h, ms, cnt))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+    def close(self):
+        if self._h:
+            lib().fl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

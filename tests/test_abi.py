@@ -1,0 +1,79 @@
+"""The C-ABI library loads, exports every declared symbol and validates its
+arguments on the host (no GPU needed: validation precedes any device call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1911_10487_amd import flayer
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flayer.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(flayer.LIB_PATH),
+                                reason="libflayer.so not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fl_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert "fl_invert" in names and "fl_plan_create" in names
+    L = ctypes.CDLL(flayer.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_defaults():
+    o = flayer.default_opts()
+    assert o.tau == 1.5 and o.eta == 1e-10 and o.precision == 0 and o.px == 0
+
+
+def _create(nx=32, ny=32, nz=16, nd=16, h=0.125, planes=None, omegas=(2 * np.pi,), c0=1.0,
+            **kw):
+    L = flayer.lib()
+    planes = np.asarray(planes if planes is not None else 2.25 + 0.125 * np.arange(nd), np.float64)
+    om = np.asarray(omegas, np.float64)
+    o = flayer.default_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    out = ctypes.c_void_p()
+    st = L.fl_plan_create(nx, ny, nz, nd, h,
+                          planes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          om.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), c0, len(om),
+                          ctypes.byref(o), ctypes.byref(out))
+    return st, L.fl_last_error().decode(), out
+
+
+@pytest.mark.parametrize("kw,status,needle", [
+    (dict(nx=0), flayer.FL_EINVAL, "sizes"),
+    (dict(h=-1.0), flayer.FL_EINVAL, "h must"),
+    (dict(c0=0.0), flayer.FL_EINVAL, "c0"),
+    (dict(omegas=(0.0,)), flayer.FL_EINVAL, "omegas"),
+    (dict(omegas=(np.nan,)), flayer.FL_EINVAL, "omegas"),
+    (dict(planes=1.0 + 0.125 * np.arange(16)), flayer.FL_EINVAL, "inside X"),
+    (dict(planes=2.25 + 0.13 * np.arange(16)), flayer.FL_EINVAL, "spaced h"),
+    (dict(px=40), flayer.FL_EINVAL, "too small"),
+    (dict(nd=8, planes=2.25 + 0.125 * np.arange(8)), flayer.FL_EUNSUPPORTED, "nd"),
+    (dict(px=77), flayer.FL_EUNSUPPORTED, "FFT sizes"),
+    (dict(nz=20, nd=20, planes=3.0 + 0.125 * np.arange(20)), flayer.FL_EUNSUPPORTED, "nz"),
+    (dict(precision=7), flayer.FL_EUNSUPPORTED, "precision"),
+])
+def test_invalid_arguments_are_rejected_on_the_host(kw, status, needle):
+    st, msg, out = _create(**kw)
+    assert st == status, msg
+    assert needle in msg
+    assert not out.value
+
+
+def test_null_plan_is_rejected():
+    L = flayer.lib()
+    assert L.fl_invert(None, None, None, 0.0, None) == flayer.FL_EINVAL
+    assert "NULL" in L.fl_last_error().decode()
+    L.fl_plan_destroy(None)  # no-op

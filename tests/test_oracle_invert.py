@@ -100,3 +100,27 @@ def test_reconstruction_is_meaningful(small):
     x1, st = invert.invert(p, synth.add_noise(p, W, 0.01), u0, 0.01, stages=True)
     assert np.linalg.norm(x1.real - xi) < 0.8 * np.linalg.norm(xi)
     assert (st["branch"] == 0).mean() > 0.5
+
+
+@pytest.mark.parametrize("eta", [1e-10, 1e-8])
+def test_noise_free_inversion_is_fft_rounding_limited(small, eta, monkeypatch):
+    # delta = 0 solves every system at alpha = eta ||A||_F^2 (condition number
+    # up to eta^-1/2). Swapping numpy's FFT for scipy's (rounding differences
+    # only) moves v^ far above u but within 1e3 * u * eta^-1/2: the gate that
+    # the GPU parity tests use for noise-free data.
+    import scipy.fft as sf
+    p, xi, u0, W, U, V = small
+    x1, s1 = invert.invert(p, W, u0, 0.0, eta=eta, stages=True)
+    monkeypatch.setattr(np.fft, "fft2", lambda a, *k, **kw: sf.fft2(a, *k, **kw, workers=1))
+    monkeypatch.setattr(np.fft, "ifft2", lambda a, *k, **kw: sf.ifft2(a, *k, **kw, workers=1))
+    x2, s2 = invert.invert(p, W, u0, 0.0, eta=eta, stages=True)
+    d = np.linalg.norm(s2["Vhat"] - s1["Vhat"]) / np.linalg.norm(s1["Vhat"])
+    assert 1e-12 < d < 1e3 * 2.0 ** -53 * eta ** -0.5
+    # with noise the zero branch removes the tiny systems: FP64-level agreement
+    Wd = synth.add_noise(p, W, 0.01)
+    monkeypatch.undo()
+    y1 = invert.invert(p, Wd, u0, 0.01)
+    monkeypatch.setattr(np.fft, "fft2", lambda a, *k, **kw: sf.fft2(a, *k, **kw, workers=1))
+    monkeypatch.setattr(np.fft, "ifft2", lambda a, *k, **kw: sf.ifft2(a, *k, **kw, workers=1))
+    y2 = invert.invert(p, Wd, u0, 0.01)
+    assert np.linalg.norm(y2 - y1) / np.linalg.norm(y1) < 1e-12
