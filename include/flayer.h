@@ -173,8 +173,8 @@ enum {
   FL_STAGE_FFT_COLS,      /* (a) FFT along y */
   FL_STAGE_CLASSIFY,      /* (b) ||w_m||, zero test, compaction, v^ := 0 */
   FL_STAGE_BIDIAG,        /* (b) Householder bidiagonalization */
-  FL_STAGE_DP,            /* (b) discrepancy root and bidiagonal Tikhonov solve */
-  FL_STAGE_BACK,          /* (b) back-transform v^ = V y */
+  FL_STAGE_DP,            /* (b) discrepancy root, bidiagonal Tikhonov solve, v^ = V y */
+  FL_STAGE_BACK,          /* (b) reserved (the back-transform is part of FL_STAGE_DP) */
   FL_STAGE_IFFT_COLS,     /* (c) inverse FFT along y, rows of X's window */
   FL_STAGE_CROP_PAD,      /* (c) inverse FFT along x, crop, pad, FFT along x */
   FL_STAGE_CONV_COLS,     /* (c) FFT along y of the padded v */

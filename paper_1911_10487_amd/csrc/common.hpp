@@ -82,4 +82,58 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// ---- cross-lane moves without the LDS crossbar (gfx950 DPP / permlane)
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// value of lane (i ^ 16), within each half-wave
+__device__ __forceinline__ double xor16_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
+  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
+  return __hiloint2double(hi, lo);
+}
+
+// value of lane (i ^ 32)
+__device__ __forceinline__ double xor32_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const bool low = (threadIdx.x & 32) == 0;
+  return __hiloint2double(low ? rh[1] : rh[0], low ? rl[1] : rl[0]);
+}
+
+// Sum over the 16 lanes of a DPP row; every lane receives the bitwise same
+// total (each step adds a symmetric pair).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0x140>(v);  // row_mirror: i <-> 15 - i
+  v += dpp_d<0x141>(v);  // row_half_mirror: i <-> 7 - i within 8
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  return v;
+}
+
+// Sum over aligned groups of W lanes (W = 16, 32, 64).
+template <int W>
+__device__ __forceinline__ double lanes_sum(double v) {
+  v = row16_sum(v);
+  if (W >= 32) v += xor16_d(v);
+  if (W >= 64) v += xor32_d(v);
+  return v;
+}
+
+// Sum over the lanes of a wave that share (lane mod W): strides W .. 32.
+template <int W>
+__device__ __forceinline__ double strided_sum(double v) {
+  if (W <= 16) v += xor16_d(v);
+  if (W <= 32) v += xor32_d(v);
+  return v;
+}
+
 }  // namespace fl

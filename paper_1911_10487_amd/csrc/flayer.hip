@@ -82,8 +82,6 @@ struct fl_plan {
   int C = 0;
   z64 *dg = nullptr, *sp = nullptr, *q = nullptr, *refl = nullptr;
   double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
-  double *d = nullptr, *e = nullptr, *rho = nullptr, *off = nullptr;
-  z64 *qr = nullptr, *dr = nullptr, *rr = nullptr, *y = nullptr;
   double* alpha = nullptr;
   signed char* branch = nullptr;
   std::vector<void*> allocs;
@@ -306,7 +304,6 @@ fl_status solve_systems(fl_plan* p, double delta) {
   a.sp = p->sp;
   a.q = p->q;
   a.fro = p->fro;
-  a.wn2 = p->wnc;
   a.list = p->list;
   a.count = p->count;
   a.C = p->C;
@@ -314,27 +311,22 @@ fl_status solve_systems(fl_plan* p, double delta) {
   a.N = p->N;
   a.thr2 = p->thr2;
   a.eta = p->opts.eta;
-  a.d = p->d;
-  a.e = p->e;
-  a.qr = p->qr;
-  a.dr = p->dr;
-  a.rho = p->rho;
-  a.off = p->off;
-  a.rr = p->rr;
-  a.y = p->y;
+  a.refl = p->refl;
+  a.gam = p->gam;
+  a.Vh = p->Vh;
   a.alpha = p->alpha;
   a.branch = p->branch;
   const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
+  const unsigned gd = (unsigned)std::min<long>(p->C, 8192);
   for (long c0 = 0; c0 < FN; c0 += p->C) {
     RUN(mark(p, FL_STAGE_BIDIAG));
     RUN(launch_bidiag(p, (int)c0, gb, o));
     a.chunk0 = (int)c0;
     RUN(mark(p, FL_STAGE_DP));
-    hipLaunchKernelGGL(k_dp, dim3(nblk(p->C, 64)), dim3(64), 0, st, a);
-    LAUNCHCHK();
-    RUN(mark(p, FL_STAGE_BACK));
-    hipLaunchKernelGGL(k_backtransform<double>, dim3(nblk(p->C, 4)), dim3(256), 0, st, p->y, p->refl,
-                       p->gam, p->list, p->count, (int)c0, p->C, n, p->N, p->Vh);
+    if (n <= 64)
+      hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, st, a);
     LAUNCHCHK();
   }
   return FL_OK;
@@ -459,7 +451,9 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->partial, F * 256);
   PALLOC(p->thr2, F);
   PALLOC(p->norm2, F);
-  const long cap = nz <= 64 ? 32768 : 16384;
+  // reflector workspace C * nz^2 complex; up to 24 GiB, so that the
+  // 128^2 x 64 grids run as one chunk even with five frequencies
+  const long cap = std::max<long>(1024, (24L << 30) / ((long)nz * nz * (long)sizeof(z64)));
   p->C = (int)std::min<long>(FN, cap);
   const long C = p->C;
   PALLOC(p->dg, C * nz);
@@ -469,14 +463,6 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->wnc, C);
   PALLOC(p->refl, C * nz * nz);
   PALLOC(p->gam, C * nz);
-  PALLOC(p->d, C * nz);
-  PALLOC(p->e, C * nz);
-  PALLOC(p->qr, C * nz);
-  PALLOC(p->dr, C * nz);
-  PALLOC(p->rho, C * nz);
-  PALLOC(p->off, C * nz);
-  PALLOC(p->rr, C * nz);
-  PALLOC(p->y, C * nz);
   PALLOC(p->alpha, FN);
   PALLOC(p->branch, FN);
 #undef PALLOC

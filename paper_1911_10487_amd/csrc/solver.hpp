@@ -12,13 +12,13 @@
 //       reflections from both sides: A = U B V^H. The left reflections are
 //       applied to w on the fly (q = U^H w); the right ones are written out
 //       for the back-transform.
-//   k_dp
-//       one lane per system: phase-scale B to a real bidiagonal, pick alpha by
-//       the discrepancy principle with a safeguarded Newton iteration on
-//       log(alpha), every trial an O(n) Givens QR of [B; sqrt(alpha) I]
-//       (Elden's bidiagonal Tikhonov solve), and solve at the chosen alpha.
-//   k_backtransform
-//       one wave per system: v^ = V y, scattered into the plane-major v^.
+//   k_dp_solve
+//       one wave per system: phase-scale B to a real bidiagonal, pick alpha by
+//       the discrepancy principle with a 64-way multisection on log(alpha)
+//       (each lane evaluates the discrepancy at its own alpha in one O(n)
+//       pass), solve at the chosen alpha by Elden's Givens QR of
+//       [B; sqrt(alpha) I], and back-transform v^ = V y into the plane-major
+//       array.
 #pragma once
 #include "common.hpp"
 
@@ -135,6 +135,205 @@ struct BidiagOut {
   double* gam;  // [C][n]
 };
 
+// Exchange areas of one bidiagonalization workgroup (index = step parity).
+template <int n, int NW>
+struct BdShared {
+  z64 tb[2 * n];
+  z64 ul[2][n];       // left reflector u (entries k..n-1)
+  z64 xr[2][n];       // row k after the left update (entries k+1..n-1)
+  z64 zp[2][NW][n];   // per-wave partial z = A v
+  double lg[2];       // left gamma
+  z64 dg[n], sp[n];
+  double gm[n];
+  double red[2][NW];
+};
+
+// One Householder step k (left reflector from column k, right reflector
+// from row k). Row slots a < SA and column slots b < SB hold only finished
+// rows / columns for every k of the current block and are skipped at compile
+// time; the partially finished slots keep per-element tests.
+template <int TR, int TC, int NA, int NB, int SA, int SB>
+__device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShared<TR * NA, (TR * TC + 63) / 64>& S,
+                                        int k, int r, int c, int tid, int lane, int wv) {
+  constexpr int n = TR * NA;
+  constexpr int NW = (TR * TC + 63) / 64;
+  const int par = k & 1;
+  const int ka = k / TR, kr = k % TR;  // row k: row class kr, slot ka
+  const int kb = k / TC, kc = k % TC;  // column k: column class kc, slot kb
+  // ---------- A. left reflector from column k (holders: column class kc)
+  if (n - k >= 2) {
+    if (c == kc) {
+      z64 col[NA];
+#pragma unroll
+      for (int a = SA; a < NA; ++a) {
+        col[a] = mk(0.0, 0.0);
+#pragma unroll
+        for (int b = SB; b < NB; ++b)
+          if (b == kb) col[a] = A[a][b];
+      }
+      double s = 0.0;
+      z64 piv = mk(0.0, 0.0);
+#pragma unroll
+      for (int a = SA; a < NA; ++a) {
+        const int i = r + TR * a;
+        if (i >= k) s += nrm2(col[a]);
+        if (a == ka && r == kr) piv = col[a];
+      }
+      s = lanes_sum<TR>(s);
+      piv.x = lanes_sum<TR>(piv.x);
+      piv.y = lanes_sum<TR>(piv.y);
+      const double xn = sqrt(s);
+      const double ap = sqrt(nrm2(piv));
+      const z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
+      const z64 beta = mk(-ph.x * xn, -ph.y * xn);
+#pragma unroll
+      for (int a = SA; a < NA; ++a) {
+        const int i = r + TR * a;
+        if (i >= k) S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
+      }
+      if (r == kr) {
+        S.lg[par] = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
+        S.dg[k] = beta;
+      }
+    }
+  } else if (c == kc && r == kr) {
+#pragma unroll
+    for (int a = SA; a < NA; ++a)
+#pragma unroll
+      for (int b = SB; b < NB; ++b)
+        if (a == ka && b == kb) S.dg[k] = A[a][b];
+  }
+  __syncthreads();
+  // ---------- B. A <- (I - g u u^H) A on columns > k, and q likewise
+  if (n - k >= 2) {
+    const double g = S.lg[par];
+    z64 ur[NA];
+#pragma unroll
+    for (int a = SA; a < NA; ++a) {
+      const int i = r + TR * a;
+      ur[a] = (i >= k) ? S.ul[par][i] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = SB; b < NB; ++b) {
+      z64 sm = mk(0.0, 0.0);
+#pragma unroll
+      for (int a = SA; a < NA; ++a) sm = cfmac(sm, ur[a], A[a][b]);
+      sm.x = lanes_sum<TR>(sm.x);
+      sm.y = lanes_sum<TR>(sm.y);
+      const z64 w = g * sm;
+      const int j = c + TC * b;
+      if (j > k) {
+#pragma unroll
+        for (int a = SA; a < NA; ++a) A[a][b] = A[a][b] - ur[a] * w;
+      }
+    }
+    if (c == 0) {
+      z64 sm = mk(0.0, 0.0);
+#pragma unroll
+      for (int a = SA; a < NA; ++a) sm = cfmac(sm, ur[a], qr[a]);
+      sm.x = lanes_sum<TR>(sm.x);
+      sm.y = lanes_sum<TR>(sm.y);
+      sm = g * sm;
+#pragma unroll
+      for (int a = SA; a < NA; ++a) qr[a] = qr[a] - ur[a] * sm;
+    }
+  }
+  const int rk = n - k - 1;
+  if (rk >= 2) {
+    if (r == kr) {
+#pragma unroll
+      for (int b = SB; b < NB; ++b) {
+        const int j = c + TC * b;
+        if (j > k) {
+#pragma unroll
+          for (int a = SA; a < NA; ++a)
+            if (a == ka) S.xr[par][j] = A[a][b];
+        }
+      }
+    }
+    __syncthreads();
+    // ---------- C. right reflector from row k (every wave computes it)
+    double s = 0.0;
+    for (int j = k + 1 + lane; j < n; j += 64) s += nrm2(S.xr[par][j]);
+    s = lanes_sum<64>(s);
+    const double xn = sqrt(s);
+    const z64 piv = cj(S.xr[par][k + 1]);
+    const double ap = sqrt(nrm2(piv));
+    const z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
+    const z64 beta = mk(-ph.x * xn, -ph.y * xn);
+    const double g = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
+    z64 vr[NB];
+#pragma unroll
+    for (int b = SB; b < NB; ++b) {
+      const int j = c + TC * b;
+      z64 v = mk(0.0, 0.0);
+      if (j > k) {
+        v = cj(S.xr[par][j]);
+        if (j == k + 1) v = v - beta;
+      }
+      vr[b] = v;
+    }
+    if (tid == 0) {
+      S.gm[k] = g;
+      S.sp[k] = cj(beta);
+    }
+#pragma unroll
+    for (int a = SA; a < NA; ++a) {
+      z64 t = mk(0.0, 0.0);
+#pragma unroll
+      for (int b = SB; b < NB; ++b) t = cfma(t, A[a][b], vr[b]);
+      t.x = strided_sum<TR>(t.x);
+      t.y = strided_sum<TR>(t.y);
+      if (lane < TR) S.zp[par][wv][r + TR * a] = t;
+    }
+    __syncthreads();
+    // ---------- D. A <- A (I - g v v^H) on rows > k, columns > k
+#pragma unroll
+    for (int a = SA; a < NA; ++a) {
+      const int i = r + TR * a;
+      if (i > k) {
+        z64 z = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) z = z + S.zp[par][w][i];
+        z = g * z;
+#pragma unroll
+        for (int b = SB; b < NB; ++b) A[a][b] = A[a][b] - z * cj(vr[b]);
+      } else if (i == k) {
+        // row k is finished: keep the reflector in its place (LAPACK style)
+#pragma unroll
+        for (int b = SB; b < NB; ++b) A[a][b] = vr[b];
+      }
+    }
+  } else {
+    if (rk == 1) {
+      const int jb = (k + 1) / TC, jc = (k + 1) % TC;
+      if (r == kr && c == jc) {
+#pragma unroll
+        for (int a = SA; a < NA; ++a)
+#pragma unroll
+          for (int b = SB; b < NB; ++b)
+            if (a == ka && b == jb) S.sp[k] = A[a][b];
+      }
+    }
+    if (tid == 0) S.gm[k] = 0.0;
+  }
+}
+
+// Steps of k-block Q (KB = max(TR, TC) consecutive k), then the next block.
+template <int TR, int TC, int NA, int NB, int Q>
+__device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB], z64 (&qr)[NA],
+                                          BdShared<TR * NA, (TR * TC + 63) / 64>& S, int r, int c,
+                                          int tid, int lane, int wv) {
+  constexpr int n = TR * NA;
+  constexpr int KB = TR > TC ? TR : TC;
+  if constexpr (Q * KB < n) {
+    constexpr int SA = Q * KB / TR, SB = Q * KB / TC;
+    for (int k = Q * KB; k < (Q + 1) * KB && k < n; ++k)
+      bd_step<TR, TC, NA, NB, SA, SB>(A, qr, S, k, r, c, tid, lane, wv);
+    bd_blocks<TR, TC, NA, NB, Q + 1>(A, qr, S, r, c, tid, lane, wv);
+  }
+}
+
 template <int TR, int TC, int NA, int NB>
 __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys, int tpitch,
                                                    const z64* __restrict__ What, long N,
@@ -143,17 +342,10 @@ __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys,
                                                    BidiagOut o) {
   constexpr int n = TR * NA;
   static_assert(TR * NA == TC * NB, "square system");
+  static_assert(TR == 16 || TR == 32 || TR == 64, "row classes form aligned lane groups");
   constexpr int NT = TR * TC;
   constexpr int NW = (NT + 63) / 64;
-  __shared__ z64 tb[2 * n];
-  __shared__ z64 us[n];
-  __shared__ z64 vs[n];
-  __shared__ z64 xr[n];
-  __shared__ z64 qv[n];
-  __shared__ z64 zpart[NW][n];
-  __shared__ z64 dg[n], sp[n];
-  __shared__ double scal[4];
-  __shared__ double red[NW];
+  __shared__ BdShared<n, NW> S;
 
   const int tid = threadIdx.x;
   const int r = tid % TR, c = tid / TR;
@@ -167,8 +359,7 @@ __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys,
     const long m = fm % N;
     const int f = (int)(fm / N);
     const z64* trow = gsys + ((long)f * N + m) * tpitch;
-    for (int t = tid; t < 2 * n - 1; t += NT) tb[t] = trow[t];
-    for (int t = tid; t < n; t += NT) qv[t] = What[((long)f * n + t) * N + m];
+    for (int t = tid; t < 2 * n - 1; t += NT) S.tb[t] = trow[t];
     __syncthreads();
 
     z64 A[NA][NB];
@@ -177,225 +368,59 @@ __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys,
     for (int a = 0; a < NA; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        int i = r + TR * a, j = c + TC * b;
-        A[a][b] = tb[i - j + n - 1];
+        const int i = r + TR * a, j = c + TC * b;
+        A[a][b] = S.tb[i - j + n - 1];
         fr += nrm2(A[a][b]);
       }
-    // block sums of ||A||_F^2 and ||w||^2 (fixed order)
-    {
-      double wsum = 0.0;
-      if (tid < n) wsum = nrm2(qv[tid]);
-      fr = group_sum<64>(fr);
-      wsum = group_sum<64>(wsum);
-      if (lane == 0) red[wv] = fr;
-      __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < NW; ++w) s += red[w];
-        o.fro[sl] = s;
+    // q = U^H w lives with the column-class-0 threads, rows r + TR a
+    z64 qr[NA];
+    double wq = 0.0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      qr[a] = mk(0.0, 0.0);
+      if (c == 0) {
+        qr[a] = What[((long)f * n + r + TR * a) * N + m];
+        wq += nrm2(qr[a]);
       }
-      __syncthreads();
-      if (lane == 0) red[wv] = wsum;
-      __syncthreads();
-      if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < NW; ++w) s += red[w];
-        o.wn2[sl] = s;
+    }
+    fr = lanes_sum<64>(fr);
+    wq = lanes_sum<64>(wq);
+    if (lane == 0) {
+      S.red[0][wv] = fr;
+      S.red[1][wv] = wq;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        s0 += S.red[0][w];
+        s1 += S.red[1][w];
       }
-      __syncthreads();
+      o.fro[sl] = s0;
+      o.wn2[sl] = s1;
     }
 
+    bd_blocks<TR, TC, NA, NB, 0>(A, qr, S, r, c, tid, lane, wv);
+
+    __syncthreads();
     z64* refl = o.refl + (long)sl * n * n;
     double* gam = o.gam + (long)sl * n;
-
-    for (int k = 0; k < n; ++k) {
-      const int ka = k / TR, kr = k % TR;  // row k: row class kr, slot ka
-      const int kb = k / TC, kc = k % TC;  // column k: column class kc, slot kb
-      // ---------------- left reflector: column k, rows k..n-1
-      if (n - k >= 2) {
-        if (c == kc) {
-          z64 col[NA];
+    // right reflector k occupies row k, columns k+1..n-1
 #pragma unroll
-          for (int a = 0; a < NA; ++a) {
-            col[a] = mk(0.0, 0.0);
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-              if (b == kb) col[a] = A[a][b];
-          }
-          double s = 0.0;
-          z64 piv = mk(0.0, 0.0);
-#pragma unroll
-          for (int a = 0; a < NA; ++a) {
-            int i = r + TR * a;
-            if (i >= k) s += nrm2(col[a]);
-            if (a == ka && r == kr) piv = col[a];
-          }
-          s = group_sum<TR>(s);
-          piv.x = group_sum<TR>(piv.x);
-          piv.y = group_sum<TR>(piv.y);
-          double xn = sqrt(s);
-          double ap = sqrt(nrm2(piv));
-          z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
-          z64 beta = mk(-ph.x * xn, -ph.y * xn);
-          double g = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
-#pragma unroll
-          for (int a = 0; a < NA; ++a) {
-            int i = r + TR * a;
-            if (i >= k) us[i] = (i == k) ? (col[a] - beta) : col[a];
-          }
-          if (r == kr) {
-            scal[0] = g;
-            dg[k] = beta;
-          }
-        }
-      } else {
-        // last column: a 1x1 block, no reflection
-        if (c == kc && r == kr) {
-#pragma unroll
-          for (int a = 0; a < NA; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-              if (a == ka && b == kb) dg[k] = A[a][b];
-        }
+      for (int b = 0; b < NB; ++b) {
+        const int i = r + TR * a, j = c + TC * b;
+        if (j > i && i + 2 < n) refl[(long)i * n + j] = A[a][b];
       }
-      __syncthreads();
-      if (n - k >= 2) {
-        const double g = scal[0];
-        z64 ur[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          int i = r + TR * a;
-          ur[a] = (i >= k) ? us[i] : mk(0.0, 0.0);
-        }
-        z64 w[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          z64 s = mk(0.0, 0.0);
-#pragma unroll
-          for (int a = 0; a < NA; ++a) s = cfmac(s, ur[a], A[a][b]);
-          s.x = group_sum<TR>(s.x);
-          s.y = group_sum<TR>(s.y);
-          w[b] = g * s;
-        }
-#pragma unroll
-        for (int a = 0; a < NA; ++a)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            int j = c + TC * b;
-            if (j > k) {
-              z64 t = ur[a] * w[b];
-              A[a][b] = A[a][b] - t;
-            }
-          }
-        // q <- (I - g u u^H) q, by wave 0
-        if (wv == 0) {
-          z64 s = mk(0.0, 0.0);
-          for (int i = k + lane; i < n; i += 64) s = cfmac(s, us[i], qv[i]);
-          s.x = group_sum<64>(s.x);
-          s.y = group_sum<64>(s.y);
-          s = g * s;
-          for (int i = k + lane; i < n; i += 64) qv[i] = qv[i] - us[i] * s;
-        }
-      }
-      // ---------------- right reflector: row k, columns k+1..n-1
-      const int rk = n - k - 1;
-      if (rk >= 2) {
-        if (r == kr) {
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            int j = c + TC * b;
-            if (j > k) {
-#pragma unroll
-              for (int a = 0; a < NA; ++a)
-                if (a == ka) xr[j] = A[a][b];
-            }
-          }
-        }
-        __syncthreads();
-        if (wv == 0) {
-          // reflector built from conj(row): row^T P = conj(beta') e_1^T
-          double s = 0.0;
-          for (int j = k + 1 + lane; j < n; j += 64) s += nrm2(xr[j]);
-          s = group_sum<64>(s);
-          double xn = sqrt(s);
-          z64 piv = cj(xr[k + 1]);
-          double ap = sqrt(nrm2(piv));
-          z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
-          z64 beta = mk(-ph.x * xn, -ph.y * xn);
-          double g = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
-          for (int j = k + 1 + lane; j < n; j += 64) {
-            z64 v = cj(xr[j]);
-            if (j == k + 1) v = v - beta;
-            vs[j] = v;
-            refl[(long)k * n + j] = v;
-          }
-          if (lane == 0) {
-            scal[1] = g;
-            gam[k] = g;
-            sp[k] = cj(beta);
-          }
-        }
-        __syncthreads();
-        const double g = scal[1];
-        z64 vr[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          int j = c + TC * b;
-          vr[b] = (j > k) ? vs[j] : mk(0.0, 0.0);
-        }
-        z64 zp[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          z64 s = mk(0.0, 0.0);
-#pragma unroll
-          for (int b = 0; b < NB; ++b) s = cfma(s, A[a][b], vr[b]);
-          // sum over the column classes held by this wave
-#pragma unroll
-          for (int ofs = TR; ofs < 64; ofs <<= 1) {
-            s.x += __shfl_xor(s.x, ofs, 64);
-            s.y += __shfl_xor(s.y, ofs, 64);
-          }
-          zp[a] = s;
-        }
-        if (lane < TR) {
-#pragma unroll
-          for (int a = 0; a < NA; ++a) zpart[wv][r + TR * a] = zp[a];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          int i = r + TR * a;
-          z64 z = mk(0.0, 0.0);
-#pragma unroll
-          for (int w = 0; w < NW; ++w) z = z + zpart[w][i];
-          z = g * z;
-          if (i > k) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              int j = c + TC * b;
-              if (j > k) A[a][b] = A[a][b] - z * cj(vr[b]);
-            }
-          }
-        }
-      } else if (rk == 1) {
-        const int jb = (k + 1) / TC, jc = (k + 1) % TC;
-        if (r == kr && c == jc) {
-#pragma unroll
-          for (int a = 0; a < NA; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-              if (a == ka && b == jb) sp[k] = A[a][b];
-        }
-        if (tid == 0) gam[k] = 0.0;
-      } else {
-        if (tid == 0) gam[k] = 0.0;
-      }
-      __syncthreads();
-    }
     for (int t = tid; t < n; t += NT) {
-      o.dg[(long)t * C + sl] = dg[t];
-      o.sp[(long)t * C + sl] = (t < n - 1) ? sp[t] : mk(0.0, 0.0);
-      o.q[(long)t * C + sl] = qv[t];
+      gam[t] = S.gm[t];
+      o.dg[(long)t * C + sl] = S.dg[t];
+      o.sp[(long)t * C + sl] = (t < n - 1) ? S.sp[t] : mk(0.0, 0.0);
+    }
+    if (c == 0) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) o.q[(long)(r + TR * a) * C + sl] = qr[a];
     }
     __syncthreads();
   }
@@ -404,197 +429,221 @@ __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys,
 // ---------------------------------------------------------------- dp
 
 struct DpArgs {
-  const z64* dg;
+  const z64* dg;       // [n][C] bidiagonal of A (complex)
   const z64* sp;
-  const z64* q;
-  const double* fro;
-  const double* wn2;
+  const z64* q;        // [n][C] U^H w
+  const double* fro;   // [C]
   const int* list;
   const int* count;
   int chunk0, C, n;
   long N;
   const double* thr2;  // per frequency: (tau delta_m)^2, < 0 for noise-free data
   double eta;
-  // scratch, [n][C]
-  double* d;
-  double* e;
-  z64* qr;
-  z64* dr;
-  double* rho;
-  double* off;
-  z64* rr;
-  z64* y;        // output [n][C]: y = D_R y' (before the right reflectors)
-  double* alpha; // [F*N]
-  signed char* branch;  // [F*N]
+  const z64* refl;     // [C][n][n] right reflectors
+  const double* gam;   // [C][n]
+  z64* Vh;             // [F][n][N] output, plane-major
+  double* alpha;       // [F*N]
+  signed char* branch; // [F*N]
 };
 
-// Elden: min ||B y - q||^2 + alpha ||y||^2 for real upper bidiagonal B (d, e)
-// by Givens QR of [B; sqrt(alpha) I]; returns phi = ||B y - q||^2 and, when
-// want_d, dphi/dalpha = 2 alpha ||R^-T y||^2. Writes y when ys != nullptr.
-__device__ double elden(const DpArgs& a, int sl, double alpha, bool want_d, double* dphi,
-                        z64* ys) {
-  const int n = a.n;
-  const long C = a.C;
+// phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
+// bidiagonal B (d, e), evaluated in one forward pass without storage:
+// phi = -alpha^2 g'(alpha) with g = q^H (B B^T + alpha I)^{-1} q, g from the
+// LDL^T recurrence of the tridiagonal B B^T + alpha I and g' by forward-mode
+// differentiation of the same recurrence.
+__device__ __forceinline__ double phi_fwd(const double* __restrict__ d, const double* __restrict__ e,
+                                          const z64* __restrict__ q, int n, double alpha) {
+  double D = d[0] * d[0] + e[0] * e[0] + alpha;
+  double Dp = 1.0;
+  z64 z = q[0], zp = mk(0.0, 0.0);
+  double rD = 1.0 / D;
+  double gp = -nrm2(z) * Dp * rD * rD;
+  for (int i = 1; i < n; ++i) {
+    const double b = e[i - 1] * d[i];
+    const double l = b * rD;
+    const double ei = (i < n - 1) ? e[i] : 0.0;
+    const double Dn = d[i] * d[i] + ei * ei + alpha - l * b;
+    const double Dpn = 1.0 + l * l * Dp;
+    const double c1 = l * Dp * rD;
+    const z64 zn = q[i] - l * z;
+    const z64 zpn = c1 * z - l * zp;
+    D = Dn;
+    Dp = Dpn;
+    z = zn;
+    zp = zpn;
+    rD = 1.0 / D;
+    gp += 2.0 * (z.x * zp.x + z.y * zp.y) * rD - nrm2(z) * Dp * rD * rD;
+  }
+  return -alpha * alpha * gp;
+}
+
+// Elden: Givens QR of [B; sqrt(alpha) I], back substitution; writes y.
+__device__ void elden_solve(const double* __restrict__ d, const double* __restrict__ e,
+                            const z64* __restrict__ q, int n, double alpha, double* rho,
+                            double* off, z64* rr, z64* y) {
   const double mu = sqrt(alpha);
   double mt = mu;
   z64 g = mk(0.0, 0.0);
   for (int i = 0; i < n; ++i) {
-    const double di = a.d[i * C + sl];
-    const z64 qi = a.qr[i * C + sl];
-    double p = sqrt(di * di + mt * mt);
-    double cs = p > 0.0 ? di / p : 1.0;
-    double sn = p > 0.0 ? mt / p : 0.0;
-    a.rho[i * C + sl] = p;
-    a.rr[i * C + sl] = cs * qi + sn * g;
-    z64 gp = (-sn) * qi + cs * g;
+    const double di = d[i];
+    const z64 qi = q[i];
+    const double p = sqrt(di * di + mt * mt);
+    const double cs = p > 0.0 ? di / p : 1.0;
+    const double sn = p > 0.0 ? mt / p : 0.0;
+    rho[i] = p;
+    rr[i] = cs * qi + sn * g;
+    const z64 gp = (-sn) * qi + cs * g;
     if (i < n - 1) {
-      const double ei = a.e[i * C + sl];
-      a.off[i * C + sl] = cs * ei;
-      double fz = -sn * ei;
-      double p2 = sqrt(mu * mu + fz * fz);
-      double s2 = p2 > 0.0 ? fz / p2 : 0.0;
+      const double ei = e[i];
+      off[i] = cs * ei;
+      const double fz = -sn * ei;
+      const double p2 = sqrt(mu * mu + fz * fz);
       mt = p2;
-      g = s2 * gp;
+      g = (p2 > 0.0 ? fz / p2 : 0.0) * gp;
     }
   }
-  // back substitution and residual
   z64 yn = mk(0.0, 0.0);
-  double phi = 0.0;
-  double ynorm_unused = 0.0;
-  (void)ynorm_unused;
   for (int i = n - 1; i >= 0; --i) {
-    const double p = a.rho[i * C + sl];
-    z64 t = a.rr[i * C + sl];
-    if (i < n - 1) t = t - a.off[i * C + sl] * yn;
-    z64 yi = p > 0.0 ? mk(t.x / p, t.y / p) : mk(0.0, 0.0);
-    // residual row i: d_i y_i + e_i y_{i+1} - q_i
-    z64 res = a.d[i * C + sl] * yi - a.qr[i * C + sl];
-    if (i < n - 1) res = res + a.e[i * C + sl] * yn;
-    phi += nrm2(res);
-    if (ys) ys[i * C + sl] = yi;
-    a.y[i * C + sl] = yi;  // keep y for the derivative pass
+    z64 t = rr[i];
+    if (i < n - 1) t = t - off[i] * yn;
+    const double p = rho[i];
+    const z64 yi = p > 0.0 ? mk(t.x / p, t.y / p) : mk(0.0, 0.0);
+    y[i] = yi;
     yn = yi;
   }
-  if (want_d) {
-    z64 zp = mk(0.0, 0.0);
-    double zz = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double p = a.rho[i * C + sl];
-      z64 t = a.y[i * C + sl];
-      if (i > 0) t = t - a.off[(i - 1) * C + sl] * zp;
-      z64 zi = p > 0.0 ? mk(t.x / p, t.y / p) : mk(0.0, 0.0);
-      zz += nrm2(zi);
-      zp = zi;
-    }
-    *dphi = 2.0 * alpha * zz;
-  }
-  return phi;
 }
 
-__global__ __launch_bounds__(64) void k_dp(DpArgs a) {
-  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl >= a.C) return;
-  const int gs = a.chunk0 + sl;
-  if (gs >= *a.count) return;
-  const int fm = a.list[gs];
-  const int f = (int)(fm / a.N);
+// One single-wave workgroup per active system: phase-scale the bidiagonal to
+// a real one, choose alpha by the discrepancy principle with a 64-way
+// multisection on log(alpha), solve at that alpha (Elden), apply the right
+// reflectors (v^ = V y) and scatter v^ into the plane-major array.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
+  __shared__ double sd[NMAX], se[NMAX], srho[NMAX], soff[NMAX];
+  __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
+  __shared__ double sx[2];
+  const int lane = threadIdx.x;
   const int n = a.n;
   const long C = a.C;
-  // phase scaling to a real nonnegative bidiagonal: B = D_L B' D_R^H
-  z64 drc = mk(1.0, 0.0);
-  for (int i = 0; i < n; ++i) {
-    z64 t = a.dg[i * C + sl] * drc;
-    double at = sqrt(nrm2(t));
-    z64 dl = at > 0.0 ? mk(t.x / at, t.y / at) : mk(1.0, 0.0);
-    a.d[i * C + sl] = at;
-    a.dr[i * C + sl] = drc;
-    a.qr[i * C + sl] = cmulc(dl, a.q[i * C + sl]);
-    if (i < n - 1) {
-      z64 s = cmulc(dl, a.sp[i * C + sl]);
-      double as = sqrt(nrm2(s));
-      a.e[i * C + sl] = as;
-      drc = as > 0.0 ? mk(s.x / as, -s.y / as) : mk(1.0, 0.0);
+  const int total = *a.count;
+  for (int sl = blockIdx.x; sl < a.C; sl += gridDim.x) {
+    const int gs = a.chunk0 + sl;
+    if (gs >= total) break;
+    const int fm = a.list[gs];
+    const int f = (int)(fm / a.N);
+    const long m = fm - (long)f * a.N;
+    // stage the complex bidiagonal and q
+    for (int i = lane; i < n; i += 64) {
+      sy[i] = a.dg[i * C + sl];
+      srr[i] = a.sp[i * C + sl];
+      sq[i] = a.q[i * C + sl];
     }
-  }
-  const double T = a.thr2[f];
-  const double amin = a.eta * a.fro[sl];
-  double alpha = amin;
-  signed char br = 1;
-  if (T >= 0.0) {
-    double dum;
-    double p0 = elden(a, sl, amin, false, &dum, nullptr);
-    if (p0 < T) {
-      br = 2;
+    __syncthreads();
+    // B = D_L B' D_R^H with B' real nonnegative (sequential phase chain)
+    if (lane == 0) {
+      z64 drc = mk(1.0, 0.0);
+      for (int i = 0; i < n; ++i) {
+        const z64 t = sy[i] * drc;
+        const double at = sqrt(nrm2(t));
+        const z64 dl = at > 0.0 ? mk(t.x / at, t.y / at) : mk(1.0, 0.0);
+        sd[i] = at;
+        sdr[i] = drc;
+        sq[i] = cmulc(dl, sq[i]);
+        if (i < n - 1) {
+          const z64 s = cmulc(dl, srr[i]);
+          const double as = sqrt(nrm2(s));
+          se[i] = as;
+          drc = as > 0.0 ? mk(s.x / as, -s.y / as) : mk(1.0, 0.0);
+        } else {
+          se[i] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    const double T = a.thr2[f];
+    const double fro = a.fro[sl];
+    const double amin = a.eta * fro;
+    double al = amin;
+    signed char br = 1;
+    if (T >= 0.0) {
+      // round 0: lane 0 tests the floor, lanes 1.. probe upward for phi >= T
       double lo = log(amin);
-      double hi = log(a.fro[sl]) + 1.0;
-      for (int it = 0; it < 400; ++it) {
-        double ph = elden(a, sl, exp(hi), false, &dum, nullptr);
-        if (ph >= T || hi > 690.0) break;
-        hi += 4.0;
+      const double h0 = log(fro) + 1.0;
+      double x = lane == 0 ? lo : h0 + 4.0 * (lane - 1);
+      bool ge = phi_fwd(sd, se, sq, n, exp(x)) >= T;
+      unsigned long long bal = __ballot(ge);
+      if (!(bal & 1ull)) {
+        br = 2;
+        unsigned long long up = bal & ~1ull;
+        double hi;
+        if (up) {
+          int l1 = __ffsll((long long)up) - 1;
+          hi = h0 + 4.0 * (l1 - 1);
+          if (l1 > 1) lo = h0 + 4.0 * (l1 - 2);
+        } else {
+          hi = h0 + 4.0 * 62;
+          lo = hi;
+        }
+        for (int round = 0; round < 12 && hi - lo > 4e-16 * fmax(1.0, fabs(hi)); ++round) {
+          const double step = (hi - lo) / 65.0;
+          const double xl = lo + step * (lane + 1);
+          const bool g2 = phi_fwd(sd, se, sq, n, exp(xl)) >= T;
+          const unsigned long long b2 = __ballot(g2);
+          if (b2) {
+            const int l1 = __ffsll((long long)b2) - 1;
+            const double nhi = lo + step * (l1 + 1);
+            const double nlo = l1 > 0 ? lo + step * l1 : lo;
+            hi = nhi;
+            lo = nlo;
+          } else {
+            lo = lo + step * 64;
+          }
+        }
+        al = exp(0.5 * (lo + hi));
       }
-      double x = 0.5 * (lo + hi);
-      for (int it = 0; it < 200; ++it) {
-        double al = exp(x);
-        double dphi = 0.0;
-        double ph = elden(a, sl, al, true, &dphi, nullptr);
-        double F = ph - T;
-        if (F >= 0.0)
-          hi = x;
-        else
-          lo = x;
-        double Fp = al * dphi;
-        double xn = (Fp > 0.0) ? x - F / Fp : 0.5 * (lo + hi);
-        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        double step = fabs(xn - x);
-        x = xn;
-        if (step <= 4e-16 * fmax(1.0, fabs(x)) || hi - lo <= 4e-16 * fmax(1.0, fabs(x))) break;
-      }
-      alpha = exp(x);
     }
+    if (lane == 0) elden_solve(sd, se, sq, n, al, srho, soff, srr, sy);
+    __syncthreads();
+    // v^ = V (D_R y'), V = P_0 P_1 ... P_{n-3}
+    z64 y0 = lane < n ? sdr[lane] * sy[lane] : mk(0.0, 0.0);
+    z64 y1 = lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
+    const z64* R = a.refl + (long)sl * n * n;
+    const double* G = a.gam + (long)sl * n;
+    // reflector k has entries k+1..n-1; rows are prefetched one step ahead
+    z64 n0 = mk(0.0, 0.0), n1 = mk(0.0, 0.0);
+    double ng = 0.0;
+    if (n >= 3) {
+      const int k = n - 3;
+      ng = G[k];
+      if (lane > k && lane < n) n0 = R[(long)k * n + lane];
+      if (lane + 64 > k && lane + 64 < n) n1 = R[(long)k * n + lane + 64];
+    }
+    for (int k = n - 3; k >= 0; --k) {
+      const double g = ng;
+      const z64 v0 = n0, v1 = n1;
+      if (k > 0) {
+        const int kk = k - 1;
+        ng = G[kk];
+        n0 = (lane > kk && lane < n) ? R[(long)kk * n + lane] : mk(0.0, 0.0);
+        n1 = (lane + 64 > kk && lane + 64 < n) ? R[(long)kk * n + lane + 64] : mk(0.0, 0.0);
+      }
+      z64 s = cmulc(v0, y0);
+      s = cfmac(s, v1, y1);
+      s.x = lanes_sum<64>(s.x);
+      s.y = lanes_sum<64>(s.y);
+      s = g * s;
+      y0 = y0 - v0 * s;
+      y1 = y1 - v1 * s;
+    }
+    z64* out = a.Vh + (long)f * n * a.N + m;
+    if (lane < n) out[(long)lane * a.N] = y0;
+    if (lane + 64 < n) out[(long)(lane + 64) * a.N] = y1;
+    if (lane == 0) {
+      a.alpha[fm] = al;
+      a.branch[fm] = br;
+    }
+    __syncthreads();
   }
-  double dum;
-  elden(a, sl, alpha, false, &dum, nullptr);
-  for (int i = 0; i < n; ++i) a.y[i * C + sl] = a.dr[i * C + sl] * a.y[i * C + sl];
-  a.alpha[fm] = alpha;
-  a.branch[fm] = br;
-}
-
-// one wave per system: v^ = V y, V = P_0 P_1 ... (right reflectors)
-template <typename T>
-__global__ __launch_bounds__(256) void k_backtransform(const z64* __restrict__ y,
-                                                       const z64* __restrict__ refl,
-                                                       const double* __restrict__ gam,
-                                                       const int* __restrict__ list,
-                                                       const int* __restrict__ count, int chunk0,
-                                                       int C, int n, long N, cx<T>* __restrict__ Vh) {
-  const int lane = threadIdx.x & 63;
-  const int sl = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (sl >= C) return;
-  const int gs = chunk0 + sl;
-  if (gs >= *count) return;
-  const int fm = list[gs];
-  const int f = (int)(fm / N);
-  const long m = fm - (long)f * N;
-  z64 y0 = lane < n ? y[(long)lane * C + sl] : mk(0.0, 0.0);
-  z64 y1 = lane + 64 < n ? y[(long)(lane + 64) * C + sl] : mk(0.0, 0.0);
-  const z64* R = refl + (long)sl * n * n;
-  const double* G = gam + (long)sl * n;
-  for (int k = n - 3; k >= 0; --k) {
-    const double g = G[k];
-    z64 v0 = (lane > k && lane < n) ? R[(long)k * n + lane] : mk(0.0, 0.0);
-    z64 v1 = (lane + 64 > k && lane + 64 < n) ? R[(long)k * n + lane + 64] : mk(0.0, 0.0);
-    z64 s = mk(0.0, 0.0);
-    s = cfmac(s, v0, y0);
-    s = cfmac(s, v1, y1);
-    s.x = group_sum<64>(s.x);
-    s.y = group_sum<64>(s.y);
-    s = g * s;
-    y0 = y0 - v0 * s;
-    y1 = y1 - v1 * s;
-  }
-  cx<T>* out = Vh + (long)f * n * N + m;
-  if (lane < n) out[(long)lane * N] = cast<T>(y0);
-  if (lane + 64 < n) out[(long)(lane + 64) * N] = cast<T>(y1);
 }
 
 }  // namespace fl
