@@ -151,8 +151,9 @@ fl_status fl_plan_refresh_info(fl_plan *plan);
  *                  sampled at height difference zeta_d), d = j - l + nz - 1
  *   FL_TAP_KTAB    [n_omega][2nz][py][px] complex: omega^2 / (2 nz px py)
  *                  times the 3D DFT of the volume kernel
- * Complex elements are complex128 when precision = 0, complex64 otherwise
- * for WHAT, VHAT, GTAB, KTAB (V and U are always complex128).
+ * WHAT and VHAT hold complex64 when precision = 1; every other tap is
+ * complex128 (the tables are built in FP64; the mixed path keeps an FP32
+ * copy of KTAB).
  * Errors: FL_EINVAL for an unknown tap or a size mismatch.
  */
 enum {

@@ -82,6 +82,21 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// ---- reciprocal and reciprocal square root: hardware estimate + two Newton
+// steps (quadratic convergence), for positive normal arguments
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  r = r * fma(-0.5 * x * r, r, 1.5);
+  return r;
+}
+
 // ---- cross-lane moves without the LDS crossbar (gfx950 DPP / permlane)
 
 template <int CTRL>

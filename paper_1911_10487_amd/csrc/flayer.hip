@@ -72,9 +72,13 @@ struct fl_plan {
   z64* gtab = nullptr;  // [F][nzeta][N]
   z64* gsys = nullptr;  // [F][N][TP]
   z64* ktab = nullptr;  // [F][2nz][N]
-  // workspaces
-  z64 *What = nullptr, *Vh = nullptr, *w1 = nullptr, *w2 = nullptr;
-  z64 *vX = nullptr, *u = nullptr, *u0w = nullptr, *Ww = nullptr;
+  // single-precision copies used by the mixed path
+  z32 *tw_x32 = nullptr, *tw_y32 = nullptr, *tw_z32 = nullptr;
+  z32* ktab32 = nullptr;
+  int prec = 0;  // 0: FP64 throughout; 1: FP32 FFTs/convolution/storage
+  // workspaces (complex64 or complex128 by precision)
+  void *What = nullptr, *Vh = nullptr, *w1 = nullptr, *w2 = nullptr;
+  z64 *vX = nullptr, *u = nullptr, *u0w = nullptr;
   double *wn2 = nullptr, *partial = nullptr, *thr2 = nullptr, *norm2 = nullptr;
   int *flag = nullptr, *cnt = nullptr, *list = nullptr, *count = nullptr;
   int nb_scan = 0;
@@ -111,21 +115,29 @@ fl_status dalloc(fl_plan* p, P** ptr, size_t count) {
   return FL_OK;
 }
 
+fl_status dalloc_bytes(fl_plan* p, void** ptr, size_t b) {
+  unsigned char* v = nullptr;
+  fl_status s = dalloc(p, &v, b);
+  *ptr = v;
+  return s;
+}
+
 #define ALLOC(ptr, cnt)                          \
   do {                                           \
     fl_status s_ = dalloc(p, &(ptr), (size_t)(cnt)); \
     if (s_ != FL_OK) return s_;                  \
   } while (0)
 
-fl_status make_twiddles(fl_plan* p, z64** out, int L) {
-  std::vector<z64> h(L);
+template <typename T>
+fl_status make_twiddles(fl_plan* p, cx<T>** out, int L) {
+  std::vector<cx<T>> h(L);
   for (int i = 0; i < L; ++i) {
-    // exp(-2 pi i i / L), argument reduced by symmetry for accuracy
+    // exp(-2 pi i i / L) in extended precision, rounded once
     long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)i / (long double)L;
-    h[i] = mk((double)cosl(a), (double)sinl(a));
+    h[i] = mk((T)cosl(a), (T)sinl(a));
   }
   ALLOC(*out, L);
-  HIPCHK(hipMemcpy(*out, h.data(), L * sizeof(z64), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(*out, h.data(), L * sizeof(cx<T>), hipMemcpyHostToDevice));
   return FL_OK;
 }
 
@@ -260,11 +272,12 @@ fl_status mark(fl_plan* p, int s) {
   return FL_OK;
 }
 
+template <typename T>
 fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   const int n = p->n;
-  const z64* What = p->What;
-#define BD(TR, TC, NA, NB)                                                                   \
-  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB>), dim3(grid), dim3(TR * TC), 0, p->st, p->gsys, \
+  const cx<T>* What = (const cx<T>*)p->What;
+#define BD(TR, TC, NA, NB)                                                                      \
+  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB, T>), dim3(grid), dim3(TR * TC), 0, p->st, p->gsys, \
                      p->TP, What, p->N, p->list, p->count, chunk0, p->C, o)
   switch (n) {
     case 16: BD(16, 4, 1, 4); break;
@@ -281,13 +294,14 @@ fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   return FL_OK;
 }
 
+template <typename T>
 fl_status solve_systems(fl_plan* p, double delta) {
   const long FN = (long)p->F * p->N;
   const int n = p->n;
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
-  hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, p->What, p->nd, p->N,
-                     p->F, p->thr2, p->wn2, p->flag);
+  hipLaunchKernelGGL(k_classify<T>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const cx<T>*)p->What,
+                     p->nd, p->N, p->F, p->thr2, p->wn2, p->flag);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
   LAUNCHCHK();
@@ -295,7 +309,7 @@ fl_status solve_systems(fl_plan* p, double delta) {
   LAUNCHCHK();
   hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt, p->list);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(FN * p->nz, 256)), dim3(256), 0, st, p->Vh,
+  hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * p->nz, 256)), dim3(256), 0, st, (cx<T>*)p->Vh,
                      FN * p->nz);
   LAUNCHCHK();
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam};
@@ -314,13 +328,14 @@ fl_status solve_systems(fl_plan* p, double delta) {
   a.refl = p->refl;
   a.gam = p->gam;
   a.Vh = p->Vh;
+  a.vh_single = sizeof(T) == 4;
   a.alpha = p->alpha;
   a.branch = p->branch;
   const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
   const unsigned gd = (unsigned)std::min<long>(p->C, 8192);
   for (long c0 = 0; c0 < FN; c0 += p->C) {
     RUN(mark(p, FL_STAGE_BIDIAG));
-    RUN(launch_bidiag(p, (int)c0, gb, o));
+    RUN(launch_bidiag<T>(p, (int)c0, gb, o));
     a.chunk0 = (int)c0;
     RUN(mark(p, FL_STAGE_DP));
     if (n <= 64)
@@ -329,6 +344,115 @@ fl_status solve_systems(fl_plan* p, double delta) {
       hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, st, a);
     LAUNCHCHK();
   }
+  return FL_OK;
+}
+
+// The inversion launch sequence; T is the FFT / storage precision.
+template <typename T>
+fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out) {
+  hipStream_t st = p->st;
+  const long N = p->N;
+  const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  const long nvox = (long)nx * ny * nz;
+  const cx<T>* twx = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_x32 : (const void*)p->tw_x);
+  const cx<T>* twy = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_y32 : (const void*)p->tw_y);
+  const cx<T>* twz = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_z32 : (const void*)p->tw_z);
+  const cx<T>* ktab = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->ktab32 : (const void*)p->ktab);
+  RUN(mark(p, FL_STAGE_NORM));
+  // noise thresholds: thr2[f] = (tau delta ||W_f||)^2
+  {
+    dim3 g(256, F);
+    if (p->opts.input_dtype == 0)
+      hipLaunchKernelGGL(k_sumsq<double>, g, dim3(256), 0, st, (const z64*)W, (long)nd * N, p->partial);
+    else
+      hipLaunchKernelGGL(k_sumsq<float>, g, dim3(256), 0, st, (const z32*)W, (long)nd * N, p->partial);
+    LAUNCHCHK();
+    double td = p->opts.tau * delta;
+    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
+                       p->norm2);
+    LAUNCHCHK();
+  }
+  const z64* u0d = (const z64*)u0;
+  if (p->opts.input_dtype == 1) {
+    hipLaunchKernelGGL(k_widen<float>, dim3(nblk(F * nvox, 256)), dim3(256), 0, st, (const z32*)u0,
+                       p->u0w, (long)F * nvox);
+    LAUNCHCHK();
+    u0d = p->u0w;
+  }
+  // (a) FFT2 of W: rows, then columns -> W^ plane-major [F][nd][py][px]
+  {
+    RUN(mark(p, FL_STAGE_FFT_ROWS));
+    FftArgs g = rows_args(W, p->w1, twx, px, (long)F * nd * py);
+    if (p->opts.input_dtype == 0)
+      RUN((run_fft<double, T, T, -1>(g, st)));
+    else
+      RUN((run_fft<float, T, T, -1>(g, st)));
+    RUN(mark(p, FL_STAGE_FFT_COLS));
+    RUN((run_fft<T, T, T, -1>(cols_args(p->w1, p->What, twy, py, px, F * nd), st)));
+  }
+  // (b) regularized solves of the active systems -> v^ plane-major
+  RUN(solve_systems<T>(p, delta));
+  // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
+  {
+    RUN(mark(p, FL_STAGE_IFFT_COLS));
+    FftArgs g = cols_args(p->Vh, p->w1, twy, py, px, F * nz);
+    g.lout = ny;
+    g.out_off = p->oy;
+    g.out_sp = (long)ny * px;
+    RUN((run_fft<T, T, T, 1>(g, st)));
+    int CB = pick_cb(px, sizeof(cx<T>));
+    long rows = (long)F * nz * ny;
+    size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(cx<T>);
+    RUN(mark(p, FL_STAGE_CROP_PAD));
+    hipLaunchKernelGGL(k_rows_crop_pad<T>, dim3(nblk(rows, CB)), dim3(256), lds, st,
+                       (const cx<T>*)p->w1, p->vX, (cx<T>*)p->w2, twx, px, nx, p->ox, (int)rows,
+                       1.0 / (double)N, CB);
+    LAUNCHCHK();
+    FftArgs c = cols_args(p->w2, p->w1, twy, py, px, F * nz);
+    c.lin = ny;
+    c.in_sp = (long)ny * px;
+    RUN(mark(p, FL_STAGE_CONV_COLS));
+    RUN((run_fft<T, T, T, -1>(c, st)));
+    FftArgs z{};
+    z.in = p->w1;
+    z.out = p->w1;
+    z.tw = twz;
+    z.L = 2 * nz;
+    z.lin = nz;
+    z.lout = nz;
+    z.in_sk = N;
+    z.in_sb = 1;
+    z.in_sp = (long)nz * N;
+    z.out_sk = N;
+    z.out_sb = 1;
+    z.out_sp = (long)nz * N;
+    z.B = (int)N;
+    z.planes = F;
+    z.scale = 1.0;
+    int CBz = pick_cb(2 * nz, sizeof(cx<T>));
+    size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(cx<T>);
+    RUN(mark(p, FL_STAGE_CONV_Z));
+    hipLaunchKernelGGL(k_fft_conv<T>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, ktab, (long)N,
+                       (long)2 * nz * N, CBz);
+    LAUNCHCHK();
+    FftArgs b = cols_args(p->w1, p->w2, twy, py, px, F * nz);
+    b.lout = ny;
+    b.out_sp = (long)ny * px;
+    RUN(mark(p, FL_STAGE_CONV_ICOLS));
+    RUN((run_fft<T, T, T, 1>(b, st)));
+    FftArgs r = rows_args(p->w2, p->u, twx, px, rows);
+    r.lout = nx;
+    r.out_sb = nx;
+    r.add = u0d;
+    RUN(mark(p, FL_STAGE_CONV_IROWS));
+    RUN((run_fft<T, T, double, 1>(r, st)));
+  }
+  // (d) xi, in FP64
+  RUN(mark(p, FL_STAGE_XI));
+  hipLaunchKernelGGL(k_xi, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->u, p->vX, nvox, F,
+                     p->opts.combine, (z64*)xi_out);
+  LAUNCHCHK();
+  RUN(mark(p, -1));
   return FL_OK;
 }
 
@@ -386,7 +510,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
                 py, 2 * nz);
   if (!(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
     return fail(FL_EUNSUPPORTED, "nz = %d: this build solves nz in {16,32,48,64,80,96,128}", nz);
-  if (o.precision != 0) return fail(FL_EUNSUPPORTED, "only precision 0 (FP64) in this build");
+  if (o.precision != 0 && o.precision != 1) return fail(FL_EUNSUPPORTED, "precision must be 0 or 1");
   if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
   if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
 
@@ -412,6 +536,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   p->ox = (px - nx) / 2;
   p->oy = (py - ny) / 2;
   p->n = nz;
+  p->prec = o.precision;
   auto bail = [&](fl_status s) {
     fl_plan_destroy(p);
     return s;
@@ -428,20 +553,30 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     if ((s = make_twiddles(p, &p->tw_x, px)) != FL_OK) return bail(s);
     if ((s = make_twiddles(p, &p->tw_y, py)) != FL_OK) return bail(s);
     if ((s = make_twiddles(p, &p->tw_z, 2 * nz)) != FL_OK) return bail(s);
+    if (p->prec) {
+      if ((s = make_twiddles(p, &p->tw_x32, px)) != FL_OK) return bail(s);
+      if ((s = make_twiddles(p, &p->tw_y32, py)) != FL_OK) return bail(s);
+      if ((s = make_twiddles(p, &p->tw_z32, 2 * nz)) != FL_OK) return bail(s);
+    }
   }
   PALLOC(p->gtab, F * p->nzeta * N);
   PALLOC(p->gsys, FN * p->TP);
   PALLOC(p->ktab, F * 2 * nz * N);
   const long big = F * std::max(nd, nz) * N;
-  PALLOC(p->What, F * nd * N);
-  PALLOC(p->Vh, F * nz * N);
-  PALLOC(p->w1, big);
-  PALLOC(p->w2, big);
+  const size_t esz = p->prec ? sizeof(z32) : sizeof(z64);
+  {
+    fl_status s;
+    if ((s = dalloc_bytes(p, &p->What, (size_t)(F * nd * N) * esz)) != FL_OK) return bail(s);
+    if ((s = dalloc_bytes(p, &p->Vh, (size_t)(F * nz * N) * esz)) != FL_OK) return bail(s);
+    // the work arrays also serve fl_forward, which runs in FP64
+    if ((s = dalloc_bytes(p, &p->w1, (size_t)big * sizeof(z64))) != FL_OK) return bail(s);
+    if ((s = dalloc_bytes(p, &p->w2, (size_t)big * sizeof(z64))) != FL_OK) return bail(s);
+  }
+  if (p->prec) PALLOC(p->ktab32, F * 2 * nz * N);
   const long nvox = (long)nx * ny * nz;
   PALLOC(p->vX, F * nvox);
   PALLOC(p->u, F * nvox);
   PALLOC(p->u0w, F * nvox);
-  PALLOC(p->Ww, F * nd * N);
   PALLOC(p->wn2, FN);
   PALLOC(p->flag, FN);
   p->nb_scan = (int)nblk(FN, 1024);
@@ -468,6 +603,13 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
 #undef PALLOC
   fl_status s = build_tables(p);
   if (s != FL_OK) return bail(s);
+  if (p->prec) {
+    const long nk = F * 2 * nz * N;
+    hipLaunchKernelGGL(k_narrow, dim3(nblk(nk, 256)), dim3(256), 0, p->st, p->ktab, p->ktab32, nk);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+    if (e != hipSuccess) return bail(fail(FL_EDEVICE, "table narrowing: %s", hipGetErrorString(e)));
+  }
   *out = p;
   return FL_OK;
 }
@@ -534,105 +676,8 @@ fl_status fl_invert(fl_plan* p, const void* W, const void* u0, double delta, voi
   if (!p) return fail(FL_EINVAL, "NULL plan");
   if (!W || !u0 || !xi_out) return fail(FL_EINVAL, "NULL array argument");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
-  hipStream_t st = p->st;
-  const long N = p->N;
-  const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
-  const long nvox = (long)nx * ny * nz;
-  RUN(mark(p, FL_STAGE_NORM));
-  // noise thresholds: thr2[f] = (tau delta ||W_f||)^2
-  {
-    dim3 g(256, F);
-    if (p->opts.input_dtype == 0)
-      hipLaunchKernelGGL(k_sumsq<double>, g, dim3(256), 0, st, (const z64*)W, (long)nd * N, p->partial);
-    else
-      hipLaunchKernelGGL(k_sumsq<float>, g, dim3(256), 0, st, (const z32*)W, (long)nd * N, p->partial);
-    LAUNCHCHK();
-    double td = p->opts.tau * delta;
-    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
-                       p->norm2);
-    LAUNCHCHK();
-  }
-  const z64* u0d = (const z64*)u0;
-  if (p->opts.input_dtype == 1) {
-    hipLaunchKernelGGL(k_widen<float>, dim3(nblk(F * nvox, 256)), dim3(256), 0, st, (const z32*)u0,
-                       p->u0w, (long)F * nvox);
-    LAUNCHCHK();
-    u0d = p->u0w;
-  }
-  // (a) FFT2 of W: rows, then columns -> W^ plane-major [F][nd][py][px]
-  {
-    RUN(mark(p, FL_STAGE_FFT_ROWS));
-    FftArgs g = rows_args(W, p->w1, p->tw_x, px, (long)F * nd * py);
-    if (p->opts.input_dtype == 0)
-      RUN((run_fft<double, double, double, -1>(g, st)));
-    else
-      RUN((run_fft<float, double, double, -1>(g, st)));
-    RUN(mark(p, FL_STAGE_FFT_COLS));
-    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
-  }
-  // (b) regularized solves of the active systems -> v^ plane-major
-  RUN(solve_systems(p, delta));
-  // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
-  {
-    RUN(mark(p, FL_STAGE_IFFT_COLS));
-    FftArgs g = cols_args(p->Vh, p->w1, p->tw_y, py, px, F * nz);
-    g.lout = ny;
-    g.out_off = p->oy;
-    g.out_sp = (long)ny * px;
-    RUN((run_fft<double, double, double, 1>(g, st)));
-    int CB = pick_cb(px, sizeof(z64));
-    long rows = (long)F * nz * ny;
-    size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(z64);
-    RUN(mark(p, FL_STAGE_CROP_PAD));
-    hipLaunchKernelGGL(k_rows_crop_pad<double>, dim3(nblk(rows, CB)), dim3(256), lds, st, p->w1, p->vX,
-                       p->w2, p->tw_x, px, nx, p->ox, (int)rows, 1.0 / (double)N, CB);
-    LAUNCHCHK();
-    FftArgs c = cols_args(p->w2, p->w1, p->tw_y, py, px, F * nz);
-    c.lin = ny;
-    c.in_sp = (long)ny * px;
-    RUN(mark(p, FL_STAGE_CONV_COLS));
-    RUN((run_fft<double, double, double, -1>(c, st)));
-    FftArgs z{};
-    z.in = p->w1;
-    z.out = p->w1;
-    z.tw = p->tw_z;
-    z.L = 2 * nz;
-    z.lin = nz;
-    z.lout = nz;
-    z.in_sk = N;
-    z.in_sb = 1;
-    z.in_sp = (long)nz * N;
-    z.out_sk = N;
-    z.out_sb = 1;
-    z.out_sp = (long)nz * N;
-    z.B = (int)N;
-    z.planes = F;
-    z.scale = 1.0;
-    int CBz = pick_cb(2 * nz, sizeof(z64));
-    size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(z64);
-    RUN(mark(p, FL_STAGE_CONV_Z));
-    hipLaunchKernelGGL(k_fft_conv<double>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, p->ktab,
-                       (long)N, (long)2 * nz * N, CBz);
-    LAUNCHCHK();
-    FftArgs b = cols_args(p->w1, p->w2, p->tw_y, py, px, F * nz);
-    b.lout = ny;
-    b.out_sp = (long)ny * px;
-    RUN(mark(p, FL_STAGE_CONV_ICOLS));
-    RUN((run_fft<double, double, double, 1>(b, st)));
-    FftArgs r = rows_args(p->w2, p->u, p->tw_x, px, rows);
-    r.lout = nx;
-    r.out_sb = nx;
-    r.add = u0d;
-    RUN(mark(p, FL_STAGE_CONV_IROWS));
-    RUN((run_fft<double, double, double, 1>(r, st)));
-  }
-  // (d) xi
-  RUN(mark(p, FL_STAGE_XI));
-  hipLaunchKernelGGL(k_xi, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->u, p->vX, nvox, F,
-                     p->opts.combine, (z64*)xi_out);
-  LAUNCHCHK();
-  RUN(mark(p, -1));
-  return FL_OK;
+  return p->prec ? invert_impl<float>(p, W, u0, delta, xi_out)
+                 : invert_impl<double>(p, W, u0, delta, xi_out);
 }
 
 fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, int maxit,
@@ -646,24 +691,26 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, px = p->px, py = p->py;
   const long nvox = (long)p->nx * p->ny * nz;
-  hipLaunchKernelGGL(k_zero<double>, dim3(nblk((long)F * nz * N, 256)), dim3(256), 0, st, p->w1,
+  z64* w1 = (z64*)p->w1;
+  z64* w2 = (z64*)p->w2;
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk((long)F * nz * N, 256)), dim3(256), 0, st, w1,
                      (long)F * nz * N);
   LAUNCHCHK();
   if (p->opts.input_dtype == 0)
     hipLaunchKernelGGL((k_current<double, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
-                       (const z64*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, p->w1);
+                       (const z64*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, w1);
   else
     hipLaunchKernelGGL((k_current<float, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
-                       (const z32*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, p->w1);
+                       (const z32*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, w1);
   LAUNCHCHK();
-  RUN((run_fft<double, double, double, -1>(rows_args(p->w1, p->w1, p->tw_x, px, (long)F * nz * py), st)));
-  RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->w1, p->tw_y, py, px, F * nz), st)));
+  RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
+  RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));
   hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
-                     p->w1, nd, nz, N, F, p->w2);
+                     w1, nd, nz, N, F, w2);
   LAUNCHCHK();
-  FftArgs c = cols_args(p->w2, p->w2, p->tw_y, py, px, F * nd);
+  FftArgs c = cols_args(w2, w2, p->tw_y, py, px, F * nd);
   RUN((run_fft<double, double, double, 1>(c, st)));
-  FftArgs r = rows_args(p->w2, W_out, p->tw_x, px, (long)F * nd * py);
+  FftArgs r = rows_args(w2, W_out, p->tw_x, px, (long)F * nd * py);
   r.scale = 1.0 / (double)N;
   RUN((run_fft<double, double, double, 1>(r, st)));
   return FL_OK;
@@ -676,8 +723,8 @@ fl_status fl_debug_read(fl_plan* p, int tap, void* dst, size_t bytes) {
   const void* src = nullptr;
   size_t need = 0;
   switch (tap) {
-    case FL_TAP_WHAT: src = p->What; need = F * p->nd * N * sizeof(z64); break;
-    case FL_TAP_VHAT: src = p->Vh; need = F * p->nz * N * sizeof(z64); break;
+    case FL_TAP_WHAT: src = p->What; need = F * p->nd * N * (p->prec ? sizeof(z32) : sizeof(z64)); break;
+    case FL_TAP_VHAT: src = p->Vh; need = F * p->nz * N * (p->prec ? sizeof(z32) : sizeof(z64)); break;
     case FL_TAP_V: src = p->vX; need = F * nvox * sizeof(z64); break;
     case FL_TAP_U: src = p->u; need = F * nvox * sizeof(z64); break;
     case FL_TAP_ALPHA: src = p->alpha; need = F * N * sizeof(double); break;

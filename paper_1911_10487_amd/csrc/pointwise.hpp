@@ -109,6 +109,12 @@ __global__ __launch_bounds__(256) void k_zero(cx<T>* __restrict__ p, long n) {
   if (i < n) p[i] = mk((T)0, (T)0);
 }
 
+__global__ __launch_bounds__(256) void k_narrow(const z64* __restrict__ in, z32* __restrict__ out,
+                                                long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cast<float>(in[i]);
+}
+
 template <typename TI>
 __global__ __launch_bounds__(256) void k_widen(const cx<TI>* __restrict__ in, z64* __restrict__ out,
                                                long n) {

@@ -334,9 +334,9 @@ __device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB], z64 (&qr)[NA],
   }
 }
 
-template <int TR, int TC, int NA, int NB>
+template <int TR, int TC, int NA, int NB, typename TW>
 __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys, int tpitch,
-                                                   const z64* __restrict__ What, long N,
+                                                   const cx<TW>* __restrict__ What, long N,
                                                    const int* __restrict__ list,
                                                    const int* __restrict__ count, int chunk0, int C,
                                                    BidiagOut o) {
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys,
     for (int a = 0; a < NA; ++a) {
       qr[a] = mk(0.0, 0.0);
       if (c == 0) {
-        qr[a] = What[((long)f * n + r + TR * a) * N + m];
+        qr[a] = cast<double>(What[((long)f * n + r + TR * a) * N + m]);
         wq += nrm2(qr[a]);
       }
     }
@@ -441,7 +441,8 @@ struct DpArgs {
   double eta;
   const z64* refl;     // [C][n][n] right reflectors
   const double* gam;   // [C][n]
-  z64* Vh;             // [F][n][N] output, plane-major
+  void* Vh;            // [F][n][N] output, plane-major (complex64 or complex128)
+  int vh_single;       // 1: Vh holds complex64
   double* alpha;       // [F*N]
   signed char* branch; // [F*N]
 };
@@ -456,7 +457,7 @@ __device__ __forceinline__ double phi_fwd(const double* __restrict__ d, const do
   double D = d[0] * d[0] + e[0] * e[0] + alpha;
   double Dp = 1.0;
   z64 z = q[0], zp = mk(0.0, 0.0);
-  double rD = 1.0 / D;
+  double rD = rcp_nr(D);
   double gp = -nrm2(z) * Dp * rD * rD;
   for (int i = 1; i < n; ++i) {
     const double b = e[i - 1] * d[i];
@@ -471,7 +472,7 @@ __device__ __forceinline__ double phi_fwd(const double* __restrict__ d, const do
     Dp = Dpn;
     z = zn;
     zp = zpn;
-    rD = 1.0 / D;
+    rD = rcp_nr(D);
     gp += 2.0 * (z.x * zp.x + z.y * zp.y) * rD - nrm2(z) * Dp * rD * rD;
   }
   return -alpha * alpha * gp;
@@ -487,9 +488,11 @@ __device__ void elden_solve(const double* __restrict__ d, const double* __restri
   for (int i = 0; i < n; ++i) {
     const double di = d[i];
     const z64 qi = q[i];
-    const double p = sqrt(di * di + mt * mt);
-    const double cs = p > 0.0 ? di / p : 1.0;
-    const double sn = p > 0.0 ? mt / p : 0.0;
+    const double p2s = di * di + mt * mt;
+    const double ip = p2s > 0.0 ? rsq_nr(p2s) : 0.0;
+    const double p = p2s * ip;
+    const double cs = p2s > 0.0 ? di * ip : 1.0;
+    const double sn = mt * ip;
     rho[i] = p;
     rr[i] = cs * qi + sn * g;
     const z64 gp = (-sn) * qi + cs * g;
@@ -497,9 +500,10 @@ __device__ void elden_solve(const double* __restrict__ d, const double* __restri
       const double ei = e[i];
       off[i] = cs * ei;
       const double fz = -sn * ei;
-      const double p2 = sqrt(mu * mu + fz * fz);
-      mt = p2;
-      g = (p2 > 0.0 ? fz / p2 : 0.0) * gp;
+      const double q2 = mu * mu + fz * fz;
+      const double iq = q2 > 0.0 ? rsq_nr(q2) : 0.0;
+      mt = q2 * iq;
+      g = (fz * iq) * gp;
     }
   }
   z64 yn = mk(0.0, 0.0);
@@ -507,7 +511,8 @@ __device__ void elden_solve(const double* __restrict__ d, const double* __restri
     z64 t = rr[i];
     if (i < n - 1) t = t - off[i] * yn;
     const double p = rho[i];
-    const z64 yi = p > 0.0 ? mk(t.x / p, t.y / p) : mk(0.0, 0.0);
+    const double ip = p > 0.0 ? rcp_nr(p) : 0.0;
+    const z64 yi = mk(t.x * ip, t.y * ip);
     y[i] = yi;
     yn = yi;
   }
@@ -544,16 +549,19 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       z64 drc = mk(1.0, 0.0);
       for (int i = 0; i < n; ++i) {
         const z64 t = sy[i] * drc;
-        const double at = sqrt(nrm2(t));
-        const z64 dl = at > 0.0 ? mk(t.x / at, t.y / at) : mk(1.0, 0.0);
+        const double t2 = nrm2(t);
+        const double it = t2 > 0.0 ? rsq_nr(t2) : 0.0;
+        const double at = t2 * it;
+        const z64 dl = t2 > 0.0 ? mk(t.x * it, t.y * it) : mk(1.0, 0.0);
         sd[i] = at;
         sdr[i] = drc;
         sq[i] = cmulc(dl, sq[i]);
         if (i < n - 1) {
           const z64 s = cmulc(dl, srr[i]);
-          const double as = sqrt(nrm2(s));
-          se[i] = as;
-          drc = as > 0.0 ? mk(s.x / as, -s.y / as) : mk(1.0, 0.0);
+          const double s2 = nrm2(s);
+          const double is = s2 > 0.0 ? rsq_nr(s2) : 0.0;
+          se[i] = s2 * is;
+          drc = s2 > 0.0 ? mk(s.x * is, -s.y * is) : mk(1.0, 0.0);
         } else {
           se[i] = 0.0;
         }
@@ -635,9 +643,16 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       y0 = y0 - v0 * s;
       y1 = y1 - v1 * s;
     }
-    z64* out = a.Vh + (long)f * n * a.N + m;
-    if (lane < n) out[(long)lane * a.N] = y0;
-    if (lane + 64 < n) out[(long)(lane + 64) * a.N] = y1;
+    const long o0 = (long)f * n * a.N + m;
+    if (a.vh_single) {
+      z32* out = (z32*)a.Vh + o0;
+      if (lane < n) out[(long)lane * a.N] = cast<float>(y0);
+      if (lane + 64 < n) out[(long)(lane + 64) * a.N] = cast<float>(y1);
+    } else {
+      z64* out = (z64*)a.Vh + o0;
+      if (lane < n) out[(long)lane * a.N] = y0;
+      if (lane + 64 < n) out[(long)(lane + 64) * a.N] = y1;
+    }
     if (lane == 0) {
       a.alpha[fm] = al;
       a.branch[fm] = br;

@@ -57,9 +57,10 @@ def gpu_run(p, W, u0, delta, **kw):
     xi = plan.invert(Wt, ut, delta)
     torch.cuda.synchronize()
     F, N = p.n_omega, p.px * p.py
+    cw = np.complex64 if kw.get("precision", 0) == 1 else np.complex128
     st = {
-        "What": plan.tap(TAP_WHAT, np.complex128, (F, p.nd, p.py, p.px)),
-        "Vhat": plan.tap(TAP_VHAT, np.complex128, (F, p.nz, p.py, p.px)),
+        "What": plan.tap(TAP_WHAT, cw, (F, p.nd, p.py, p.px)),
+        "Vhat": plan.tap(TAP_VHAT, cw, (F, p.nz, p.py, p.px)),
         "v": plan.tap(TAP_V, np.complex128, (F, p.nz, p.ny, p.nx)),
         "u": plan.tap(TAP_U, np.complex128, (F, p.nz, p.ny, p.nx)),
         "alpha": plan.tap(TAP_ALPHA, np.float64, (F, N)),
@@ -200,3 +201,49 @@ def test_single_workload_full_size_matches_oracle():
     ref_xi, ref = invert.invert(p, Wd, u0, 0.01, stages=True)
     xi_g, st = gpu_run(p, Wd, u0, 0.01)
     compare(p, ref_xi, ref, xi_g, st)
+
+
+# ---------------------------------------------------------------- mixed
+# FP32 FFTs, convolution and storage; FP64 regularized solve and division.
+# Gate: relative L2 <= 1e-4 on xi; the errors of every stage are stated.
+MIXED_TOL = 1e-4
+
+
+def mixed_errors(ref_xi, ref, xi, st):
+    return {"What": rel(st["What"], ref["What"]), "Vhat": rel(st["Vhat"], ref["Vhat"]),
+            "v": rel(st["v"], ref["v"]), "u": rel(st["u"], ref["u"]), "xi": rel(xi, ref_xi)}
+
+
+def test_mixed_small_workload(small):
+    p, xi_true, u0, W = small
+    Wd = synth.add_noise(p, W, 0.01)
+    ref_xi, ref = invert.invert(p, Wd, u0, 0.01, stages=True)
+    xi, st = gpu_run(p, Wd, u0, 0.01, precision=1)
+    e = mixed_errors(ref_xi, ref, xi, st)
+    say("mixed small errors", e)
+    assert e["xi"] <= MIXED_TOL and e["u"] <= MIXED_TOL and e["v"] <= MIXED_TOL
+
+
+def test_mixed_ragged_two_frequency():
+    p, u0, W = _ragged()
+    Wd = synth.add_noise(p, W, 0.02)
+    ref_xi, ref = invert.invert(p, Wd, u0, 0.02, stages=True)
+    xi, st = gpu_run(p, Wd, u0, 0.02, precision=1)
+    e = mixed_errors(ref_xi, ref, xi, st)
+    say("mixed ragged errors", e)
+    assert e["xi"] <= MIXED_TOL
+
+
+@pytest.mark.slow
+def test_mixed_single_workload_full_size():
+    p = synth.workload("single")[0]
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, U, V, info = forward.synthesize(p, xi, u0, born=True)
+    Wd = synth.add_noise(p, W, 0.01)
+    say("oracle single full size (mixed)")
+    ref_xi, ref = invert.invert(p, Wd, u0, 0.01, stages=True)
+    xi_g, st = gpu_run(p, Wd, u0, 0.01, precision=1)
+    e = mixed_errors(ref_xi, ref, xi_g, st)
+    say("mixed single errors", e)
+    assert e["xi"] <= MIXED_TOL
