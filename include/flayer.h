@@ -113,6 +113,31 @@ fl_status fl_invert(fl_plan *plan, const void *W, const void *u0, double delta,
                     void *xi_out);
 
 /*
+ * Reverse derivative (vector-Jacobian product) of xi = invert(W, u0):
+ * given the xi cotangent grad_xi ([nz][ny][nx] complex128, the gradient of a
+ * real loss as dL/dRe + i dL/dIm), write grad_W ([n_omega][nd][py][px]
+ * complex128) and, if grad_u0 is not NULL, grad_u0 ([n_omega][nz][ny][nx]
+ * complex128), with <grad_W, dW> = Re sum conj(grad_W) dW the directional
+ * derivative. Hand-written adjoint of every stage: the transposed FFTs, the
+ * adjoint of the volume convolution, the adjoint Tikhonov solve reusing the
+ * forward factorization, the implicit derivative of the discrepancy-chosen
+ * alpha (including the dependence of delta_m on ||W||). Runs the forward
+ * first (same inputs as fl_invert). Errors: FL_EINVAL, FL_EUNSUPPORTED
+ * (combine = 1, or more systems than the plan's factorization workspace
+ * holds), FL_EDEVICE.
+ */
+fl_status fl_invert_vjp(fl_plan *plan, const void *W, const void *u0, double delta,
+                        const void *grad_xi, void *grad_W, void *grad_u0);
+
+/*
+ * Tangent (Jacobian-vector product): dxi ([nz][ny][nx] complex128) for the
+ * data tangent dW (same layout and element type as W), u0 held fixed.
+ * Same errors as fl_invert_vjp.
+ */
+fl_status fl_invert_jvp(fl_plan *plan, const void *W, const void *u0, double delta,
+                        const void *dW, void *dxi);
+
+/*
  * Synthetic data (the role of Algorithm 1, Section 3): v = xi u in X, then
  * W = omega^2 G * v on the data planes (eq. 7, second line) over the torus.
  * maxit = 0 takes u = u0 (Born data); maxit > 0 is reserved for the

@@ -1,0 +1,335 @@
+// Reverse (VJP) and tangent (JVP) derivatives of the inversion map W -> xi.
+//
+// Per solved system (M = A^H A + alpha I, v^ = M^-1 A^H w):
+//   VJP  w^bar = A M^-1 v^bar, and for a discrepancy-chosen alpha the
+//        implicit term w^bar -= (s / phi_a) q, Tbar += s / phi_a with
+//        s = -Re(v^bar^H M^-1 v^), phi_a = 2 alpha v^H M^-1 v^,
+//        q = 2 (-alpha A M^-1 v^ - r), r = A v^ - w;
+//   JVP  alpha' = (T' - Re(q^H w')) / phi_a, v^' = M^-1 (A^H w' - alpha' v^).
+// M^-1 is applied through the forward factorization: A = U D_L B' D_R^H V^H
+// (Householder reflectors V, phases D_R, real bidiagonal B'), so
+// M^-1 x = V D_R (B'^T B' + alpha I)^-1 D_R^H V^H x, and the tridiagonal
+// solve uses R^T R = B'^T B' + alpha I from the Givens QR of [B'; sqrt(alpha) I].
+// A and A^H are applied directly from the system's Toeplitz table row.
+#pragma once
+#include "common.hpp"
+
+namespace fl {
+
+struct AdjArgs {
+  const z64* gsys;      // [F][N][tpitch] Toeplitz table rows
+  int tpitch;
+  const int* list;
+  const int* count;
+  int C, n;
+  long N;
+  const double* alpha;  // [F*N]
+  const signed char* branch;
+  const double* bd_d;   // [C][n] real bidiagonal and phases from the forward
+  const double* bd_e;
+  const z64* bd_dr;
+  const z64* refl;      // [C][n][n]
+  const double* gam;    // [C][n]
+  const void* What;     // [F][n][N] forward W^ (complex64 or complex128)
+  const void* Vh;       // [F][n][N] forward v^
+  const void* X;        // VJP: v^bar [F][n][N]; JVP: W^' [F][n][N]
+  int single;           // 1: What, Vh, X hold complex64
+  const double* Tdot;   // JVP: per frequency T'
+  void* Y;              // VJP: w^bar [F][n][N] complex128; JVP: v^' (type of Vh)
+  double* cm;           // VJP: [F*N] implicit-alpha coefficients s / phi_a
+};
+
+template <typename T>
+__device__ __forceinline__ z64 ld(const void* p, long i) {
+  return cast<double>(((const cx<T>*)p)[i]);
+}
+
+__device__ __forceinline__ z64 ldx(const void* p, long i, int single) {
+  return single ? ld<float>(p, i) : ld<double>(p, i);
+}
+
+// complex dot conj(a) . b over the wave's two-slot distribution
+__device__ __forceinline__ z64 wdot(z64 a0, z64 a1, z64 b0, z64 b1) {
+  z64 s = cmulc(a0, b0);
+  s = cfmac(s, a1, b1);
+  s.x = lanes_sum<64>(s.x);
+  s.y = lanes_sum<64>(s.y);
+  return s;
+}
+
+template <int NMAX>
+struct AdjShared {
+  z64 t[2 * NMAX];
+  z64 vec[NMAX];
+  double d[NMAX], e[NMAX], irho[NMAX], off[NMAX];
+  z64 dr[NMAX];
+};
+
+// y = M^-1 x for the wave-distributed x (entries lane, lane + 64)
+template <int NMAX>
+__device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64& x1) {
+  const int n = a.n, lane = threadIdx.x;
+  const z64* R = a.refl + (long)sl * n * n;
+  const double* G = a.gam + (long)sl * n;
+  // z = V^H x = P_{n-3} ... P_0 x
+  for (int k = 0; k <= n - 3; ++k) {
+    const double g = G[k];
+    const z64 v0 = (lane > k && lane < n) ? R[(long)k * n + lane] : mk(0.0, 0.0);
+    const z64 v1 = (lane + 64 > k && lane + 64 < n) ? R[(long)k * n + lane + 64] : mk(0.0, 0.0);
+    const z64 s = g * wdot(v0, v1, x0, x1);
+    x0 = x0 - v0 * s;
+    x1 = x1 - v1 * s;
+  }
+  // D_R^H, then (R^T R)^-1 sequentially on lane 0
+  if (lane < n) S.vec[lane] = cmulc(S.dr[lane], x0);
+  if (lane + 64 < n) S.vec[lane + 64] = cmulc(S.dr[lane + 64], x1);
+  __syncthreads();
+  if (lane == 0) {
+    z64 tp = mk(0.0, 0.0);
+    for (int i = 0; i < n; ++i) {  // R^T t = z
+      z64 t = S.vec[i];
+      if (i > 0) t = t - S.off[i - 1] * tp;
+      t = S.irho[i] * t;
+      S.vec[i] = t;
+      tp = t;
+    }
+    z64 yn = mk(0.0, 0.0);
+    for (int i = n - 1; i >= 0; --i) {  // R y = t
+      z64 y = S.vec[i];
+      if (i < n - 1) y = y - S.off[i] * yn;
+      y = S.irho[i] * y;
+      S.vec[i] = y;
+      yn = y;
+    }
+  }
+  __syncthreads();
+  x0 = lane < n ? S.dr[lane] * S.vec[lane] : mk(0.0, 0.0);
+  x1 = lane + 64 < n ? S.dr[lane + 64] * S.vec[lane + 64] : mk(0.0, 0.0);
+  __syncthreads();
+  // V y = P_0 (P_1 (... P_{n-3} y))
+  for (int k = n - 3; k >= 0; --k) {
+    const double g = G[k];
+    const z64 v0 = (lane > k && lane < n) ? R[(long)k * n + lane] : mk(0.0, 0.0);
+    const z64 v1 = (lane + 64 > k && lane + 64 < n) ? R[(long)k * n + lane + 64] : mk(0.0, 0.0);
+    const z64 s = g * wdot(v0, v1, x0, x1);
+    x0 = x0 - v0 * s;
+    x1 = x1 - v1 * s;
+  }
+}
+
+// (A x)_j = sum_l t[j - l + n - 1] x_l, or (A^H x)_l = sum_j conj(t[j - l + n - 1]) x_j
+template <int NMAX, bool HERM>
+__device__ void toeplitz(AdjShared<NMAX>& S, int n, z64& x0, z64& x1) {
+  const int lane = threadIdx.x;
+  if (lane < n) S.vec[lane] = x0;
+  if (lane + 64 < n) S.vec[lane + 64] = x1;
+  __syncthreads();
+  z64 o[2] = {mk(0.0, 0.0), mk(0.0, 0.0)};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = lane + 64 * h;
+    if (j < n) {
+      z64 acc = mk(0.0, 0.0);
+      for (int l = 0; l < n; ++l) {
+        if (HERM)
+          acc = cfmac(acc, S.t[l - j + n - 1], S.vec[l]);
+        else
+          acc = cfma(acc, S.t[j - l + n - 1], S.vec[l]);
+      }
+      o[h] = acc;
+    }
+  }
+  __syncthreads();
+  x0 = o[0];
+  x1 = o[1];
+}
+
+// MODE 0: VJP, MODE 1: JVP. One single-wave workgroup per solved system.
+template <int NMAX, int MODE>
+__global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
+  __shared__ AdjShared<NMAX> S;
+  const int lane = threadIdx.x;
+  const int n = a.n;
+  const int total = *a.count;
+  for (int sl = blockIdx.x; sl < a.C && sl < total; sl += gridDim.x) {
+    const int fm = a.list[sl];
+    const int f = (int)(fm / a.N);
+    const long m = fm - (long)f * a.N;
+    const double al = a.alpha[fm];
+    const bool root = a.branch[fm] == 2;
+    const z64* trow = a.gsys + ((long)f * a.N + m) * a.tpitch;
+    for (int i = lane; i < 2 * n - 1; i += 64) S.t[i] = trow[i];
+    for (int i = lane; i < n; i += 64) {
+      S.d[i] = a.bd_d[(long)sl * n + i];
+      S.e[i] = a.bd_e[(long)sl * n + i];
+      S.dr[i] = a.bd_dr[(long)sl * n + i];
+    }
+    __syncthreads();
+    if (lane == 0) {
+      // R of the Givens QR of [B'; sqrt(alpha) I] (rhs not needed)
+      const double mu = sqrt(al);
+      double mt = mu;
+      for (int i = 0; i < n; ++i) {
+        const double di = S.d[i];
+        const double p2 = di * di + mt * mt;
+        const double ip = p2 > 0.0 ? rsq_nr(p2) : 0.0;
+        S.irho[i] = ip;
+        if (i < n - 1) {
+          const double cs = p2 > 0.0 ? di * ip : 1.0;
+          const double sn = mt * ip;
+          S.off[i] = cs * S.e[i];
+          const double fz = -sn * S.e[i];
+          const double q2 = mu * mu + fz * fz;
+          mt = q2 > 0.0 ? q2 * rsq_nr(q2) : 0.0;
+        }
+      }
+    }
+    __syncthreads();
+    const long base = (long)f * n * a.N + m;
+    auto at = [&](const void* p, int i) { return i < n ? ldx(p, base + (long)i * a.N, a.single) : mk(0.0, 0.0); };
+    const z64 vh0 = at(a.Vh, lane), vh1 = at(a.Vh, lane + 64);
+    const z64 w0 = at(a.What, lane), w1 = at(a.What, lane + 64);
+    const z64 x0i = at(a.X, lane), x1i = at(a.X, lane + 64);
+    // pieces of the implicit alpha derivative
+    z64 q0 = mk(0.0, 0.0), q1 = mk(0.0, 0.0);
+    double phia = 1.0, sx2 = 0.0;
+    if (root) {
+      z64 m0 = vh0, m1 = vh1;
+      minv<NMAX>(a, S, sl, m0, m1);                   // x2 = M^-1 v^
+      phia = 2.0 * al * wdot(vh0, vh1, m0, m1).x;
+      if (MODE == 0) sx2 = -wdot(x0i, x1i, m0, m1).x; // s = -Re(v^bar^H x2)
+      z64 a0 = m0, a1 = m1;
+      toeplitz<NMAX, false>(S, n, a0, a1);            // A x2
+      z64 r0 = vh0, r1 = vh1;
+      toeplitz<NMAX, false>(S, n, r0, r1);            // A v^
+      r0 = r0 - w0;
+      r1 = r1 - w1;
+      q0 = 2.0 * ((-al) * a0 - r0);
+      q1 = 2.0 * ((-al) * a1 - r1);
+    }
+    if (MODE == 0) {
+      z64 y0 = x0i, y1 = x1i;
+      minv<NMAX>(a, S, sl, y0, y1);
+      toeplitz<NMAX, false>(S, n, y0, y1);            // A M^-1 v^bar
+      double c = 0.0;
+      if (root) {
+        c = sx2 / phia;
+        y0 = y0 - c * q0;
+        y1 = y1 - c * q1;
+      }
+      z64* out = (z64*)a.Y + base;
+      if (lane < n) out[(long)lane * a.N] = y0;
+      if (lane + 64 < n) out[(long)(lane + 64) * a.N] = y1;
+      if (lane == 0) a.cm[fm] = c;
+    } else {
+      z64 b0 = x0i, b1 = x1i;
+      toeplitz<NMAX, true>(S, n, b0, b1);             // A^H w'
+      if (root) {
+        const double ad = (a.Tdot[f] - wdot(q0, q1, x0i, x1i).x) / phia;
+        b0 = b0 - ad * vh0;
+        b1 = b1 - ad * vh1;
+      }
+      minv<NMAX>(a, S, sl, b0, b1);
+      if (a.single) {
+        z32* out = (z32*)a.Y + base;
+        if (lane < n) out[(long)lane * a.N] = cast<float>(b0);
+        if (lane + 64 < n) out[(long)(lane + 64) * a.N] = cast<float>(b1);
+      } else {
+        z64* out = (z64*)a.Y + base;
+        if (lane < n) out[(long)lane * a.N] = b0;
+        if (lane + 64 < n) out[(long)(lane + 64) * a.N] = b1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// (d) reversed: vbar_f = g u_f / den, ubar_f = (conj(g)(v_f - xi u_f) - g conj(xi) u_f) / den
+__global__ __launch_bounds__(256) void k_xi_vjp(const z64* __restrict__ g, const z64* __restrict__ xi,
+                                                const z64* __restrict__ u, const z64* __restrict__ v,
+                                                long nvox, int F, z64* __restrict__ vbar,
+                                                z64* __restrict__ ubar) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox) return;
+  double den = 0.0;
+  for (int f = 0; f < F; ++f) den += nrm2(u[(long)f * nvox + i]);
+  const double inv = den > 0.0 ? 1.0 / den : 0.0;
+  const z64 gg = g[i], x = xi[i];
+  for (int f = 0; f < F; ++f) {
+    const z64 uu = u[(long)f * nvox + i], vv = v[(long)f * nvox + i];
+    vbar[(long)f * nvox + i] = inv * (gg * uu);
+    const z64 t = cj(gg) * (vv - x * uu) - gg * (cj(x) * uu);
+    ubar[(long)f * nvox + i] = inv * t;
+  }
+}
+
+// (d) tangent: xi' = sum_f [conj(u) v' + conj(u')(v - xi u) - xi conj(u) u'] / den
+__global__ __launch_bounds__(256) void k_xi_jvp(const z64* __restrict__ xi, const z64* __restrict__ u,
+                                                const z64* __restrict__ v, const z64* __restrict__ vd,
+                                                const z64* __restrict__ ud, long nvox, int F,
+                                                z64* __restrict__ out) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox) return;
+  double den = 0.0;
+  z64 acc = mk(0.0, 0.0);
+  const z64 x = xi[i];
+  for (int f = 0; f < F; ++f) {
+    const long o = (long)f * nvox + i;
+    const z64 uu = u[o], vv = v[o], dv = vd[o], du = ud[o];
+    den += nrm2(uu);
+    acc = acc + cmulc(uu, dv) + cmulc(du, vv - x * uu) - x * cmulc(uu, du);
+  }
+  out[i] = den > 0.0 ? (1.0 / den) * acc : mk(0.0, 0.0);
+}
+
+// Tbar[f] = sum_m cm[f * N + m] (fixed order), one block per frequency
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ x, long N,
+                                                  double* __restrict__ out) {
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  double s = 0.0;
+  for (long i = threadIdx.x; i < N; i += blockDim.x) s += x[(long)f * N + i];
+  s = lanes_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[f] = red[0] + red[1] + red[2] + red[3];
+}
+
+// gW[f] += c * Tbar[f] * W[f]
+template <typename TI>
+__global__ __launch_bounds__(256) void k_add_noise_term(z64* __restrict__ gW, const cx<TI>* __restrict__ W,
+                                                        const double* __restrict__ Tbar, double c,
+                                                        long per_f, int F) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per_f * F) return;
+  const int f = (int)(i / per_f);
+  gW[i] = gW[i] + (c * Tbar[f]) * cast<double>(W[i]);
+}
+
+// per-frequency partial sums of Re(conj(a) b): grid (nb, F)
+template <typename TI>
+__global__ __launch_bounds__(256) void k_dotre(const cx<TI>* __restrict__ a, const cx<TI>* __restrict__ b,
+                                               long per_f, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int f = blockIdx.y, nb = gridDim.x;
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per_f; i += (long)nb * blockDim.x) {
+    const cx<TI> x = a[(long)f * per_f + i], y = b[(long)f * per_f + i];
+    s += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+  }
+  s = lanes_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[f * nb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_finish_dot(const double* __restrict__ partial, int nb, int F, double c,
+                             double* __restrict__ out) {
+  for (int f = threadIdx.x; f < F; f += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[f * nb + b];
+    out[f] = c * s;
+  }
+}
+
+}  // namespace fl

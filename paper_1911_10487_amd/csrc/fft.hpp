@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_fft(FftArgs g, int CB) {
 // the 3D volume convolution, where b runs over horizontal wavenumbers.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_conv(FftArgs g, const void* mul, long mul_sk,
-                                                  long mul_sp, int CB) {
+                                                  long mul_sp, int CB, int conj_mul) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int LP = g.L + 1;
   cx<T>* a = (cx<T>*)smem;
@@ -242,7 +242,11 @@ __global__ __launch_bounds__(256) void k_fft_conv(FftArgs g, const void* mul, lo
   for (int t = tid; t < CB * g.L; t += nt) {
     int k = t / CB, bb = t - k * CB;
     int bg = b0 + bb;
-    if (bg < g.B) r[bb * LP + k] = r[bb * LP + k] * K[(long)k * mul_sk + bg];
+    if (bg < g.B) {
+      cx<T> kk = K[(long)k * mul_sk + bg];
+      if (conj_mul) kk.y = -kk.y;
+      r[bb * LP + k] = r[bb * LP + k] * kk;
+    }
   }
   __syncthreads();
   cx<T>* o = (r == a) ? b : a;

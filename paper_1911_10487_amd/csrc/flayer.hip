@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/flayer.h"
+#include "adjoint.hpp"
 #include "fft.hpp"
 #include "pointwise.hpp"
 #include "solver.hpp"
@@ -86,6 +87,13 @@ struct fl_plan {
   int C = 0;
   z64 *dg = nullptr, *sp = nullptr, *q = nullptr, *refl = nullptr;
   double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
+  double *bd_d = nullptr, *bd_e = nullptr;
+  z64* bd_dr = nullptr;
+  // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
+  bool has_adj = false;
+  z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;
+  void *Xb = nullptr, *Yb = nullptr;
+  double *cm = nullptr, *Tb = nullptr;
   double* alpha = nullptr;
   signed char* branch = nullptr;
   std::vector<void*> allocs;
@@ -331,6 +339,9 @@ fl_status solve_systems(fl_plan* p, double delta) {
   a.vh_single = sizeof(T) == 4;
   a.alpha = p->alpha;
   a.branch = p->branch;
+  a.bd_d = p->bd_d;
+  a.bd_e = p->bd_e;
+  a.bd_dr = p->bd_dr;
   const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
   const unsigned gd = (unsigned)std::min<long>(p->C, 8192);
   for (long c0 = 0; c0 < FN; c0 += p->C) {
@@ -345,6 +356,98 @@ fl_status solve_systems(fl_plan* p, double delta) {
     LAUNCHCHK();
   }
   return FL_OK;
+}
+
+template <typename T>
+struct Tw {
+  const cx<T>*x, *y, *z, *ktab;
+};
+
+template <typename T>
+Tw<T> twiddles_of(fl_plan* p) {
+  Tw<T> t;
+  t.x = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_x32 : (const void*)p->tw_x);
+  t.y = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_y32 : (const void*)p->tw_y);
+  t.z = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_z32 : (const void*)p->tw_z);
+  t.ktab = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->ktab32 : (const void*)p->ktab);
+  return t;
+}
+
+// Columns [F*nz][py][px] in w1 (rows 0..ny-1 significant, zero padded) ->
+// FFT along y -> FFT along z, product with the kernel transform (conjugated
+// for the adjoint), inverse along z -> inverse along y (rows 0..ny-1) ->
+// inverse along x (columns 0..nx-1) + addend -> out [F][nz][ny][nx].
+// in_rows: the padded x-transformed rows, [F*nz*ny][px], in w2.
+template <typename T>
+fl_status conv_tail(fl_plan* p, z64* out, const z64* add, int conj_mul) {
+  hipStream_t st = p->st;
+  const Tw<T> tw = twiddles_of<T>(p);
+  const long N = p->N;
+  const int F = p->F, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  FftArgs c = cols_args(p->w2, p->w1, tw.y, py, px, F * nz);
+  c.lin = ny;
+  c.in_sp = (long)ny * px;
+  RUN(mark(p, FL_STAGE_CONV_COLS));
+  RUN((run_fft<T, T, T, -1>(c, st)));
+  FftArgs z{};
+  z.in = p->w1;
+  z.out = p->w1;
+  z.tw = tw.z;
+  z.L = 2 * nz;
+  z.lin = nz;
+  z.lout = nz;
+  z.in_sk = N;
+  z.in_sb = 1;
+  z.in_sp = (long)nz * N;
+  z.out_sk = N;
+  z.out_sb = 1;
+  z.out_sp = (long)nz * N;
+  z.B = (int)N;
+  z.planes = F;
+  z.scale = 1.0;
+  int CBz = pick_cb(2 * nz, sizeof(cx<T>));
+  size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(cx<T>);
+  RUN(mark(p, FL_STAGE_CONV_Z));
+  hipLaunchKernelGGL(k_fft_conv<T>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, tw.ktab, (long)N,
+                     (long)2 * nz * N, CBz, conj_mul);
+  LAUNCHCHK();
+  FftArgs b = cols_args(p->w1, p->w2, tw.y, py, px, F * nz);
+  b.lout = ny;
+  b.out_sp = (long)ny * px;
+  RUN(mark(p, FL_STAGE_CONV_ICOLS));
+  RUN((run_fft<T, T, T, 1>(b, st)));
+  FftArgs r = rows_args(p->w2, out, tw.x, px, (long)F * nz * ny);
+  r.lout = nx;
+  r.out_sb = nx;
+  r.add = add;
+  RUN(mark(p, FL_STAGE_CONV_IROWS));
+  RUN((run_fft<T, T, double, 1>(r, st)));
+  return FL_OK;
+}
+
+// Stage (c) of the forward map: v = crop(IFFT2(Vin)) / N -> vout, then
+// uout = add + omega^2 K v.
+template <typename T>
+fl_status stage_c(fl_plan* p, const void* Vin, z64* vout, z64* uout, const z64* add) {
+  hipStream_t st = p->st;
+  const Tw<T> tw = twiddles_of<T>(p);
+  const long N = p->N;
+  const int F = p->F, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  RUN(mark(p, FL_STAGE_IFFT_COLS));
+  FftArgs g = cols_args(Vin, p->w1, tw.y, py, px, F * nz);
+  g.lout = ny;
+  g.out_off = p->oy;
+  g.out_sp = (long)ny * px;
+  RUN((run_fft<T, T, T, 1>(g, st)));
+  int CB = pick_cb(px, sizeof(cx<T>));
+  long rows = (long)F * nz * ny;
+  size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(cx<T>);
+  RUN(mark(p, FL_STAGE_CROP_PAD));
+  hipLaunchKernelGGL(k_rows_crop_pad<T>, dim3(nblk(rows, CB)), dim3(256), lds, st,
+                     (const cx<T>*)p->w1, vout, (cx<T>*)p->w2, tw.x, px, nx, p->ox, (int)rows,
+                     1.0 / (double)N, CB);
+  LAUNCHCHK();
+  return conv_tail<T>(p, uout, add, 0);
 }
 
 // The inversion launch sequence; T is the FFT / storage precision.
@@ -393,66 +496,188 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   // (b) regularized solves of the active systems -> v^ plane-major
   RUN(solve_systems<T>(p, delta));
   // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
-  {
-    RUN(mark(p, FL_STAGE_IFFT_COLS));
-    FftArgs g = cols_args(p->Vh, p->w1, twy, py, px, F * nz);
-    g.lout = ny;
-    g.out_off = p->oy;
-    g.out_sp = (long)ny * px;
-    RUN((run_fft<T, T, T, 1>(g, st)));
-    int CB = pick_cb(px, sizeof(cx<T>));
-    long rows = (long)F * nz * ny;
-    size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(cx<T>);
-    RUN(mark(p, FL_STAGE_CROP_PAD));
-    hipLaunchKernelGGL(k_rows_crop_pad<T>, dim3(nblk(rows, CB)), dim3(256), lds, st,
-                       (const cx<T>*)p->w1, p->vX, (cx<T>*)p->w2, twx, px, nx, p->ox, (int)rows,
-                       1.0 / (double)N, CB);
-    LAUNCHCHK();
-    FftArgs c = cols_args(p->w2, p->w1, twy, py, px, F * nz);
-    c.lin = ny;
-    c.in_sp = (long)ny * px;
-    RUN(mark(p, FL_STAGE_CONV_COLS));
-    RUN((run_fft<T, T, T, -1>(c, st)));
-    FftArgs z{};
-    z.in = p->w1;
-    z.out = p->w1;
-    z.tw = twz;
-    z.L = 2 * nz;
-    z.lin = nz;
-    z.lout = nz;
-    z.in_sk = N;
-    z.in_sb = 1;
-    z.in_sp = (long)nz * N;
-    z.out_sk = N;
-    z.out_sb = 1;
-    z.out_sp = (long)nz * N;
-    z.B = (int)N;
-    z.planes = F;
-    z.scale = 1.0;
-    int CBz = pick_cb(2 * nz, sizeof(cx<T>));
-    size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(cx<T>);
-    RUN(mark(p, FL_STAGE_CONV_Z));
-    hipLaunchKernelGGL(k_fft_conv<T>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, ktab, (long)N,
-                       (long)2 * nz * N, CBz);
-    LAUNCHCHK();
-    FftArgs b = cols_args(p->w1, p->w2, twy, py, px, F * nz);
-    b.lout = ny;
-    b.out_sp = (long)ny * px;
-    RUN(mark(p, FL_STAGE_CONV_ICOLS));
-    RUN((run_fft<T, T, T, 1>(b, st)));
-    FftArgs r = rows_args(p->w2, p->u, twx, px, rows);
-    r.lout = nx;
-    r.out_sb = nx;
-    r.add = u0d;
-    RUN(mark(p, FL_STAGE_CONV_IROWS));
-    RUN((run_fft<T, T, double, 1>(r, st)));
-  }
+  RUN(stage_c<T>(p, p->Vh, p->vX, p->u, u0d));
   // (d) xi, in FP64
   RUN(mark(p, FL_STAGE_XI));
   hipLaunchKernelGGL(k_xi, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->u, p->vX, nvox, F,
                      p->opts.combine, (z64*)xi_out);
   LAUNCHCHK();
   RUN(mark(p, -1));
+  return FL_OK;
+}
+
+// ------------------------------------------------------------ derivatives
+
+fl_status ensure_adjoint_buffers(fl_plan* p) {
+  if (p->has_adj) return FL_OK;
+  const long N = p->N, F = p->F;
+  const long nvox = (long)p->nx * p->ny * p->nz;
+  const size_t big = (size_t)(F * std::max(p->nd, p->nz) * N) * sizeof(z64);
+  ALLOC(p->xi_tmp, F * nvox);
+  ALLOC(p->vbar, F * nvox);
+  ALLOC(p->ubar, F * nvox);
+  ALLOC(p->vbar2, F * nvox);
+  RUN(dalloc_bytes(p, &p->Xb, big));
+  RUN(dalloc_bytes(p, &p->Yb, big));
+  ALLOC(p->cm, F * N);
+  ALLOC(p->Tb, F);
+  p->has_adj = true;
+  return FL_OK;
+}
+
+fl_status adjoint_preconditions(fl_plan* p) {
+  if (p->opts.combine != 0)
+    return fail(FL_EUNSUPPORTED, "derivatives are implemented for the least-squares xi (combine 0)");
+  if ((long)p->C < (long)p->F * p->N)
+    return fail(FL_EUNSUPPORTED,
+                "derivatives need every system's factorization resident (%ld systems, workspace %d)",
+                (long)p->F * p->N, p->C);
+  return ensure_adjoint_buffers(p);
+}
+
+AdjArgs adj_args(fl_plan* p) {
+  AdjArgs a{};
+  a.gsys = p->gsys;
+  a.tpitch = p->TP;
+  a.list = p->list;
+  a.count = p->count;
+  a.C = p->C;
+  a.n = p->n;
+  a.N = p->N;
+  a.alpha = p->alpha;
+  a.branch = p->branch;
+  a.bd_d = p->bd_d;
+  a.bd_e = p->bd_e;
+  a.bd_dr = p->bd_dr;
+  a.refl = p->refl;
+  a.gam = p->gam;
+  a.What = p->What;
+  a.Vh = p->Vh;
+  a.single = p->prec;
+  return a;
+}
+
+template <int MODE>
+fl_status launch_sys_adjoint(fl_plan* p, AdjArgs& a) {
+  const unsigned g = (unsigned)std::min<long>(p->C, 8192);
+  if (p->n <= 64)
+    hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(g), dim3(64), 0, p->st, a);
+  else
+    hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(g), dim3(64), 0, p->st, a);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
+template <typename T>
+fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, const z64* gxi,
+                   z64* gW, z64* gu0) {
+  hipStream_t st = p->st;
+  const long N = p->N;
+  const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  const long nvox = (long)nx * ny * nz;
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  const Tw<T> tw = twiddles_of<T>(p);
+  // (d) reversed
+  hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, p->xi_tmp, p->u, p->vX,
+                     nvox, F, p->vbar, p->ubar);
+  LAUNCHCHK();
+  // (c) reversed: vbar2 = vbar + K^H ubar, then V^bar = FFT2(pad(vbar2)) / N
+  {
+    FftArgs r = rows_args(p->ubar, p->w2, tw.x, px, (long)F * nz * ny);
+    r.lin = nx;
+    r.in_sb = nx;
+    RUN((run_fft<double, T, T, -1>(r, st)));
+    RUN(conv_tail<T>(p, p->vbar2, p->vbar, 1));
+    FftArgs a = rows_args(p->vbar2, p->w1, tw.x, px, (long)F * nz * ny);
+    a.lin = nx;
+    a.in_sb = nx;
+    a.in_off = p->ox;
+    RUN((run_fft<double, T, T, -1>(a, st)));
+    FftArgs c = cols_args(p->w1, p->Xb, tw.y, py, px, F * nz);
+    c.lin = ny;
+    c.in_off = p->oy;
+    c.in_sp = (long)ny * px;
+    c.scale = 1.0 / (double)N;
+    RUN((run_fft<T, T, T, -1>(c, st)));
+  }
+  // (b) reversed, per solved system
+  const long FN = (long)F * N;
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(FN * nd, 256)), dim3(256), 0, st, (z64*)p->Yb, FN * nd);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_zero_real, dim3(nblk(FN, 256)), dim3(256), 0, st, p->cm, FN);
+  LAUNCHCHK();
+  AdjArgs a = adj_args(p);
+  a.X = p->Xb;
+  a.Y = p->Yb;
+  a.cm = p->cm;
+  RUN(launch_sys_adjoint<0>(p, a));
+  hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(256), 0, st, p->cm, N, p->Tb);
+  LAUNCHCHK();
+  // (a) reversed: Wbar = N IFFT2(W^bar) + 2 tau^2 delta^2 Tbar_f W_f (FP64)
+  {
+    FftArgs c = cols_args(p->Yb, p->w1, p->tw_y, py, px, F * nd);
+    RUN((run_fft<double, double, double, 1>(c, st)));
+    FftArgs r = rows_args(p->w1, gW, p->tw_x, px, (long)F * nd * py);
+    RUN((run_fft<double, double, double, 1>(r, st)));
+    const double cc = 2.0 * p->opts.tau * p->opts.tau * delta * delta;
+    const long per_f = (long)nd * N;
+    if (p->opts.input_dtype == 0)
+      hipLaunchKernelGGL(k_add_noise_term<double>, dim3(nblk(per_f * F, 256)), dim3(256), 0, st, gW,
+                         (const z64*)W, p->Tb, cc, per_f, F);
+    else
+      hipLaunchKernelGGL(k_add_noise_term<float>, dim3(nblk(per_f * F, 256)), dim3(256), 0, st, gW,
+                         (const z32*)W, p->Tb, cc, per_f, F);
+    LAUNCHCHK();
+  }
+  if (gu0) HIPCHK(hipMemcpyAsync(gu0, p->ubar, (size_t)F * nvox * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  return FL_OK;
+}
+
+template <typename T>
+fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, const void* dW,
+                   z64* dxi) {
+  hipStream_t st = p->st;
+  const long N = p->N;
+  const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
+  const long nvox = (long)nx * ny * nz;
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  const Tw<T> tw = twiddles_of<T>(p);
+  // T'_f = 2 tau^2 delta^2 Re <W_f, W'_f>
+  {
+    dim3 g(256, F);
+    if (p->opts.input_dtype == 0)
+      hipLaunchKernelGGL(k_dotre<double>, g, dim3(256), 0, st, (const z64*)W, (const z64*)dW,
+                         (long)nd * N, p->partial);
+    else
+      hipLaunchKernelGGL(k_dotre<float>, g, dim3(256), 0, st, (const z32*)W, (const z32*)dW,
+                         (long)nd * N, p->partial);
+    LAUNCHCHK();
+    const double cc = 2.0 * p->opts.tau * p->opts.tau * delta * delta;
+    hipLaunchKernelGGL(k_finish_dot, dim3(1), dim3(64), 0, st, p->partial, 256, F, cc, p->Tb);
+    LAUNCHCHK();
+  }
+  // W^' = FFT2(W')
+  {
+    FftArgs g = rows_args(dW, p->w1, tw.x, px, (long)F * nd * py);
+    if (p->opts.input_dtype == 0)
+      RUN((run_fft<double, T, T, -1>(g, st)));
+    else
+      RUN((run_fft<float, T, T, -1>(g, st)));
+    RUN((run_fft<T, T, T, -1>(cols_args(p->w1, p->Xb, tw.y, py, px, F * nd), st)));
+  }
+  const long FN = (long)F * N;
+  hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * nz, 256)), dim3(256), 0, st, (cx<T>*)p->Yb, FN * nz);
+  LAUNCHCHK();
+  AdjArgs a = adj_args(p);
+  a.X = p->Xb;
+  a.Y = p->Yb;
+  a.Tdot = p->Tb;
+  RUN(launch_sys_adjoint<1>(p, a));
+  // v' and u' = K v' (no incident term), then xi'
+  RUN(stage_c<T>(p, p->Yb, p->vbar, p->ubar, nullptr));
+  hipLaunchKernelGGL(k_xi_jvp, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->xi_tmp, p->u, p->vX,
+                     p->vbar, p->ubar, nvox, F, dxi);
+  LAUNCHCHK();
   return FL_OK;
 }
 
@@ -598,6 +823,9 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->wnc, C);
   PALLOC(p->refl, C * nz * nz);
   PALLOC(p->gam, C * nz);
+  PALLOC(p->bd_d, C * nz);
+  PALLOC(p->bd_e, C * nz);
+  PALLOC(p->bd_dr, C * nz);
   PALLOC(p->alpha, FN);
   PALLOC(p->branch, FN);
 #undef PALLOC
@@ -678,6 +906,26 @@ fl_status fl_invert(fl_plan* p, const void* W, const void* u0, double delta, voi
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   return p->prec ? invert_impl<float>(p, W, u0, delta, xi_out)
                  : invert_impl<double>(p, W, u0, delta, xi_out);
+}
+
+fl_status fl_invert_vjp(fl_plan* p, const void* W, const void* u0, double delta,
+                        const void* grad_xi, void* grad_W, void* grad_u0) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!W || !u0 || !grad_xi || !grad_W) return fail(FL_EINVAL, "NULL array argument");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  RUN(adjoint_preconditions(p));
+  return p->prec ? vjp_impl<float>(p, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W, (z64*)grad_u0)
+                 : vjp_impl<double>(p, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W, (z64*)grad_u0);
+}
+
+fl_status fl_invert_jvp(fl_plan* p, const void* W, const void* u0, double delta, const void* dW,
+                        void* dxi) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!W || !u0 || !dW || !dxi) return fail(FL_EINVAL, "NULL array argument");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  RUN(adjoint_preconditions(p));
+  return p->prec ? jvp_impl<float>(p, W, u0, delta, dW, (z64*)dxi)
+                 : jvp_impl<double>(p, W, u0, delta, dW, (z64*)dxi);
 }
 
 fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, int maxit,

@@ -115,6 +115,11 @@ __global__ __launch_bounds__(256) void k_narrow(const z64* __restrict__ in, z32*
   if (i < n) out[i] = cast<float>(in[i]);
 }
 
+__global__ __launch_bounds__(256) void k_zero_real(double* __restrict__ p, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
 template <typename TI>
 __global__ __launch_bounds__(256) void k_widen(const cx<TI>* __restrict__ in, z64* __restrict__ out,
                                                long n) {

@@ -445,6 +445,9 @@ struct DpArgs {
   int vh_single;       // 1: Vh holds complex64
   double* alpha;       // [F*N]
   signed char* branch; // [F*N]
+  double* bd_d;        // [C][n] real bidiagonal and right phases, kept for
+  double* bd_e;        //        the derivative kernels
+  z64* bd_dr;
 };
 
 // phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
@@ -568,6 +571,11 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       }
     }
     __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+      a.bd_d[(long)sl * n + i] = sd[i];
+      a.bd_e[(long)sl * n + i] = se[i];
+      a.bd_dr[(long)sl * n + i] = sdr[i];
+    }
     const double T = a.thr2[f];
     const double fro = a.fro[sl];
     const double amin = a.eta * fro;

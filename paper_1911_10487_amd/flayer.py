@@ -72,6 +72,10 @@ def lib():
     L.fl_plan_create.restype = I
     L.fl_invert.argtypes = [P, P, P, D, P]
     L.fl_invert.restype = I
+    L.fl_invert_vjp.argtypes = [P, P, P, D, P, P, P]
+    L.fl_invert_vjp.restype = I
+    L.fl_invert_jvp.argtypes = [P, P, P, D, P, P]
+    L.fl_invert_jvp.restype = I
     L.fl_forward.argtypes = [P, P, P, D, I, P]
     L.fl_forward.restype = I
     L.fl_plan_info.argtypes = [P, ctypes.POINTER(FlPlanInfo)]
@@ -159,6 +163,29 @@ class Plan:
                                ctypes.c_void_p(u0.data_ptr()), float(delta),
                                ctypes.c_void_p(xi_out.data_ptr())))
         return xi_out
+
+    def vjp(self, W, u0, delta, grad_xi, want_u0=False):
+        """Cotangents of W (and u0) for the xi cotangent grad_xi (complex128)."""
+        import torch
+        gW = torch.empty(W.shape, dtype=torch.complex128, device=W.device)
+        gu = (torch.empty((self.n_omega, self.nz, self.ny, self.nx), dtype=torch.complex128,
+                          device=W.device) if want_u0 else None)
+        g = grad_xi.to(torch.complex128).contiguous()
+        _check(lib().fl_invert_vjp(self._h, ctypes.c_void_p(W.data_ptr()),
+                                   ctypes.c_void_p(u0.data_ptr()), float(delta),
+                                   ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(gW.data_ptr()),
+                                   ctypes.c_void_p(gu.data_ptr() if gu is not None else None)))
+        return gW, gu
+
+    def jvp(self, W, u0, delta, dW):
+        """Tangent of xi for the data tangent dW (same dtype as W)."""
+        import torch
+        out = torch.empty((self.nz, self.ny, self.nx), dtype=torch.complex128, device=W.device)
+        d = dW.to(W.dtype).contiguous()
+        _check(lib().fl_invert_jvp(self._h, ctypes.c_void_p(W.data_ptr()),
+                                   ctypes.c_void_p(u0.data_ptr()), float(delta),
+                                   ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def forward(self, xi, u0, W_out=None):
         """Born data: W = omega^2 G * (xi u0) on the data planes' torus."""
