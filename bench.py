@@ -81,6 +81,11 @@ def main():
     ap.add_argument("--workload", default="single", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--delta", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
+                    help="time one precision only (profiling runs)")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB before timing "
+                         "(a known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -109,10 +114,31 @@ def main():
     Wd = torch.from_numpy(Wd_np).to(dev)
     del W
 
+    if args.calibrate_copy_mb:
+        # known-size kernels: a fill (writes nb bytes), a sum (reads nb bytes)
+        # and an out-of-place copy (reads and writes nb bytes)
+        nb = args.calibrate_copy_mb << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        s = src.sum()
+        dst = src * 1.0
+        torch.cuda.synchronize()
+        print(f"[bench] calibration kernels over {nb} bytes (sum {float(s):.0f})", file=sys.stderr,
+              flush=True)
+        del src, dst
+
     runs = {}
-    for label, prec in (("fp64", 0), ("mixed", 1)):
+    precs = (("fp64", 0), ("mixed", 1))
+    if args.only:
+        precs = tuple(x for x in precs if x[0] == args.only)
+    for label, prec in precs:
         runs[label] = time_precision(p, prec, Wd, u0, delta, args, torch, dev)
         print(f"[bench] {label}: {runs[label]['ms']:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.only:
+        r = runs[args.only]
+        print(json.dumps({"metric": "voxel-frequencies inverted/s", "precision": args.only,
+                          "value": p.voxel_frequencies / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                          "roofline": r["roofline"], "stages_ms_per_step": r["stages"]}), flush=True)
+        return
     xi64 = runs["fp64"]["xi"]
     ximx = runs["mixed"]["xi"]
     mixed_vs_fp64 = float(np.linalg.norm(ximx - xi64) / np.linalg.norm(xi64))
