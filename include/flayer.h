@@ -214,6 +214,35 @@ fl_status fl_profile_enable(fl_plan *plan, int on);
 fl_status fl_profile_read(fl_plan *plan, double *ms /*[FL_N_STAGES]*/,
                           int *launches /*[FL_N_STAGES]*/);
 
+/*
+ * Graph replay: capture the whole launch sequence of
+ * fl_invert(plan, W, u0, delta, xi_out) into a HIP graph (no host work and no
+ * memset nodes inside), then replay it with fl_graph_launch on the plan's
+ * stream. The graph keeps the pointers and delta it was captured with; the
+ * caller may change the contents of W and u0 between replays. The plan must
+ * outlive the graph. Errors: as fl_invert, plus FL_EDEVICE for capture
+ * failures.
+ */
+typedef struct fl_graph fl_graph;
+fl_status fl_graph_create(fl_plan *plan, const void *W, const void *u0, double delta,
+                          void *xi_out, fl_graph **out);
+fl_status fl_graph_launch(fl_graph *graph);
+void fl_graph_destroy(fl_graph *graph);
+
+/*
+ * Uneven batch: several independent inversions with different grids (one
+ * plan each) issued together. fl_batch_invert forks one stream per plan from
+ * `stream` (event waits, so it can itself be graph-captured), runs each
+ * instance's fl_invert on its own stream so that their kernels overlap, and
+ * joins them back into `stream`. Array i of W, u0, xi and delta[i] belong to
+ * plans[i]. The batch borrows the plans; destroy it before them.
+ */
+typedef struct fl_batch fl_batch;
+fl_status fl_batch_create(fl_plan *const *plans, int n, void *stream, fl_batch **out);
+fl_status fl_batch_invert(fl_batch *batch, const void *const *W, const void *const *u0,
+                          const double *delta, void *const *xi_out);
+void fl_batch_destroy(fl_batch *batch);
+
 /* Free a plan and everything it owns (NULL is a no-op). */
 void fl_plan_destroy(fl_plan *plan);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -284,17 +285,17 @@ template <typename T>
 fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   const int n = p->n;
   const cx<T>* What = (const cx<T>*)p->What;
-#define BD(TR, TC, NA, NB)                                                                      \
-  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB, T>), dim3(grid), dim3(TR * TC), 0, p->st, p->gsys, \
-                     p->TP, What, p->N, p->list, p->count, chunk0, p->C, o)
+#define BD(TR, TC, NA, NB, WPE)                                                          \
+  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB, T, WPE>), dim3(grid), dim3(TR * TC), 0, p->st, \
+                     p->gsys, p->TP, What, p->N, p->list, p->count, chunk0, p->C, o)
   switch (n) {
-    case 16: BD(16, 4, 1, 4); break;
-    case 32: BD(16, 8, 2, 4); break;
-    case 48: BD(16, 16, 3, 3); break;
-    case 64: BD(16, 16, 4, 4); break;
-    case 80: BD(16, 16, 5, 5); break;
-    case 96: BD(16, 16, 6, 6); break;
-    case 128: BD(32, 16, 4, 8); break;
+    case 16: BD(16, 4, 1, 4, 1); break;
+    case 32: BD(16, 8, 2, 4, 1); break;
+    case 48: BD(16, 16, 3, 3, 1); break;
+    case 64: BD(16, 16, 4, 4, 3); break;  // 168 VGPRs: three waves per SIMD measured fastest
+    case 80: BD(16, 16, 5, 5, 1); break;
+    case 96: BD(16, 16, 6, 6, 1); break;
+    case 128: BD(32, 16, 4, 8, 1); break;
     default: return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
   }
 #undef BD
@@ -866,6 +867,128 @@ fl_status fl_profile_read(fl_plan* p, double* ms, int* launches) {
   p->marks.clear();
   p->ev_used = 0;
   return FL_OK;
+}
+
+struct fl_graph {
+  fl_plan* plan;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+fl_status fl_graph_create(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out,
+                          fl_graph** out) {
+  if (!p || !out) return fail(FL_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (p->prof) return fail(FL_EINVAL, "disable stage timing before capturing a graph");
+  hipStream_t cap;
+  HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipStream_t keep = p->st;
+  // order the capture after everything already queued on the plan's stream
+  HIPCHK(hipStreamSynchronize(keep));
+  p->st = cap;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  fl_status s = FL_OK;
+  if (e == hipSuccess) {
+    s = fl_invert(p, W, u0, delta, xi_out);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cap, &graph) : e;
+  p->st = keep;
+  (void)hipStreamDestroy(cap);
+  if (s != FL_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(FL_EDEVICE, "stream capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  fl_graph* g = new fl_graph();
+  g->plan = p;
+  g->graph = graph;
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    fl_graph_destroy(g);
+    return fail(FL_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return FL_OK;
+}
+
+fl_status fl_graph_launch(fl_graph* g) {
+  if (!g) return fail(FL_EINVAL, "NULL graph");
+  HIPCHK(hipGraphLaunch(g->exec, g->plan->st));
+  return FL_OK;
+}
+
+void fl_graph_destroy(fl_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+struct fl_batch {
+  std::vector<fl_plan*> plans;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> done;
+  hipEvent_t fork = nullptr;
+  hipStream_t st = nullptr;
+};
+
+fl_status fl_batch_create(fl_plan* const* plans, int n, void* stream, fl_batch** out) {
+  if (!plans || n < 1 || !out) return fail(FL_EINVAL, "need at least one plan");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!plans[i]) return fail(FL_EINVAL, "plan %d is NULL", i);
+  fl_batch* b = new fl_batch();
+  b->st = (hipStream_t)stream;
+  b->plans.assign(plans, plans + n);
+  hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    hipStream_t s;
+    hipEvent_t ev;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) break;
+    b->streams.push_back(s);
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) break;
+    b->done.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    fl_batch_destroy(b);
+    return fail(FL_EDEVICE, "batch streams: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return FL_OK;
+}
+
+fl_status fl_batch_invert(fl_batch* b, const void* const* W, const void* const* u0,
+                          const double* delta, void* const* xi) {
+  if (!b || !W || !u0 || !delta || !xi) return fail(FL_EINVAL, "NULL argument");
+  const int n = (int)b->plans.size();
+  HIPCHK(hipEventRecord(b->fork, b->st));
+  fl_status s = FL_OK;
+  for (int i = 0; i < n && s == FL_OK; ++i) {
+    fl_plan* p = b->plans[i];
+    HIPCHK(hipStreamWaitEvent(b->streams[i], b->fork, 0));
+    hipStream_t keep = p->st;
+    p->st = b->streams[i];
+    s = fl_invert(p, W[i], u0[i], delta[i], xi[i]);
+    p->st = keep;
+    HIPCHK(hipEventRecord(b->done[i], b->streams[i]));
+  }
+  for (int i = 0; i < (int)b->done.size(); ++i) HIPCHK(hipStreamWaitEvent(b->st, b->done[i], 0));
+  return s;
+}
+
+void fl_batch_destroy(fl_batch* b) {
+  if (!b) return;
+  for (hipStream_t s : b->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
 }
 
 void fl_plan_destroy(fl_plan* p) {

@@ -334,8 +334,9 @@ __device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB], z64 (&qr)[NA],
   }
 }
 
-template <int TR, int TC, int NA, int NB, typename TW>
-__global__ __launch_bounds__(TR* TC) void k_bidiag(const z64* __restrict__ gsys, int tpitch,
+// WPE: minimum waves per SIMD requested from the register allocator
+template <int TR, int TC, int NA, int NB, typename TW, int WPE>
+__global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ gsys, int tpitch,
                                                    const cx<TW>* __restrict__ What, long N,
                                                    const int* __restrict__ list,
                                                    const int* __restrict__ count, int chunk0, int C,

@@ -88,6 +88,19 @@ def lib():
     L.fl_profile_enable.restype = I
     L.fl_profile_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I)]
     L.fl_profile_read.restype = I
+    L.fl_graph_create.argtypes = [P, P, P, D, P, ctypes.POINTER(P)]
+    L.fl_graph_create.restype = I
+    L.fl_graph_launch.argtypes = [P]
+    L.fl_graph_launch.restype = I
+    L.fl_graph_destroy.argtypes = [P]
+    L.fl_graph_destroy.restype = None
+    PP = ctypes.POINTER(P)
+    L.fl_batch_create.argtypes = [PP, I, P, PP]
+    L.fl_batch_create.restype = I
+    L.fl_batch_invert.argtypes = [P, PP, PP, ctypes.POINTER(D), PP]
+    L.fl_batch_invert.restype = I
+    L.fl_batch_destroy.argtypes = [P]
+    L.fl_batch_destroy.restype = None
     L.fl_plan_destroy.argtypes = [P]
     L.fl_plan_destroy.restype = None
     _lib = L
@@ -217,6 +230,66 @@ class Plan:
     def close(self):
         if self._h:
             lib().fl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured fl_invert (fixed pointers and delta), replayed on the
+    plan's stream."""
+
+    def __init__(self, plan, W, u0, delta, xi_out):
+        self._keep = (plan, W, u0, xi_out)
+        h = ctypes.c_void_p()
+        _check(lib().fl_graph_create(plan._h, ctypes.c_void_p(W.data_ptr()),
+                                     ctypes.c_void_p(u0.data_ptr()), float(delta),
+                                     ctypes.c_void_p(xi_out.data_ptr()), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(lib().fl_graph_launch(self._h))
+
+    def close(self):
+        if self._h:
+            lib().fl_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several plans (uneven grids) inverted together on forked streams."""
+
+    def __init__(self, plans, stream=None):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        st = stream if stream is not None else _stream_handle()
+        _check(lib().fl_batch_create(arr, len(self.plans), st, ctypes.byref(h)))
+        self._h = h
+
+    def invert(self, Ws, u0s, deltas, xis):
+        n = len(self.plans)
+        P = ctypes.c_void_p
+        W = (P * n)(*[w.data_ptr() for w in Ws])
+        U = (P * n)(*[u.data_ptr() for u in u0s])
+        X = (P * n)(*[x.data_ptr() for x in xis])
+        D = (ctypes.c_double * n)(*[float(d) for d in deltas])
+        _check(lib().fl_batch_invert(self._h, W, U, D, X))
+        return xis
+
+    def close(self):
+        if self._h:
+            lib().fl_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
