@@ -76,6 +76,10 @@ typedef struct {
                           1 = one xi per frequency: xi_out is [n_omega][nz][ny][nx] */
   int input_dtype;     /* 0 = complex128 W and u0 (default); 1 = complex64 */
   void *stream;        /* hipStream_t for every call on this plan */
+  int max_chunk;       /* 0 = library default; otherwise an upper bound on the
+                          systems factorized per solver launch (the workspace
+                          holds one chunk of n x n reflectors; derivative calls
+                          re-factorize chunk by chunk when there are several) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);

@@ -22,6 +22,7 @@ struct AdjArgs {
   const int* list;
   const int* count;
   int C, n;
+  int chunk0;           // first compacted system of the resident chunk
   long N;
   const double* alpha;  // [F*N]
   const signed char* branch;
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
   const int lane = threadIdx.x;
   const int n = a.n;
   const int total = *a.count;
-  for (int sl = blockIdx.x; sl < a.C && sl < total; sl += gridDim.x) {
-    const int fm = a.list[sl];
+  for (int sl = blockIdx.x; sl < a.C && a.chunk0 + sl < total; sl += gridDim.x) {
+    const int fm = a.list[a.chunk0 + sl];
     const int f = (int)(fm / a.N);
     const long m = fm - (long)f * a.N;
     const double al = a.alpha[fm];

@@ -150,18 +150,53 @@ fl_status make_twiddles(fl_plan* p, cx<T>** out, int L) {
   return FL_OK;
 }
 
+// FFT tiles: a twiddle table of L entries plus two buffers of CB transforms,
+// within kFftLds bytes of LDS (the kernels opt in to that much dynamic LDS).
+constexpr size_t kFftLds = 96 * 1024;
+
 int pick_cb(int L, size_t esz) {
-  long cb = 65536 / (2L * (L + 1) * (long)esz);
+  long cb = (long)(kFftLds - L * esz) / (2L * (L + 1) * (long)esz);
   int r = 1;
   while (r * 2 <= cb && r < 16) r *= 2;
   return r;
 }
 
+size_t fft_lds(int L, int CB, size_t esz) { return ((size_t)L + 2 * (size_t)CB * (L + 1)) * esz; }
+
+template <typename K>
+void allow_lds(K kernel) {
+  static bool done = false;
+  if (!done) {
+    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kFftLds);
+    done = true;
+  }
+}
+
+template <typename TI, typename T, typename TO, int DIR, int L>
+void launch_p2(const FftArgs& g, hipStream_t st) {
+  constexpr int CB = p2_cb<L, T>(), NT = CB * (L / P2<L>::E);
+  hipLaunchKernelGGL((k_fft_p2<TI, T, TO, DIR, L>), dim3(nblk(g.B, CB), g.planes), dim3(NT), 0, st, g);
+}
+
 template <typename TI, typename T, typename TO, int DIR>
 fl_status run_fft(const FftArgs& g, hipStream_t st) {
+  if (p2_supported(g.L) && g.in_kfast == g.out_kfast) {
+    switch (g.L) {
+      case 32: launch_p2<TI, T, TO, DIR, 32>(g, st); break;
+      case 64: launch_p2<TI, T, TO, DIR, 64>(g, st); break;
+      case 128: launch_p2<TI, T, TO, DIR, 128>(g, st); break;
+      case 256: launch_p2<TI, T, TO, DIR, 256>(g, st); break;
+      case 512: launch_p2<TI, T, TO, DIR, 512>(g, st); break;
+      default: launch_p2<TI, T, TO, DIR, 1024>(g, st); break;
+    }
+    LAUNCHCHK();
+    return FL_OK;
+  }
   int CB = pick_cb(g.L, sizeof(cx<T>));
-  size_t lds = 2 * (size_t)CB * (g.L + 1) * sizeof(cx<T>);
+  size_t lds = fft_lds(g.L, CB, sizeof(cx<T>));
   dim3 grid(nblk(g.B, CB), g.planes);
+  allow_lds(k_fft<TI, T, TO, DIR>);
   hipLaunchKernelGGL((k_fft<TI, T, TO, DIR>), grid, dim3(256), lds, st, g, CB);
   LAUNCHCHK();
   return FL_OK;
@@ -303,10 +338,11 @@ fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   return FL_OK;
 }
 
+// Classification, compaction of the systems that need a solve, and the
+// zero fill of v^ (inactive systems keep v^ = 0).
 template <typename T>
-fl_status solve_systems(fl_plan* p, double delta) {
+fl_status solve_prepare(fl_plan* p) {
   const long FN = (long)p->F * p->N;
-  const int n = p->n;
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
   hipLaunchKernelGGL(k_classify<T>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const cx<T>*)p->What,
@@ -321,6 +357,15 @@ fl_status solve_systems(fl_plan* p, double delta) {
   hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * p->nz, 256)), dim3(256), 0, st, (cx<T>*)p->Vh,
                      FN * p->nz);
   LAUNCHCHK();
+  return FL_OK;
+}
+
+// Bidiagonalization and discrepancy solve of compacted systems
+// [c0, c0 + C); leaves their factorization in the chunk workspace.
+template <typename T>
+fl_status solve_chunk(fl_plan* p, long c0) {
+  const int n = p->n;
+  hipStream_t st = p->st;
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam};
   DpArgs a{};
   a.dg = p->dg;
@@ -343,19 +388,25 @@ fl_status solve_systems(fl_plan* p, double delta) {
   a.bd_d = p->bd_d;
   a.bd_e = p->bd_e;
   a.bd_dr = p->bd_dr;
+  a.chunk0 = (int)c0;
   const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
   const unsigned gd = (unsigned)std::min<long>(p->C, 8192);
-  for (long c0 = 0; c0 < FN; c0 += p->C) {
-    RUN(mark(p, FL_STAGE_BIDIAG));
-    RUN(launch_bidiag<T>(p, (int)c0, gb, o));
-    a.chunk0 = (int)c0;
-    RUN(mark(p, FL_STAGE_DP));
-    if (n <= 64)
-      hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, st, a);
-    LAUNCHCHK();
-  }
+  RUN(mark(p, FL_STAGE_BIDIAG));
+  RUN(launch_bidiag<T>(p, (int)c0, gb, o));
+  RUN(mark(p, FL_STAGE_DP));
+  if (n <= 64)
+    hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, st, a);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
+template <typename T>
+fl_status solve_systems(fl_plan* p) {
+  const long FN = (long)p->F * p->N;
+  RUN(solve_prepare<T>(p));
+  for (long c0 = 0; c0 < FN; c0 += p->C) RUN(solve_chunk<T>(p, c0));
   return FL_OK;
 }
 
@@ -406,11 +457,28 @@ fl_status conv_tail(fl_plan* p, z64* out, const z64* add, int conj_mul) {
   z.B = (int)N;
   z.planes = F;
   z.scale = 1.0;
-  int CBz = pick_cb(2 * nz, sizeof(cx<T>));
-  size_t ldsz = 2 * (size_t)CBz * (2 * nz + 1) * sizeof(cx<T>);
   RUN(mark(p, FL_STAGE_CONV_Z));
-  hipLaunchKernelGGL(k_fft_conv<T>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, tw.ktab, (long)N,
-                     (long)2 * nz * N, CBz, conj_mul);
+  if (p2_supported(2 * nz)) {
+#define CONVP2(LL)                                                                              \
+  hipLaunchKernelGGL((k_fft_conv_p2<T, LL>), dim3(nblk(N, p2_cb<LL, T>()), F),                 \
+                     dim3(p2_cb<LL, T>() * (LL / P2<LL>::E)), 0, st, z, tw.ktab, (long)N,       \
+                     (long)2 * nz * N, conj_mul)
+    switch (2 * nz) {
+      case 32: CONVP2(32); break;
+      case 64: CONVP2(64); break;
+      case 128: CONVP2(128); break;
+      case 256: CONVP2(256); break;
+      case 512: CONVP2(512); break;
+      default: CONVP2(1024); break;
+    }
+#undef CONVP2
+  } else {
+    int CBz = pick_cb(2 * nz, sizeof(cx<T>));
+    size_t ldsz = fft_lds(2 * nz, CBz, sizeof(cx<T>));
+    allow_lds(k_fft_conv<T>);
+    hipLaunchKernelGGL(k_fft_conv<T>, dim3(nblk(N, CBz), F), dim3(256), ldsz, st, z, tw.ktab,
+                       (long)N, (long)2 * nz * N, CBz, conj_mul);
+  }
   LAUNCHCHK();
   FftArgs b = cols_args(p->w1, p->w2, tw.y, py, px, F * nz);
   b.lout = ny;
@@ -440,13 +508,30 @@ fl_status stage_c(fl_plan* p, const void* Vin, z64* vout, z64* uout, const z64* 
   g.out_off = p->oy;
   g.out_sp = (long)ny * px;
   RUN((run_fft<T, T, T, 1>(g, st)));
-  int CB = pick_cb(px, sizeof(cx<T>));
   long rows = (long)F * nz * ny;
-  size_t lds = 2 * (size_t)CB * (px + 1) * sizeof(cx<T>);
   RUN(mark(p, FL_STAGE_CROP_PAD));
-  hipLaunchKernelGGL(k_rows_crop_pad<T>, dim3(nblk(rows, CB)), dim3(256), lds, st,
-                     (const cx<T>*)p->w1, vout, (cx<T>*)p->w2, tw.x, px, nx, p->ox, (int)rows,
-                     1.0 / (double)N, CB);
+  if (p2_supported(px)) {
+#define CROPP2(LL)                                                                             \
+  hipLaunchKernelGGL((k_rows_crop_pad_p2<T, LL>), dim3(nblk(rows, p2_cb<LL, T>())),            \
+                     dim3(p2_cb<LL, T>() * (LL / P2<LL>::E)), 0, st, (const cx<T>*)p->w1, vout, \
+                     (cx<T>*)p->w2, tw.x, nx, p->ox, (int)rows, 1.0 / (double)N)
+    switch (px) {
+      case 32: CROPP2(32); break;
+      case 64: CROPP2(64); break;
+      case 128: CROPP2(128); break;
+      case 256: CROPP2(256); break;
+      case 512: CROPP2(512); break;
+      default: CROPP2(1024); break;
+    }
+#undef CROPP2
+  } else {
+    int CB = pick_cb(px, sizeof(cx<T>));
+    size_t lds = fft_lds(px, CB, sizeof(cx<T>));
+    allow_lds(k_rows_crop_pad<T>);
+    hipLaunchKernelGGL(k_rows_crop_pad<T>, dim3(nblk(rows, CB)), dim3(256), lds, st,
+                       (const cx<T>*)p->w1, vout, (cx<T>*)p->w2, tw.x, px, nx, p->ox, (int)rows,
+                       1.0 / (double)N, CB);
+  }
   LAUNCHCHK();
   return conv_tail<T>(p, uout, add, 0);
 }
@@ -495,7 +580,7 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
     RUN((run_fft<T, T, T, -1>(cols_args(p->w1, p->What, twy, py, px, F * nd), st)));
   }
   // (b) regularized solves of the active systems -> v^ plane-major
-  RUN(solve_systems<T>(p, delta));
+  RUN(solve_systems<T>(p));
   // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
   RUN(stage_c<T>(p, p->Vh, p->vX, p->u, u0d));
   // (d) xi, in FP64
@@ -529,10 +614,6 @@ fl_status ensure_adjoint_buffers(fl_plan* p) {
 fl_status adjoint_preconditions(fl_plan* p) {
   if (p->opts.combine != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the least-squares xi (combine 0)");
-  if ((long)p->C < (long)p->F * p->N)
-    return fail(FL_EUNSUPPORTED,
-                "derivatives need every system's factorization resident (%ld systems, workspace %d)",
-                (long)p->F * p->N, p->C);
   return ensure_adjoint_buffers(p);
 }
 
@@ -558,14 +639,24 @@ AdjArgs adj_args(fl_plan* p) {
   return a;
 }
 
-template <int MODE>
+// Per-system derivative pass over every compacted system. The forward left
+// the factorization of the last chunk in the workspace; when the systems span
+// several chunks, each chunk is factorized again (same kernels, same
+// results) right before its derivative pass.
+template <int MODE, typename T>
 fl_status launch_sys_adjoint(fl_plan* p, AdjArgs& a) {
+  const long FN = (long)p->F * p->N;
   const unsigned g = (unsigned)std::min<long>(p->C, 8192);
-  if (p->n <= 64)
-    hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(g), dim3(64), 0, p->st, a);
-  else
-    hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(g), dim3(64), 0, p->st, a);
-  LAUNCHCHK();
+  const bool resident = (long)p->C >= FN;
+  for (long c0 = 0; c0 < FN; c0 += p->C) {
+    if (!resident) RUN(solve_chunk<T>(p, c0));
+    a.chunk0 = (int)c0;
+    if (p->n <= 64)
+      hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(g), dim3(64), 0, p->st, a);
+    else
+      hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(g), dim3(64), 0, p->st, a);
+    LAUNCHCHK();
+  }
   return FL_OK;
 }
 
@@ -611,7 +702,7 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   a.X = p->Xb;
   a.Y = p->Yb;
   a.cm = p->cm;
-  RUN(launch_sys_adjoint<0>(p, a));
+  RUN((launch_sys_adjoint<0, T>(p, a)));
   hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(256), 0, st, p->cm, N, p->Tb);
   LAUNCHCHK();
   // (a) reversed: Wbar = N IFFT2(W^bar) + 2 tau^2 delta^2 Tbar_f W_f (FP64)
@@ -673,7 +764,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   a.X = p->Xb;
   a.Y = p->Yb;
   a.Tdot = p->Tb;
-  RUN(launch_sys_adjoint<1>(p, a));
+  RUN((launch_sys_adjoint<1, T>(p, a)));
   // v' and u' = K v' (no incident term), then xi'
   RUN(stage_c<T>(p, p->Yb, p->vbar, p->ubar, nullptr));
   hipLaunchKernelGGL(k_xi_jvp, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->xi_tmp, p->u, p->vX,
@@ -814,7 +905,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->norm2, F);
   // reflector workspace C * nz^2 complex; up to 24 GiB, so that the
   // 128^2 x 64 grids run as one chunk even with five frequencies
-  const long cap = std::max<long>(1024, (24L << 30) / ((long)nz * nz * (long)sizeof(z64)));
+  long cap = std::max<long>(1024, (24L << 30) / ((long)nz * nz * (long)sizeof(z64)));
+  if (o.max_chunk > 0) cap = std::min<long>(cap, o.max_chunk);
   p->C = (int)std::min<long>(FN, cap);
   const long C = p->C;
   PALLOC(p->dg, C * nz);

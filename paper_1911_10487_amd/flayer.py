@@ -36,6 +36,7 @@ class FlOpts(ctypes.Structure):
         ("tau", ctypes.c_double), ("eta", ctypes.c_double),
         ("combine", ctypes.c_int), ("input_dtype", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("max_chunk", ctypes.c_int),
     ]
 
 
@@ -127,10 +128,11 @@ class Plan:
     """A flayer plan for one geometry and frequency set (owns device tables)."""
 
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
-                 tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None):
+                 tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
+        o.max_chunk = max_chunk
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)

@@ -140,3 +140,30 @@ def test_mixed_precision_derivatives(case):
     rW, _ = adjoint.vjp(p, W, u0, d, g)
     say("mixed vjp rel err", rel(gW, rW))
     assert rel(gW, rW) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_chunked_factorization_matches_resident(case, precision):
+    """A plan whose solver workspace holds a few dozen systems (so that the
+    derivative passes re-factorize chunk by chunk) gives bitwise the same
+    xi, VJP and JVP as a plan holding every system at once."""
+    import torch
+    p, W, u0, d = case
+    g = synth.random_field((p.nz, p.ny, p.nx), (45,))
+    dW = synth.random_field(W.shape, (46,))
+    Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    gt, dWt = torch.from_numpy(g).cuda(), torch.from_numpy(dW).cuda()
+    outs = []
+    for mc in (0, 37):
+        say("chunk", mc, "precision", precision)
+        plan = _plan(p, precision=precision, max_chunk=mc)
+        xi = plan.invert(Wt, ut, d).cpu().numpy()
+        n_act = plan.active_systems()
+        gW, gu = plan.vjp(Wt, ut, d, gt, want_u0=True)
+        jv = plan.jvp(Wt, ut, d, dWt)
+        torch.cuda.synchronize()
+        outs.append((xi, gW.cpu().numpy(), gu.cpu().numpy(), jv.cpu().numpy()))
+        plan.close()
+    assert n_act > 2 * 37, n_act
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
