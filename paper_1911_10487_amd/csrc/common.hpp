@@ -54,6 +54,20 @@ __device__ __forceinline__ cx<T> cfmac(cx<T> acc, cx<T> a, cx<T> b) {
   acc.y = fma(a.x, b.y, fma(-a.y, b.x, acc.y));
   return acc;
 }
+// acc - a * b
+template <typename T>
+__device__ __forceinline__ cx<T> cfms(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.x = fma(-a.x, b.x, fma(a.y, b.y, acc.x));
+  acc.y = fma(-a.x, b.y, fma(-a.y, b.x, acc.y));
+  return acc;
+}
+// acc - a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cfmsc(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.x = fma(-a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(-a.y, b.x, fma(a.x, b.y, acc.y));
+  return acc;
+}
 // multiply by -i (dir < 0) or +i (dir > 0)
 template <typename T, int DIR>
 __device__ __forceinline__ cx<T> rot90(cx<T> a) {
@@ -107,21 +121,22 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// value of lane (i ^ 16), within each half-wave
-__device__ __forceinline__ double xor16_d(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_ds_swizzle(lo, 0x401F);
-  hi = __builtin_amdgcn_ds_swizzle(hi, 0x401F);
-  return __hiloint2double(hi, lo);
+// v plus the value of lane (i ^ 16). The swap leaves each lane holding its
+// own value and its partner's, and both lanes of a pair add them in the same
+// order (lower lane's value first), so they get bitwise the same sum.
+__device__ __forceinline__ double add_xor16(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(rh[0], rl[0]) + __hiloint2double(rh[1], rl[1]);
 }
 
-// value of lane (i ^ 32)
-__device__ __forceinline__ double xor32_d(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  const bool low = (threadIdx.x & 32) == 0;
-  return __hiloint2double(low ? rh[1] : rh[0], low ? rl[1] : rl[0]);
+// v plus the value of lane (i ^ 32), same pairing as add_xor16
+__device__ __forceinline__ double add_xor32(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(rh[0], rl[0]) + __hiloint2double(rh[1], rl[1]);
 }
 
 // Sum over the 16 lanes of a DPP row; every lane receives the bitwise same
@@ -138,16 +153,16 @@ __device__ __forceinline__ double row16_sum(double v) {
 template <int W>
 __device__ __forceinline__ double lanes_sum(double v) {
   v = row16_sum(v);
-  if (W >= 32) v += xor16_d(v);
-  if (W >= 64) v += xor32_d(v);
+  if (W >= 32) v = add_xor16(v);
+  if (W >= 64) v = add_xor32(v);
   return v;
 }
 
 // Sum over the lanes of a wave that share (lane mod W): strides W .. 32.
 template <int W>
 __device__ __forceinline__ double strided_sum(double v) {
-  if (W <= 16) v += xor16_d(v);
-  if (W <= 32) v += xor32_d(v);
+  if (W <= 16) v = add_xor16(v);
+  if (W <= 32) v = add_xor32(v);
   return v;
 }
 

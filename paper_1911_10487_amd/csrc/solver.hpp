@@ -182,9 +182,11 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
       s = lanes_sum<TR>(s);
       piv.x = lanes_sum<TR>(piv.x);
       piv.y = lanes_sum<TR>(piv.y);
-      const double xn = sqrt(s);
-      const double ap = sqrt(nrm2(piv));
-      const z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
+      const double xn = s > 0.0 ? s * rsq_nr(s) : 0.0;
+      const double a2 = nrm2(piv);
+      const double iap = a2 > 0.0 ? rsq_nr(a2) : 0.0;
+      const double ap = a2 * iap;
+      const z64 ph = a2 > 0.0 ? mk(piv.x * iap, piv.y * iap) : mk(1.0, 0.0);
       const z64 beta = mk(-ph.x * xn, -ph.y * xn);
 #pragma unroll
       for (int a = SA; a < NA; ++a) {
@@ -192,7 +194,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
         if (i >= k) S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
       }
       if (r == kr) {
-        S.lg[par] = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
+        S.lg[par] = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
         S.dg[k] = beta;
       }
     }
@@ -224,7 +226,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
       const int j = c + TC * b;
       if (j > k) {
 #pragma unroll
-        for (int a = SA; a < NA; ++a) A[a][b] = A[a][b] - ur[a] * w;
+        for (int a = SA; a < NA; ++a) A[a][b] = cfms(A[a][b], ur[a], w);
       }
     }
     if (c == 0) {
@@ -235,7 +237,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
       sm.y = lanes_sum<TR>(sm.y);
       sm = g * sm;
 #pragma unroll
-      for (int a = SA; a < NA; ++a) qr[a] = qr[a] - ur[a] * sm;
+      for (int a = SA; a < NA; ++a) qr[a] = cfms(qr[a], ur[a], sm);
     }
   }
   const int rk = n - k - 1;
@@ -256,12 +258,14 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
     double s = 0.0;
     for (int j = k + 1 + lane; j < n; j += 64) s += nrm2(S.xr[par][j]);
     s = lanes_sum<64>(s);
-    const double xn = sqrt(s);
+    const double xn = s > 0.0 ? s * rsq_nr(s) : 0.0;
     const z64 piv = cj(S.xr[par][k + 1]);
-    const double ap = sqrt(nrm2(piv));
-    const z64 ph = ap > 0.0 ? mk(piv.x / ap, piv.y / ap) : mk(1.0, 0.0);
+    const double a2 = nrm2(piv);
+    const double iap = a2 > 0.0 ? rsq_nr(a2) : 0.0;
+    const double ap = a2 * iap;
+    const z64 ph = a2 > 0.0 ? mk(piv.x * iap, piv.y * iap) : mk(1.0, 0.0);
     const z64 beta = mk(-ph.x * xn, -ph.y * xn);
-    const double g = xn > 0.0 ? 1.0 / (xn * (xn + ap)) : 0.0;
+    const double g = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
     z64 vr[NB];
 #pragma unroll
     for (int b = SB; b < NB; ++b) {
@@ -297,7 +301,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
         for (int w = 0; w < NW; ++w) z = z + S.zp[par][w][i];
         z = g * z;
 #pragma unroll
-        for (int b = SB; b < NB; ++b) A[a][b] = A[a][b] - z * cj(vr[b]);
+        for (int b = SB; b < NB; ++b) A[a][b] = cfmsc(A[a][b], z, vr[b]);
       } else if (i == k) {
         // row k is finished: keep the reflector in its place (LAPACK style)
 #pragma unroll
@@ -587,36 +591,66 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       double lo = log(amin);
       const double h0 = log(fro) + 1.0;
       double x = lane == 0 ? lo : h0 + 4.0 * (lane - 1);
-      bool ge = phi_fwd(sd, se, sq, n, exp(x)) >= T;
-      unsigned long long bal = __ballot(ge);
+      double ph = phi_fwd(sd, se, sq, n, exp(x));
+      unsigned long long bal = __ballot(ph >= T);
       if (!(bal & 1ull)) {
         br = 2;
+        // bracket [lo, hi] on x = log(alpha) with phi(lo) < T <= phi(hi);
+        // flo / fhi hold phi at the ends once known (NaN otherwise)
+        const double nan = __longlong_as_double(0x7ff8000000000000ll);
         unsigned long long up = bal & ~1ull;
-        double hi;
+        double hi, flo = __shfl(ph, 0), fhi = nan;
         if (up) {
-          int l1 = __ffsll((long long)up) - 1;
+          const int l1 = __ffsll((long long)up) - 1;
           hi = h0 + 4.0 * (l1 - 1);
-          if (l1 > 1) lo = h0 + 4.0 * (l1 - 2);
+          fhi = __shfl(ph, l1);
+          if (l1 > 1) {
+            lo = h0 + 4.0 * (l1 - 2);
+            flo = __shfl(ph, l1 - 1);
+          }
         } else {
           hi = h0 + 4.0 * 62;
           lo = hi;
         }
-        for (int round = 0; round < 12 && hi - lo > 4e-16 * fmax(1.0, fabs(hi)); ++round) {
-          const double step = (hi - lo) / 65.0;
-          const double xl = lo + step * (lane + 1);
-          const bool g2 = phi_fwd(sd, se, sq, n, exp(xl)) >= T;
-          const unsigned long long b2 = __ballot(g2);
+        // Multisection with 64 points per round. Once phi is known at both
+        // ends, the points are packed around the secant estimate of the
+        // root (phi is smooth in log alpha, so the secant error shrinks like
+        // the square of the bracket). A window that misses the root still
+        // leaves a valid, smaller bracket; the round after a miss spreads
+        // its points over the whole bracket again.
+        bool miss = false;
+        for (int round = 0; round < 24 && hi - lo > 1e-13 * fmax(1.0, fabs(hi)); ++round) {
+          const double wdt = hi - lo;
+          double a0 = lo, a1 = hi;
+          if (!miss && flo == flo && fhi == fhi && fhi > flo) {
+            const double xs = lo + (T - flo) / (fhi - flo) * wdt;
+            const double hw = fmax(0.25 * wdt * wdt, 1e-3 * wdt);
+            a0 = fmax(lo, xs - hw);
+            a1 = fmin(hi, xs + hw);
+          }
+          // 64 points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
+          const double step = (a1 - a0) / (a1 < hi ? 64.0 : 65.0);
+          const double pl = phi_fwd(sd, se, sq, n, exp(a0 + step * (lane + 1)));
+          const unsigned long long b2 = __ballot(pl >= T);
           if (b2) {
             const int l1 = __ffsll((long long)b2) - 1;
-            const double nhi = lo + step * (l1 + 1);
-            const double nlo = l1 > 0 ? lo + step * l1 : lo;
-            hi = nhi;
-            lo = nlo;
+            miss = l1 == 0 && a0 > lo;  // the root may lie left of the window
+            hi = a0 + step * (l1 + 1);
+            fhi = __shfl(pl, l1);
+            if (l1 > 0) {
+              lo = a0 + step * l1;
+              flo = __shfl(pl, l1 - 1);
+            }
           } else {
-            lo = lo + step * 64;
+            miss = a1 < hi;             // the root lies right of the window
+            lo = a0 + step * 64;
+            flo = __shfl(pl, 63);
           }
         }
-        al = exp(0.5 * (lo + hi));
+        double xr = 0.5 * (lo + hi);
+        if (flo == flo && fhi == fhi && fhi > flo)
+          xr = fmin(hi, fmax(lo, lo + (T - flo) / (fhi - flo) * (hi - lo)));
+        al = exp(xr);
       }
     }
     if (lane == 0) elden_solve(sd, se, sq, n, al, srho, soff, srr, sy);
