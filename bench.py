@@ -33,31 +33,39 @@ WORKLOAD_TEXT = {
 
 
 def stage_units(p, active, n, b=16):
-    """Algorithmic bytes (HBM-bound stages; b bytes per complex element of the
-    FFT-side arrays) or FP64 flops per call, per stage."""
+    """Algorithmic work per timed step and stage: HBM bytes that the stage
+    must move at least (b bytes per complex element of the FFT-side arrays,
+    16 for the complex128 input W, the FP64 v, u, u0 and xi), or FP64 flops."""
     F, N, nd, nz = p.n_omega, p.px * p.py, p.nd, p.nz
     nvox = p.nx * p.ny * p.nz
-    rows_y = F * nz * p.ny * p.px
+    rows_y = F * nz * p.ny * p.px      # rows of X's y-window on the padded x axis
+    planes_n = F * nz * N              # one value per (f, z, system)
     u = {
-        "norm": ("GB/s", F * nd * N * b),
-        "fft_rows": ("GB/s", 2 * F * nd * N * b),
+        "norm": ("GB/s", F * nd * N * 16),
+        "fft_rows": ("GB/s", F * nd * N * (16 + b)),
         "fft_cols": ("GB/s", 2 * F * nd * N * b),
-        "classify": ("GB/s", F * nd * N * b + F * N * 8),
-        "ifft_cols": ("GB/s", F * nz * N * b + rows_y * b),
-        "crop_pad": ("GB/s", rows_y * b + F * nvox * b + rows_y * b),
-        "conv_cols": ("GB/s", rows_y * b + F * nz * N * b),
-        "conv_z": ("GB/s", 2 * F * nz * N * b + 2 * F * nz * N * b),
-        "conv_icols": ("GB/s", F * nz * N * b + rows_y * b),
-        "conv_irows": ("GB/s", rows_y * b + 2 * F * nvox * b),
-        "xi": ("GB/s", 2 * F * nvox * b + nvox * b),
+        # read W^, write ||w||^2 and flags, read flags twice, write the list,
+        # zero v^
+        "classify": ("GB/s", F * nd * N * b + F * N * (8 + 4 * 3) + active * 4 + planes_n * b),
+        "ifft_cols": ("GB/s", planes_n * b + rows_y * b),
+        "crop_pad": ("GB/s", rows_y * b + F * nvox * 16 + rows_y * b),
+        "conv_cols": ("GB/s", rows_y * b + planes_n * b),
+        # read the nz nonzero z samples and the 2 nz kernel values, write nz
+        "conv_z": ("GB/s", planes_n * b + 2 * planes_n * b + planes_n * b),
+        "conv_icols": ("GB/s", planes_n * b + rows_y * b),
+        "conv_irows": ("GB/s", rows_y * b + 2 * F * nvox * 16),
+        "xi": ("GB/s", 2 * F * nvox * 16 + nvox * 16),
         # complex Householder bidiagonalization of an n x n matrix: 4 x (8/3) n^3
         "bidiag": ("TFLOP/s", active * 32.0 / 3.0 * n ** 3),
         # per system: about 60 Newton trials of ~60 flops per row (estimate)
         "dp": ("TFLOP/s", active * 60.0 * 60.0 * n),
-        # reflector application: n^2/2 complex multiply-adds twice
-        "backtransform": ("GB/s", active * (n * n * b // 2 + 2 * n * b)),
+        "backtransform": ("GB/s", 0),
     }
     return u
+
+
+FFT_STAGES = ("fft_rows", "fft_cols", "ifft_cols", "crop_pad", "conv_cols", "conv_z",
+              "conv_icols", "conv_irows")
 
 
 def cpu_baseline(p, Wd, u0, delta, vf):
@@ -83,6 +91,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
                     help="time one precision only (profiling runs)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the solver schedule on the data before timing (the "
+                         "default schedule is the tuner's choice for this workload)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing "
                          "(a known-size kernel for scaling HBM counters)")
@@ -137,7 +148,9 @@ def main():
         r = runs[args.only]
         print(json.dumps({"metric": "voxel-frequencies inverted/s", "precision": args.only,
                           "value": p.voxel_frequencies / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
-                          "roofline": r["roofline"], "stages_ms_per_step": r["stages"]}), flush=True)
+                          "schedule": r["tuning"], "roofline": r["roofline"],
+                          "fft_stages": r["fft_stages"], "hbm_stages": r["hbm_stages"],
+                          "stages_ms_per_step": r["stages"]}), flush=True)
         return
     xi64 = runs["fp64"]["xi"]
     ximx = runs["mixed"]["xi"]
@@ -169,14 +182,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "delta": delta, "precision": head, "active_systems": h["active"],
-                   "systems": p.n_omega * p.px * p.py, "n": p.nz, "plan_ms": h["plan_ms"]},
+                   "systems": p.n_omega * p.px * p.py, "n": p.nz, "plan_ms": h["plan_ms"],
+                   "tune_ms": h["tune_ms"], "schedule": h["tuning"]},
         "roofline": h["roofline"],
+        "fft_stages": h["fft_stages"],
+        "hbm_stages": h["hbm_stages"],
         "stages_ms_per_step": h["stages"],
         "fp64": {"value": vf / (runs["fp64"]["ms"] * 1e-3), "ms_per_step": runs["fp64"]["ms"],
-                 "xi_rel_l2_vs_oracle": runs["fp64"].get("vs_oracle")},
+                 "xi_rel_l2_vs_oracle": runs["fp64"].get("vs_oracle"),
+                 "schedule": runs["fp64"]["tuning"], "fft_stages": runs["fp64"]["fft_stages"],
+                 "roofline": runs["fp64"]["roofline"]},
         "mixed": {"value": vf / (runs["mixed"]["ms"] * 1e-3), "ms_per_step": runs["mixed"]["ms"],
                   "xi_rel_l2_vs_fp64_gpu": mixed_vs_fp64,
-                  "xi_rel_l2_vs_oracle": runs["mixed"].get("vs_oracle")},
+                  "xi_rel_l2_vs_oracle": runs["mixed"].get("vs_oracle"),
+                  "schedule": runs["mixed"]["tuning"], "fft_stages": runs["mixed"]["fft_stages"],
+                  "roofline": runs["mixed"]["roofline"]},
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
@@ -190,6 +210,12 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
     xi = torch.empty((p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+    tune_ms = 0.0
+    if args.tune:
+        t0 = time.perf_counter()
+        plan.tune(Wd, u0, delta, reps=3)
+        tune_ms = 1e3 * (time.perf_counter() - t0)
+    tuning = dict(plan.tuning(), schedule=plan.tuning_variants()[plan.tuning()["bidiag_variant"]])
     for _ in range(args.warmup):
         plan.invert(Wd, u0, delta, xi)
     torch.cuda.synchronize()
@@ -225,7 +251,20 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": None, "kernel": dom,
             "avg_launch_ms": per_launch_ms}
-    out = {"ms": ms, "plan_ms": plan_ms, "active": active, "roofline": roof,
+    # HBM-bound stages: algorithmic bytes / event-timed stage duration
+    hbm = {}
+    for k, (sms, cnt) in stages.items():
+        uu, wk = units.get(k, ("", 0))
+        if uu == "GB/s" and wk and sms > 0:
+            gbs = wk * args.steps / (sms * 1e-3) / 1e9
+            hbm[k] = {"GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 3)}
+    fb = sum(units[k][1] for k in FFT_STAGES) * args.steps
+    fms = sum(stages[k][0] for k in FFT_STAGES)
+    fft_all = {"GB/s": round(fb / (fms * 1e-3) / 1e9, 1),
+               "frac": round(fb / (fms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
+               "ms_per_step": fms / args.steps}
+    out = {"ms": ms, "plan_ms": plan_ms, "tune_ms": tune_ms, "tuning": tuning,
+           "hbm_stages": hbm, "fft_stages": fft_all, "active": active, "roofline": roof,
            "stages": {k: v[0] / args.steps for k, v in stages.items()},
            "xi": xi.cpu().numpy()}
     plan.close()

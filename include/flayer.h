@@ -247,6 +247,36 @@ fl_status fl_batch_invert(fl_batch *batch, const void *const *W, const void *con
                           const double *delta, void *const *xi_out);
 void fl_batch_destroy(fl_batch *batch);
 
+/*
+ * Launch schedule of the per-system solver, and its autotuner (a project-
+ * written search over schedules timed on the caller's own data).
+ *   bidiag_variant  bidiagonalization schedule, 0 .. fl_tuning_variants() - 1:
+ *                   a TR x TC thread grid per system (each thread holds an
+ *                   (n/TR) x (n/TC) block of the matrix in registers) and a
+ *                   waves-per-SIMD register budget (fl_tuning_describe)
+ *   bidiag_grid     workgroups of the persistent bidiagonalization launch
+ *                   (0 = 8192 for n <= 64, else 2048)
+ *   dp_grid         one-wave workgroups of the discrepancy launch (0 = 16384)
+ * Schedules sum in different orders, so their results agree to rounding, not
+ * bitwise; a plan starts with schedule {0, 0, 0}.
+ */
+typedef struct {
+  int bidiag_variant, bidiag_grid, dp_grid;
+} fl_tuning;
+fl_status fl_tuning_get(const fl_plan *plan, fl_tuning *t);
+fl_status fl_tuning_set(fl_plan *plan, const fl_tuning *t); /* FL_EINVAL if out of range */
+int fl_tuning_variants(const fl_plan *plan);                 /* 0 for a NULL plan */
+fl_status fl_tuning_describe(const fl_plan *plan, int variant, int *tr, int *tc,
+                             int *waves_per_simd);
+/* Autotune: one fl_invert(plan, W, u0, delta, xi_scratch) to classify the
+ * systems, then every schedule candidate timed with HIP events over `reps`
+ * solver launches on the first chunk; the fastest is kept in the plan and
+ * copied to *chosen (nullable). xi_scratch: device buffer shaped like
+ * fl_invert's xi_out (its contents are an inversion result afterwards).
+ * Synchronizes the plan's stream. */
+fl_status fl_plan_tune(fl_plan *plan, const void *W, const void *u0, double delta, int reps,
+                       void *xi_scratch, fl_tuning *chosen);
+
 /* Free a plan and everything it owns (NULL is a no-op). */
 void fl_plan_destroy(fl_plan *plan);
 

@@ -369,8 +369,13 @@ __host__ __device__ constexpr bool p2_supported(int L) {
 
 // one pad slot after every 16 elements keeps strided scatters off one bank
 __device__ __forceinline__ int p2pad(int x) { return x + (x >> 4); }
+// Row pitch of a transform in LDS: the padded length rounded up to 1 mod 32
+// elements, so that consecutive transforms (the lanes of a column map) start
+// on different banks.
 template <int L>
-__host__ __device__ constexpr int p2_row() { return L + L / 16; }
+__host__ __device__ constexpr int p2_row() {
+  return L + L / 16 + (((1 - (L + L / 16)) % 32) + 32) % 32;
+}
 
 // Transforms per workgroup: up to 512 threads and 64 KiB of LDS (twiddles
 // plus one padded row per transform).

@@ -86,6 +86,8 @@ struct fl_plan {
   int nb_scan = 0;
   // solver chunk
   int C = 0;
+  // launch schedule (fl_tuning): bidiagonalization variant and grid sizes
+  int bd_var = 0, bd_grid = 0, dp_grid = 0;
   z64 *dg = nullptr, *sp = nullptr, *q = nullptr, *refl = nullptr;
   double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
   double *bd_d = nullptr, *bd_e = nullptr;
@@ -316,26 +318,90 @@ fl_status mark(fl_plan* p, int s) {
   return FL_OK;
 }
 
+// Bidiagonalization schedules per system size n: thread grid TR x TC (each
+// thread holds an (n/TR) x (n/TC) block of the 2D-cyclic matrix layout) and
+// the waves-per-SIMD hint given to the register allocator. Different grids
+// sum in different orders, so results agree to rounding, not bitwise.
+struct BdVariant {
+  int tr, tc, wpe;
+};
+const std::vector<BdVariant>& bd_variants(int n) {
+  static const std::vector<BdVariant> v16{{16, 4, 1}};
+  static const std::vector<BdVariant> v32{{16, 8, 1}, {16, 4, 1}, {16, 4, 2}};
+  static const std::vector<BdVariant> v48{{16, 8, 2}, {16, 16, 1}, {16, 8, 1}};
+  static const std::vector<BdVariant> v64{{16, 8, 2}, {16, 16, 3}, {16, 16, 2}, {16, 8, 1}};
+  static const std::vector<BdVariant> v80{{16, 16, 1}, {16, 8, 1}};
+  static const std::vector<BdVariant> v96{{16, 16, 1}, {32, 16, 1}};
+  static const std::vector<BdVariant> v128{{32, 16, 1}, {32, 32, 1}};
+  static const std::vector<BdVariant> none{};
+  switch (n) {
+    case 16: return v16;
+    case 32: return v32;
+    case 48: return v48;
+    case 64: return v64;
+    case 80: return v80;
+    case 96: return v96;
+    case 128: return v128;
+    default: return none;
+  }
+}
+
 template <typename T>
 fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   const int n = p->n;
   const cx<T>* What = (const cx<T>*)p->What;
-#define BD(TR, TC, NA, NB, WPE)                                                          \
-  hipLaunchKernelGGL((k_bidiag<TR, TC, NA, NB, T, WPE>), dim3(grid), dim3(TR * TC), 0, p->st, \
-                     p->gsys, p->TP, What, p->N, p->list, p->count, chunk0, p->C, o)
+  const auto& vs = bd_variants(n);
+  if (p->bd_var < 0 || p->bd_var >= (int)vs.size())
+    return fail(FL_EUNSUPPORTED, "nz = %d has no solver schedule %d", n, p->bd_var);
+  const BdVariant v = vs[p->bd_var];
+#define BD(TR, TC, WPE)                                                                     \
+  if (v.tr == TR && v.tc == TC && v.wpe == WPE) {                                           \
+    hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, T, WPE>), dim3(grid), dim3(TR * TC), 0, \
+                       p->st, p->gsys, p->TP, What, p->N, p->list, p->count, chunk0, p->C, o); \
+    LAUNCHCHK();                                                                            \
+    return FL_OK;                                                                           \
+  }
   switch (n) {
-    case 16: BD(16, 4, 1, 4, 1); break;
-    case 32: BD(16, 8, 2, 4, 1); break;
-    case 48: BD(16, 16, 3, 3, 1); break;
-    case 64: BD(16, 16, 4, 4, 3); break;  // 168 VGPRs: three waves per SIMD measured fastest
-    case 80: BD(16, 16, 5, 5, 1); break;
-    case 96: BD(16, 16, 6, 6, 1); break;
-    case 128: BD(32, 16, 4, 8, 1); break;
-    default: return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
+    case 16: {
+      constexpr int NN = 16;
+      BD(16, 4, 1)
+      break;
+    }
+    case 32: {
+      constexpr int NN = 32;
+      BD(16, 8, 1) BD(16, 4, 1) BD(16, 4, 2)
+      break;
+    }
+    case 48: {
+      constexpr int NN = 48;
+      BD(16, 8, 2) BD(16, 16, 1) BD(16, 8, 1)
+      break;
+    }
+    case 64: {
+      constexpr int NN = 64;
+      BD(16, 8, 2) BD(16, 16, 3) BD(16, 16, 2) BD(16, 8, 1)
+      break;
+    }
+    case 80: {
+      constexpr int NN = 80;
+      BD(16, 16, 1) BD(16, 8, 1)
+      break;
+    }
+    case 96: {
+      constexpr int NN = 96;
+      BD(16, 16, 1) BD(32, 16, 1)
+      break;
+    }
+    case 128: {
+      constexpr int NN = 128;
+      BD(32, 16, 1) BD(32, 32, 1)
+      break;
+    }
+    default:
+      break;
   }
 #undef BD
-  LAUNCHCHK();
-  return FL_OK;
+  return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
 }
 
 // Classification, compaction of the systems that need a solve, and the
@@ -360,13 +426,20 @@ fl_status solve_prepare(fl_plan* p) {
   return FL_OK;
 }
 
-// Bidiagonalization and discrepancy solve of compacted systems
-// [c0, c0 + C); leaves their factorization in the chunk workspace.
+// Bidiagonalization of compacted systems [c0, c0 + C) into the chunk
+// workspace (reflectors, bidiagonal, q = U^H w, ||A||_F^2).
 template <typename T>
-fl_status solve_chunk(fl_plan* p, long c0) {
-  const int n = p->n;
-  hipStream_t st = p->st;
+fl_status run_bidiag(fl_plan* p, long c0) {
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam};
+  const long gdef = p->n <= 64 ? 8192 : 2048;
+  const unsigned gb = (unsigned)std::min<long>(p->C, p->bd_grid > 0 ? p->bd_grid : gdef);
+  RUN(mark(p, FL_STAGE_BIDIAG));
+  return launch_bidiag<T>(p, (int)c0, gb, o);
+}
+
+// Discrepancy root, Tikhonov solve and back-transform of the same chunk.
+template <typename T>
+fl_status run_dp(fl_plan* p, long c0) {
   DpArgs a{};
   a.dg = p->dg;
   a.sp = p->sp;
@@ -375,7 +448,7 @@ fl_status solve_chunk(fl_plan* p, long c0) {
   a.list = p->list;
   a.count = p->count;
   a.C = p->C;
-  a.n = n;
+  a.n = p->n;
   a.N = p->N;
   a.thr2 = p->thr2;
   a.eta = p->opts.eta;
@@ -389,17 +462,22 @@ fl_status solve_chunk(fl_plan* p, long c0) {
   a.bd_e = p->bd_e;
   a.bd_dr = p->bd_dr;
   a.chunk0 = (int)c0;
-  const unsigned gb = (unsigned)std::min<long>(p->C, 2048);
-  const unsigned gd = (unsigned)std::min<long>(p->C, 8192);
-  RUN(mark(p, FL_STAGE_BIDIAG));
-  RUN(launch_bidiag<T>(p, (int)c0, gb, o));
+  const unsigned gd = (unsigned)std::min<long>(p->C, p->dp_grid > 0 ? p->dp_grid : 16384);
   RUN(mark(p, FL_STAGE_DP));
-  if (n <= 64)
-    hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, st, a);
+  if (p->n <= 64)
+    hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, p->st, a);
   else
-    hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, p->st, a);
   LAUNCHCHK();
   return FL_OK;
+}
+
+// Both solver launches for compacted systems [c0, c0 + C); leaves their
+// factorization in the chunk workspace.
+template <typename T>
+fl_status solve_chunk(fl_plan* p, long c0) {
+  RUN(run_bidiag<T>(p, c0));
+  return run_dp<T>(p, c0);
 }
 
 template <typename T>
@@ -552,12 +630,12 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   {
     dim3 g(256, F);
     if (p->opts.input_dtype == 0)
-      hipLaunchKernelGGL(k_sumsq<double>, g, dim3(256), 0, st, (const z64*)W, (long)nd * N, p->partial);
+      hipLaunchKernelGGL(k_sumsq<double>, g, dim3(1024), 0, st, (const z64*)W, (long)nd * N, p->partial);
     else
-      hipLaunchKernelGGL(k_sumsq<float>, g, dim3(256), 0, st, (const z32*)W, (long)nd * N, p->partial);
+      hipLaunchKernelGGL(k_sumsq<float>, g, dim3(1024), 0, st, (const z32*)W, (long)nd * N, p->partial);
     LAUNCHCHK();
     double td = p->opts.tau * delta;
-    hipLaunchKernelGGL(k_thresholds, dim3(1), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
+    hipLaunchKernelGGL(k_thresholds, dim3(F), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
                        p->norm2);
     LAUNCHCHK();
   }
@@ -773,6 +851,62 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   return FL_OK;
 }
 
+}  // namespace
+
+namespace {
+template <typename T>
+fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const bool prof = p->prof;
+  p->prof = false;
+  auto time_it = [&](auto&& launch, float* ms) -> fl_status {
+    RUN(launch());  // warm-up
+    HIPCHK(hipEventRecord(e0, p->st));
+    for (int r = 0; r < reps; ++r) RUN(launch());
+    HIPCHK(hipEventRecord(e1, p->st));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    return FL_OK;
+  };
+  fl_status st = FL_OK;
+  float bt = 1e30f;
+  const int grids[] = {1024, 2048, 4096, 8192};
+  const int nv = (int)bd_variants(p->n).size();
+  for (int v = 0; v < nv && st == FL_OK; ++v)
+    for (int g : grids) {
+      p->bd_var = v;
+      p->bd_grid = g;
+      float ms = 0.f;
+      st = time_it([&] { return run_bidiag<T>(p, 0); }, &ms);
+      if (st != FL_OK) break;
+      if (ms < bt) {
+        bt = ms;
+        best->bidiag_variant = v;
+        best->bidiag_grid = g;
+      }
+    }
+  p->bd_var = best->bidiag_variant;
+  p->bd_grid = best->bidiag_grid;
+  float dt = 1e30f;
+  const int dgrids[] = {4096, 8192, 16384};
+  for (int g : dgrids) {
+    if (st != FL_OK) break;
+    p->dp_grid = g;
+    float ms = 0.f;
+    st = time_it([&] { return run_dp<T>(p, 0); }, &ms);
+    if (st == FL_OK && ms < dt) {
+      dt = ms;
+      best->dp_grid = g;
+    }
+  }
+  p->dp_grid = best->dp_grid;
+  p->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
 }  // namespace
 
 extern "C" {
@@ -1112,6 +1246,59 @@ fl_status fl_plan_refresh_info(fl_plan* p) {
   HIPCHK(hipMemcpyAsync(&c, p->count, sizeof(int), hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipStreamSynchronize(p->st));
   p->last_active = c;
+  return FL_OK;
+}
+
+fl_status fl_tuning_get(const fl_plan* p, fl_tuning* t) {
+  if (!p || !t) return fail(FL_EINVAL, "NULL argument");
+  t->bidiag_variant = p->bd_var;
+  t->bidiag_grid = p->bd_grid;
+  t->dp_grid = p->dp_grid;
+  return FL_OK;
+}
+
+fl_status fl_tuning_set(fl_plan* p, const fl_tuning* t) {
+  if (!p || !t) return fail(FL_EINVAL, "NULL argument");
+  const int nv = (int)bd_variants(p->n).size();
+  if (t->bidiag_variant < 0 || t->bidiag_variant >= nv)
+    return fail(FL_EINVAL, "bidiag_variant %d out of range [0, %d)", t->bidiag_variant, nv);
+  if (t->bidiag_grid < 0 || t->dp_grid < 0) return fail(FL_EINVAL, "grid sizes must be >= 0");
+  p->bd_var = t->bidiag_variant;
+  p->bd_grid = t->bidiag_grid;
+  p->dp_grid = t->dp_grid;
+  return FL_OK;
+}
+
+int fl_tuning_variants(const fl_plan* p) { return p ? (int)bd_variants(p->n).size() : 0; }
+
+fl_status fl_tuning_describe(const fl_plan* p, int variant, int* tr, int* tc, int* wps) {
+  if (!p || !tr || !tc || !wps) return fail(FL_EINVAL, "NULL argument");
+  const auto& vs = bd_variants(p->n);
+  if (variant < 0 || variant >= (int)vs.size()) return fail(FL_EINVAL, "variant out of range");
+  *tr = vs[variant].tr;
+  *tc = vs[variant].tc;
+  *wps = vs[variant].wpe;
+  return FL_OK;
+}
+
+
+fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, int reps,
+                       void* xi_scratch, fl_tuning* chosen) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!W || !u0 || !xi_scratch) return fail(FL_EINVAL, "NULL array argument");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  if (reps < 1) reps = 1;
+  fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid};
+  RUN(fl_invert(p, W, u0, delta, xi_scratch));
+  fl_tuning best = keep;
+  fl_status s = p->prec ? tune_impl<float>(p, reps, &best) : tune_impl<double>(p, reps, &best);
+  if (s != FL_OK) {
+    p->bd_var = keep.bidiag_variant;
+    p->bd_grid = keep.bidiag_grid;
+    p->dp_grid = keep.dp_grid;
+    return s;
+  }
+  if (chosen) *chosen = best;
   return FL_OK;
 }
 

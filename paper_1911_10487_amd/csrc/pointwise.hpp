@@ -76,28 +76,49 @@ __global__ __launch_bounds__(256) void k_to_sys(const cx<T>* __restrict__ in, z6
 
 // per-frequency partial sums of |W|^2: grid (nb, F), partial[f * nb + b]
 template <typename TI>
-__global__ __launch_bounds__(256) void k_sumsq(const cx<TI>* __restrict__ W, long per_f,
-                                               double* __restrict__ partial) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(1024) void k_sumsq(const cx<TI>* __restrict__ W, long per_f,
+                                                double* __restrict__ partial) {
+  __shared__ double red[16];
   const int f = blockIdx.y, nb = gridDim.x;
   const cx<TI>* w = W + (long)f * per_f;
-  double s = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per_f; i += (long)nb * blockDim.x) {
-    cx<TI> v = w[i];
-    s = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, s));
+  // four independent loads in flight per thread and iteration
+  constexpr int U = 4;
+  const long stride = (long)nb * blockDim.x;
+  double s[U] = {0.0, 0.0, 0.0, 0.0};
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < per_f; i += U * stride) {
+    cx<TI> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = w[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = fma((double)v[u].x, (double)v[u].x, fma((double)v[u].y, (double)v[u].y, s[u]));
   }
-  s = group_sum<64>(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  for (; i < per_f; i += stride) {
+    const cx<TI> v = w[i];
+    s[0] = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, s[0]));
+  }
+  double t = (s[0] + s[1]) + (s[2] + s[3]);
+  t = group_sum<64>(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) partial[f * nb + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) a += red[k];
+    partial[f * nb + blockIdx.x] = a;
+  }
 }
 
-// thr2[f] = (tau delta)^2 ||W_f||^2, or -1 for noise-free data
-__global__ void k_thresholds(const double* __restrict__ partial, int nb, int F, double td2,
-                             double* __restrict__ thr2, double* __restrict__ norm2) {
-  for (int f = threadIdx.x; f < F; f += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[f * nb + b];
+// thr2[f] = (tau delta)^2 ||W_f||^2, or -1 for noise-free data. One wave per
+// frequency: strided partial sums, then a fixed-order lane reduction.
+__global__ __launch_bounds__(64) void k_thresholds(const double* __restrict__ partial, int nb, int F,
+                                                   double td2, double* __restrict__ thr2,
+                                                   double* __restrict__ norm2) {
+  const int f = blockIdx.x;
+  if (f >= F) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 64) s += partial[f * nb + b];
+  s = group_sum<64>(s);
+  if (threadIdx.x == 0) {
     norm2[f] = s;
     thr2[f] = td2 > 0.0 ? td2 * s : -1.0;
   }

@@ -36,11 +36,22 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   int f = (int)(fm / N);
   long m = fm - (long)f * N;
   const cx<T>* w = What + (long)f * nd * N + m;
-  double s = 0.0;
-  for (int j = 0; j < nd; ++j) {
-    cx<T> v = w[(long)j * N];
-    s = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, s));
+  // eight loads in flight, four partial sums
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = 0;
+  for (; j + 8 <= nd; j += 8) {
+    cx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = w[(long)(j + u) * N];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      s4[u & 3] = fma((double)v[u].x, (double)v[u].x, fma((double)v[u].y, (double)v[u].y, s4[u & 3]));
   }
+  for (; j < nd; ++j) {
+    const cx<T> v = w[(long)j * N];
+    s4[0] = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, s4[0]));
+  }
+  const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   wn2[fm] = s;
   // thr2[f] < 0 marks noise-free data: every nonzero system is solved
   double t = thr2[f];
@@ -144,6 +155,7 @@ struct BdShared {
   z64 zp[2][NW][n];   // per-wave partial z = A v
   double lg[2];       // left gamma
   z64 dg[n], sp[n];
+  z64 qv[n];          // q = U^H w (row i kept by the column-class-0 thread of row class i % TR)
   double gm[n];
   double red[2][NW];
 };
@@ -153,7 +165,7 @@ struct BdShared {
 // rows / columns for every k of the current block and are skipped at compile
 // time; the partially finished slots keep per-element tests.
 template <int TR, int TC, int NA, int NB, int SA, int SB>
-__device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShared<TR * NA, (TR * TC + 63) / 64>& S,
+__device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR * TC + 63) / 64>& S,
                                         int k, int r, int c, int tid, int lane, int wv) {
   constexpr int n = TR * NA;
   constexpr int NW = (TR * TC + 63) / 64;
@@ -230,14 +242,17 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
       }
     }
     if (c == 0) {
+      z64 qa[NA];
+#pragma unroll
+      for (int a = SA; a < NA; ++a) qa[a] = S.qv[r + TR * a];
       z64 sm = mk(0.0, 0.0);
 #pragma unroll
-      for (int a = SA; a < NA; ++a) sm = cfmac(sm, ur[a], qr[a]);
+      for (int a = SA; a < NA; ++a) sm = cfmac(sm, ur[a], qa[a]);
       sm.x = lanes_sum<TR>(sm.x);
       sm.y = lanes_sum<TR>(sm.y);
       sm = g * sm;
 #pragma unroll
-      for (int a = SA; a < NA; ++a) qr[a] = cfms(qr[a], ur[a], sm);
+      for (int a = SA; a < NA; ++a) S.qv[r + TR * a] = cfms(qa[a], ur[a], sm);
     }
   }
   const int rk = n - k - 1;
@@ -325,7 +340,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], z64 (&qr)[NA], BdShare
 
 // Steps of k-block Q (KB = max(TR, TC) consecutive k), then the next block.
 template <int TR, int TC, int NA, int NB, int Q>
-__device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB], z64 (&qr)[NA],
+__device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB],
                                           BdShared<TR * NA, (TR * TC + 63) / 64>& S, int r, int c,
                                           int tid, int lane, int wv) {
   constexpr int n = TR * NA;
@@ -333,8 +348,8 @@ __device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB], z64 (&qr)[NA],
   if constexpr (Q * KB < n) {
     constexpr int SA = Q * KB / TR, SB = Q * KB / TC;
     for (int k = Q * KB; k < (Q + 1) * KB && k < n; ++k)
-      bd_step<TR, TC, NA, NB, SA, SB>(A, qr, S, k, r, c, tid, lane, wv);
-    bd_blocks<TR, TC, NA, NB, Q + 1>(A, qr, S, r, c, tid, lane, wv);
+      bd_step<TR, TC, NA, NB, SA, SB>(A, S, k, r, c, tid, lane, wv);
+    bd_blocks<TR, TC, NA, NB, Q + 1>(A, S, r, c, tid, lane, wv);
   }
 }
 
@@ -377,15 +392,14 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
         A[a][b] = S.tb[i - j + n - 1];
         fr += nrm2(A[a][b]);
       }
-    // q = U^H w lives with the column-class-0 threads, rows r + TR a
-    z64 qr[NA];
+    // q = U^H w (starts as w), rows r + TR a kept by the column-class-0 threads
     double wq = 0.0;
+    if (c == 0) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      qr[a] = mk(0.0, 0.0);
-      if (c == 0) {
-        qr[a] = cast<double>(What[((long)f * n + r + TR * a) * N + m]);
-        wq += nrm2(qr[a]);
+      for (int a = 0; a < NA; ++a) {
+        const z64 w = cast<double>(What[((long)f * n + r + TR * a) * N + m]);
+        S.qv[r + TR * a] = w;
+        wq += nrm2(w);
       }
     }
     fr = lanes_sum<64>(fr);
@@ -405,7 +419,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
       o.wn2[sl] = s1;
     }
 
-    bd_blocks<TR, TC, NA, NB, 0>(A, qr, S, r, c, tid, lane, wv);
+    bd_blocks<TR, TC, NA, NB, 0>(A, S, r, c, tid, lane, wv);
 
     __syncthreads();
     z64* refl = o.refl + (long)sl * n * n;
@@ -425,7 +439,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
     }
     if (c == 0) {
 #pragma unroll
-      for (int a = 0; a < NA; ++a) o.q[(long)(r + TR * a) * C + sl] = qr[a];
+      for (int a = 0; a < NA; ++a) o.q[(long)(r + TR * a) * C + sl] = S.qv[r + TR * a];
     }
     __syncthreads();
   }

@@ -40,6 +40,11 @@ class FlOpts(ctypes.Structure):
     ]
 
 
+class FlTuning(ctypes.Structure):
+    _fields_ = [("bidiag_variant", ctypes.c_int), ("bidiag_grid", ctypes.c_int),
+                ("dp_grid", ctypes.c_int)]
+
+
 class FlPlanInfo(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("nd", ctypes.c_int),
@@ -104,6 +109,18 @@ def lib():
     L.fl_batch_destroy.restype = None
     L.fl_plan_destroy.argtypes = [P]
     L.fl_plan_destroy.restype = None
+    TP = ctypes.POINTER(FlTuning)
+    L.fl_tuning_get.argtypes = [P, TP]
+    L.fl_tuning_get.restype = I
+    L.fl_tuning_set.argtypes = [P, TP]
+    L.fl_tuning_set.restype = I
+    L.fl_tuning_variants.argtypes = [P]
+    L.fl_tuning_variants.restype = I
+    IP = ctypes.POINTER(I)
+    L.fl_tuning_describe.argtypes = [P, I, IP, IP, IP]
+    L.fl_tuning_describe.restype = I
+    L.fl_plan_tune.argtypes = [P, P, P, D, I, P, TP]
+    L.fl_plan_tune.restype = I
     _lib = L
     return L
 
@@ -212,6 +229,68 @@ class Plan:
                                 ctypes.c_void_p(u0.data_ptr()), 0.0, 0,
                                 ctypes.c_void_p(W_out.data_ptr())))
         return W_out
+
+    # ---- launch schedule and autotuner
+
+    def tuning(self) -> dict:
+        t = FlTuning()
+        _check(lib().fl_tuning_get(self._h, ctypes.byref(t)))
+        return {"bidiag_variant": t.bidiag_variant, "bidiag_grid": t.bidiag_grid,
+                "dp_grid": t.dp_grid}
+
+    def set_tuning(self, bidiag_variant=0, bidiag_grid=0, dp_grid=0):
+        t = FlTuning(bidiag_variant, bidiag_grid, dp_grid)
+        _check(lib().fl_tuning_set(self._h, ctypes.byref(t)))
+
+    def tuning_variants(self):
+        """[(TR, TC, waves per SIMD)] of the bidiagonalization schedules."""
+        out = []
+        for v in range(lib().fl_tuning_variants(self._h)):
+            a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            _check(lib().fl_tuning_describe(self._h, v, ctypes.byref(a), ctypes.byref(b),
+                                            ctypes.byref(c)))
+            out.append((a.value, b.value, c.value))
+        return out
+
+    def tune(self, W, u0, delta, reps=3, cache_path=None):
+        """Run the autotuner on (W, u0, delta) and keep the fastest schedule.
+        With cache_path, a JSON file keyed by geometry, precision and device
+        is read first (a hit skips the timing) and updated after a search."""
+        import json
+
+        import torch
+        key = None
+        if cache_path is not None:
+            i = self.info()
+            key = (f"{torch.cuda.get_device_name(W.device)}|n{self.nz}|{self.px}x{self.py}"
+                   f"|F{self.n_omega}|p{i.precision}")
+            try:
+                with open(cache_path) as fh:
+                    cache = json.load(fh)
+            except (OSError, ValueError):
+                cache = {}
+            if key in cache:
+                self.set_tuning(**cache[key])
+                return self.tuning()
+        shape = (self.nz, self.ny, self.nx)
+        if self.combine == 1:
+            shape = (self.n_omega,) + shape
+        xi = torch.empty(shape, dtype=torch.complex128, device=W.device)
+        t = FlTuning()
+        _check(lib().fl_plan_tune(self._h, ctypes.c_void_p(W.data_ptr()),
+                                  ctypes.c_void_p(u0.data_ptr()), float(delta), int(reps),
+                                  ctypes.c_void_p(xi.data_ptr()), ctypes.byref(t)))
+        best = self.tuning()
+        if key is not None:
+            try:
+                with open(cache_path) as fh:
+                    cache = json.load(fh)
+            except (OSError, ValueError):
+                cache = {}
+            cache[key] = best
+            with open(cache_path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+        return best
 
     def tap(self, which, dtype, shape):
         out = np.empty(shape, dtype)

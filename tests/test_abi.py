@@ -77,3 +77,15 @@ def test_null_plan_is_rejected():
     assert L.fl_invert(None, None, None, 0.0, None) == flayer.FL_EINVAL
     assert "NULL" in L.fl_last_error().decode()
     L.fl_plan_destroy(None)  # no-op
+
+
+def test_tuning_calls_reject_null_arguments():
+    L = flayer.lib()
+    t = flayer.FlTuning()
+    assert L.fl_tuning_variants(None) == 0
+    assert L.fl_tuning_get(None, ctypes.byref(t)) == flayer.FL_EINVAL
+    assert L.fl_tuning_set(None, ctypes.byref(t)) == flayer.FL_EINVAL
+    i = ctypes.c_int()
+    assert L.fl_tuning_describe(None, 0, ctypes.byref(i), ctypes.byref(i),
+                                ctypes.byref(i)) == flayer.FL_EINVAL
+    assert L.fl_plan_tune(None, None, None, 0.0, 1, None, None) == flayer.FL_EINVAL

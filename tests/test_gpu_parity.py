@@ -247,3 +247,43 @@ def test_mixed_single_workload_full_size():
     e = mixed_errors(ref_xi, ref, xi_g, st)
     say("mixed single errors", e)
     assert e["xi"] <= MIXED_TOL
+
+
+def _born_data(p, delta):
+    W, _, _, _ = forward.synthesize(p, synth.contrast(p), synth.incident_field(p), born=True)
+    return synth.add_noise(p, W, delta), synth.incident_field(p)
+
+
+def test_every_solver_schedule_matches_oracle():
+    """Each bidiagonalization schedule (thread grid / register budget) and
+    a few grid sizes give the oracle's xi on the ragged two-frequency case;
+    the autotuner returns one of them and keeps it in the plan."""
+    import torch
+    from paper_1911_10487_amd.flayer import Plan
+    p = synth.make_problem("sched", 20, 12, 16, [2 * np.pi, 3 * np.pi], 3, (27, 0), (0.02,),
+                           px=40, py=30)
+    W, u0 = _born_data(p, 0.02)
+    ref = invert.invert(p, W, u0, 0.02)
+    for nz in (32, 48, 64):
+        q = synth.make_problem("sched", 12, 10, nz, [2 * np.pi], 2, (28, nz), (0.02,),
+                               px=24, py=20)
+        Wq, uq = _born_data(q, 0.02)
+        rq = invert.invert(q, Wq, uq, 0.02)
+        plan = Plan.from_problem(q)
+        for v in range(len(plan.tuning_variants())):
+            for g in (0, 1000):
+                plan.set_tuning(v, g, g)
+                got = plan.invert(torch.from_numpy(Wq).cuda(), torch.from_numpy(uq).cuda(),
+                                  0.02).cpu().numpy()
+                err = rel(got, rq)
+                say("schedule", nz, v, g, err)
+                assert err <= TOL
+        plan.close()
+    plan = Plan.from_problem(p)
+    Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    best = plan.tune(Wt, ut, 0.02, reps=1)
+    assert best == plan.tuning()
+    assert 0 <= best["bidiag_variant"] < len(plan.tuning_variants())
+    err = rel(plan.invert(Wt, ut, 0.02).cpu().numpy(), ref)
+    assert err <= TOL
+    plan.close()
