@@ -113,11 +113,14 @@ __device__ __forceinline__ double rsq_nr(double x) {
 
 // ---- cross-lane moves without the LDS crossbar (gfx950 DPP / permlane)
 
+// DPP read of another lane's value. Only permutations inside a row of 16 are
+// used (mirror, half-mirror, quad_perm), where every lane has a valid source,
+// so the move needs no "old" value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 

@@ -601,30 +601,43 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     double al = amin;
     signed char br = 1;
     if (T >= 0.0) {
-      // round 0: lane 0 tests the floor, lanes 1.. probe upward for phi >= T
-      double lo = log(amin);
+      // round 0: lane 0 tests the floor alpha_min; lanes 1..63 spread over
+      // (log alpha_min, log ||A||_F^2 + 1], where the root almost always is
       const double h0 = log(fro) + 1.0;
-      double x = lane == 0 ? lo : h0 + 4.0 * (lane - 1);
-      double ph = phi_fwd(sd, se, sq, n, exp(x));
+      double lo = log(amin);
+      const double st0 = (h0 - lo) / 63.0;
+      double ph = phi_fwd(sd, se, sq, n, exp(lane == 0 ? lo : lo + st0 * lane));
       unsigned long long bal = __ballot(ph >= T);
       if (!(bal & 1ull)) {
         br = 2;
         // bracket [lo, hi] on x = log(alpha) with phi(lo) < T <= phi(hi);
         // flo / fhi hold phi at the ends once known (NaN otherwise)
         const double nan = __longlong_as_double(0x7ff8000000000000ll);
-        unsigned long long up = bal & ~1ull;
-        double hi, flo = __shfl(ph, 0), fhi = nan;
-        if (up) {
-          const int l1 = __ffsll((long long)up) - 1;
-          hi = h0 + 4.0 * (l1 - 1);
+        double hi, flo, fhi = nan;
+        if (bal) {
+          const int l1 = __ffsll((long long)bal) - 1;
+          hi = lo + st0 * l1;
           fhi = __shfl(ph, l1);
-          if (l1 > 1) {
-            lo = h0 + 4.0 * (l1 - 2);
-            flo = __shfl(ph, l1 - 1);
-          }
+          lo = lo + st0 * (l1 - 1);
+          flo = __shfl(ph, l1 - 1);
         } else {
-          hi = h0 + 4.0 * 62;
-          lo = hi;
+          // the root lies above: probe upward in steps of 4
+          lo = h0;
+          flo = __shfl(ph, 63);
+          const double pu = phi_fwd(sd, se, sq, n, exp(h0 + 4.0 * (lane + 1)));
+          const unsigned long long bu = __ballot(pu >= T);
+          if (bu) {
+            const int l1 = __ffsll((long long)bu) - 1;
+            hi = h0 + 4.0 * (l1 + 1);
+            fhi = __shfl(pu, l1);
+            if (l1 > 0) {
+              lo = h0 + 4.0 * l1;
+              flo = __shfl(pu, l1 - 1);
+            }
+          } else {
+            hi = h0 + 4.0 * 64;
+            lo = hi;
+          }
         }
         // Multisection with 64 points per round. Once phi is known at both
         // ends, the points are packed around the secant estimate of the
@@ -638,7 +651,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
           double a0 = lo, a1 = hi;
           if (!miss && flo == flo && fhi == fhi && fhi > flo) {
             const double xs = lo + (T - flo) / (fhi - flo) * wdt;
-            const double hw = fmax(0.25 * wdt * wdt, 1e-3 * wdt);
+            const double hw = fmax(0.25 * wdt * wdt, 1e-5 * wdt);
             a0 = fmax(lo, xs - hw);
             a1 = fmin(hi, xs + hw);
           }
