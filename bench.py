@@ -68,6 +68,28 @@ FFT_STAGES = ("fft_rows", "fft_cols", "ifft_cols", "crop_pad", "conv_cols", "con
               "conv_icols", "conv_irows")
 
 
+PROFILE_COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                "counters_single_128x128x64.json")
+
+
+def profiled_traffic(workload, prec, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE profile of this workload (already scaled by the calibration
+    factors), or None when there is none or the HIP sources changed since."""
+    from paper_1911_10487_amd.build import source_sha256
+    if workload != "single" or not os.path.exists(PROFILE_COUNTERS):
+        return None
+    with open(PROFILE_COUNTERS) as fh:
+        js = json.load(fh)
+    if js.get("source_sha256") != source_sha256():
+        return None
+    k = js.get("kernels", {}).get("mixed" if prec else "fp64", {}).get(kernel)
+    if not k:
+        return None
+    return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "profiled_avg_us": k["avg_us"]}
+
+
 def cpu_baseline(p, Wd, u0, delta, vf):
     from threadpoolctl import threadpool_info
 
@@ -248,9 +270,18 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
     else:
         achieved = work_per_launch / (per_launch_ms * 1e-3) / 1e12
         peak, bound = PEAK_FP64_VALU_TFLOPS, "alu"
+    kname = dom
+    if dom == "bidiag":
+        tr, tc, wpe = tuning["schedule"]
+        kname = (f"k_bidiag<{tr}, {tc}, {p.nz // tr}, {p.nz // tc}, "
+                 f"{'float' if prec else 'double'}, {wpe}>")
+    tr_ = profiled_traffic(args.workload, prec, kname)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel": dom,
-            "avg_launch_ms": per_launch_ms}
+            "frac": achieved / peak, "traffic": tr_["bytes"] if tr_ else None,
+            "kernel": kname, "avg_launch_ms": per_launch_ms}
+    if tr_:
+        roof["traffic_detail"] = dict(tr_, source=os.path.relpath(PROFILE_COUNTERS,
+                                                                   os.path.dirname(PROFILE_COUNTERS) + "/.."))
     # HBM-bound stages: algorithmic bytes / event-timed stage duration
     hbm = {}
     for k, (sms, cnt) in stages.items():

@@ -21,6 +21,22 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_sha256() -> str:
+    """Digest of the HIP sources and the C header (names and contents): a
+    stored profile of a kernel stays valid while this digest is unchanged."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(PKG, "csrc", "*.hip")) +
+                   glob.glob(os.path.join(PKG, "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "flayer.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = OUT + ".tmp"

@@ -137,9 +137,9 @@ __global__ __launch_bounds__(1024) void k_scatter(const int* __restrict__ flag, 
 // ---------------------------------------------------------------- bidiag
 
 struct BidiagOut {
-  z64* dg;      // [n][C] diagonal of B (complex)
-  z64* sp;      // [n][C] superdiagonal of B (complex; entry n-1 unused)
-  z64* q;       // [n][C] U^H w
+  z64* dg;      // [C][n] diagonal of B (complex)
+  z64* sp;      // [C][n] superdiagonal of B (complex; entry n-1 unused)
+  z64* q;       // [C][n] U^H w
   double* fro;  // [C] ||A||_F^2
   double* wn2;  // [C] ||w||^2
   z64* refl;    // [C][n][n] right reflector k in row k, entries k+1..n-1
@@ -434,12 +434,12 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
       }
     for (int t = tid; t < n; t += NT) {
       gam[t] = S.gm[t];
-      o.dg[(long)t * C + sl] = S.dg[t];
-      o.sp[(long)t * C + sl] = (t < n - 1) ? S.sp[t] : mk(0.0, 0.0);
+      o.dg[(long)sl * n + t] = S.dg[t];
+      o.sp[(long)sl * n + t] = (t < n - 1) ? S.sp[t] : mk(0.0, 0.0);
     }
     if (c == 0) {
 #pragma unroll
-      for (int a = 0; a < NA; ++a) o.q[(long)(r + TR * a) * C + sl] = S.qv[r + TR * a];
+      for (int a = 0; a < NA; ++a) o.q[(long)sl * n + r + TR * a] = S.qv[r + TR * a];
     }
     __syncthreads();
   }
@@ -448,9 +448,9 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
 // ---------------------------------------------------------------- dp
 
 struct DpArgs {
-  const z64* dg;       // [n][C] bidiagonal of A (complex)
+  const z64* dg;       // [C][n] bidiagonal of A (complex)
   const z64* sp;
-  const z64* q;        // [n][C] U^H w
+  const z64* q;        // [C][n] U^H w
   const double* fro;   // [C]
   const int* list;
   const int* count;
@@ -551,7 +551,6 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
   __shared__ double sx[2];
   const int lane = threadIdx.x;
   const int n = a.n;
-  const long C = a.C;
   const int total = *a.count;
   for (int sl = blockIdx.x; sl < a.C; sl += gridDim.x) {
     const int gs = a.chunk0 + sl;
@@ -561,9 +560,9 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     const long m = fm - (long)f * a.N;
     // stage the complex bidiagonal and q
     for (int i = lane; i < n; i += 64) {
-      sy[i] = a.dg[i * C + sl];
-      srr[i] = a.sp[i * C + sl];
-      sq[i] = a.q[i * C + sl];
+      sy[i] = a.dg[(long)sl * n + i];
+      srr[i] = a.sp[(long)sl * n + i];
+      sq[i] = a.q[(long)sl * n + i];
     }
     __syncthreads();
     // B = D_L B' D_R^H with B' real nonnegative (sequential phase chain)
