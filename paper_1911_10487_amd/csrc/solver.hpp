@@ -565,26 +565,81 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       sq[i] = a.q[(long)sl * n + i];
     }
     __syncthreads();
-    // B = D_L B' D_R^H with B' real nonnegative (sequential phase chain)
-    if (lane == 0) {
-      z64 drc = mk(1.0, 0.0);
-      for (int i = 0; i < n; ++i) {
-        const z64 t = sy[i] * drc;
-        const double t2 = nrm2(t);
-        const double it = t2 > 0.0 ? rsq_nr(t2) : 0.0;
-        const double at = t2 * it;
-        const z64 dl = t2 > 0.0 ? mk(t.x * it, t.y * it) : mk(1.0, 0.0);
-        sd[i] = at;
-        sdr[i] = drc;
-        sq[i] = cmulc(dl, sq[i]);
-        if (i < n - 1) {
-          const z64 s = cmulc(dl, srr[i]);
-          const double s2 = nrm2(s);
-          const double is = s2 > 0.0 ? rsq_nr(s2) : 0.0;
-          se[i] = s2 * is;
-          drc = s2 > 0.0 ? mk(s.x * is, -s.y * is) : mk(1.0, 0.0);
-        } else {
-          se[i] = 0.0;
+    // B = D_L B' D_R^H with B' real nonnegative. The right phases obey
+    // r_i = rho_i r_{i-1} (or restart at a zero entry), an affine recurrence
+    // evaluated by a parallel prefix over the lanes (elements lane, lane + 64).
+    {
+      z64 ra[2], rb[2], pd[2];
+      bool dz[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        z64 am = mk(1.0, 0.0), bm = mk(0.0, 0.0), ph = mk(1.0, 0.0);
+        dz[h] = true;
+        if (i < n) {
+          const z64 dgi = sy[i];
+          const double d2 = nrm2(dgi);
+          const double idd = d2 > 0.0 ? rsq_nr(d2) : 0.0;
+          sd[i] = d2 * idd;
+          dz[h] = !(d2 > 0.0);
+          if (d2 > 0.0) ph = mk(dgi.x * idd, dgi.y * idd);
+          z64 cs = mk(1.0, 0.0);  // conj(phase(sp_i))
+          double ei = 0.0;
+          if (i < n - 1) {
+            const z64 spi = srr[i];
+            const double s2 = nrm2(spi);
+            const double is = s2 > 0.0 ? rsq_nr(s2) : 0.0;
+            ei = s2 * is;
+            if (s2 > 0.0) cs = mk(spi.x * is, -spi.y * is);
+            if (!(s2 > 0.0)) {
+              am = mk(0.0, 0.0);
+              bm = mk(1.0, 0.0);
+            } else if (!(d2 > 0.0)) {
+              am = mk(0.0, 0.0);
+              bm = cs;
+            } else {
+              am = ph * cs;
+            }
+          }
+          se[i] = ei;
+        }
+        pd[h] = ph;
+        ra[h] = am;
+        rb[h] = bm;
+      }
+      // inclusive scan of x -> a x + b within each half (Hillis-Steele)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const double ax = __shfl_up(ra[h].x, o), ay = __shfl_up(ra[h].y, o);
+          const double bx = __shfl_up(rb[h].x, o), by = __shfl_up(rb[h].y, o);
+          if (lane >= o) {
+            // (a, b) o (a', b') = (a a', a b' + b)
+            const z64 ap = mk(ax, ay), bp = mk(bx, by);
+            rb[h] = cfma(rb[h], ra[h], bp);
+            ra[h] = ra[h] * ap;
+          }
+        }
+      }
+      // right phase entering element i: x_{i-1}, with x_{-1} = 1
+      const z64 x0 = ra[0] + rb[0];                       // x_lane
+      const z64 end0 = mk(__shfl(x0.x, 63), __shfl(x0.y, 63));
+      const z64 x1 = cfma(rb[1], ra[1], end0);            // x_{lane+64}
+      z64 in0 = mk(__shfl_up(x0.x, 1), __shfl_up(x0.y, 1));
+      z64 in1 = mk(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));
+      if (lane == 0) {
+        in0 = mk(1.0, 0.0);
+        in1 = end0;
+      }
+      const z64 xin[2] = {in0, in1};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        if (i < n) {
+          sdr[i] = xin[h];
+          const z64 dl = dz[h] ? mk(1.0, 0.0) : pd[h] * xin[h];
+          sq[i] = cmulc(dl, sq[i]);
         }
       }
     }
