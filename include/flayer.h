@@ -68,7 +68,8 @@ typedef struct {
   int px, py;          /* horizontal torus; 0 => 2 nx, 2 ny; need px >= 2 nx - 1,
                           py >= 2 ny - 1, and px, py of the form 2^a 3^b 5^c */
   int precision;       /* 0 = FP64 throughout; 1 = mixed: FP32 FFTs and
-                          convolution, FP64 regularized solve and division */
+                          convolution of stage (c), FP64 data transform (a),
+                          regularized solve and division */
   double tau;          /* discrepancy factor: ||A v - w|| = tau delta_m; default 1.5 */
   double eta;          /* alpha >= eta ||A_m||_F^2; default 1e-10; also the
                           parameter used for noise-free data (delta = 0) */
@@ -180,9 +181,8 @@ fl_status fl_plan_refresh_info(fl_plan *plan);
  *                  sampled at height difference zeta_d), d = j - l + nz - 1
  *   FL_TAP_KTAB    [n_omega][2nz][py][px] complex: omega^2 / (2 nz px py)
  *                  times the 3D DFT of the volume kernel
- * WHAT and VHAT hold complex64 when precision = 1; every other tap is
- * complex128 (the tables are built in FP64; the mixed path keeps an FP32
- * copy of KTAB).
+ * VHAT holds complex64 when precision = 1; every other tap is complex128
+ * (the tables are built in FP64; the mixed path keeps an FP32 copy of KTAB).
  * Errors: FL_EINVAL for an unknown tap or a size mismatch.
  */
 enum {

@@ -31,10 +31,11 @@ struct AdjArgs {
   const z64* bd_dr;
   const z64* refl;      // [C][n][n]
   const double* gam;    // [C][n]
-  const void* What;     // [F][n][N] forward W^ (complex64 or complex128)
+  const void* What;     // [F][n][N] forward W^ (complex128)
   const void* Vh;       // [F][n][N] forward v^
   const void* X;        // VJP: v^bar [F][n][N]; JVP: W^' [F][n][N]
-  int single;           // 1: What, Vh, X hold complex64
+  int single;           // 1: Vh (and the JVP's Y) hold complex64
+  int x_single;         // 1: X holds complex64
   const double* Tdot;   // JVP: per frequency T'
   void* Y;              // VJP: w^bar [F][n][N] complex128; JVP: v^' (type of Vh)
   double* cm;           // VJP: [F*N] implicit-alpha coefficients s / phi_a
@@ -187,10 +188,12 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     }
     __syncthreads();
     const long base = (long)f * n * a.N + m;
-    auto at = [&](const void* p, int i) { return i < n ? ldx(p, base + (long)i * a.N, a.single) : mk(0.0, 0.0); };
-    const z64 vh0 = at(a.Vh, lane), vh1 = at(a.Vh, lane + 64);
-    const z64 w0 = at(a.What, lane), w1 = at(a.What, lane + 64);
-    const z64 x0i = at(a.X, lane), x1i = at(a.X, lane + 64);
+    auto at = [&](const void* p, int i, int sgl) {
+      return i < n ? ldx(p, base + (long)i * a.N, sgl) : mk(0.0, 0.0);
+    };
+    const z64 vh0 = at(a.Vh, lane, a.single), vh1 = at(a.Vh, lane + 64, a.single);
+    const z64 w0 = at(a.What, lane, 0), w1 = at(a.What, lane + 64, 0);
+    const z64 x0i = at(a.X, lane, a.x_single), x1i = at(a.X, lane + 64, a.x_single);
     // pieces of the implicit alpha derivative
     z64 q0 = mk(0.0, 0.0), q1 = mk(0.0, 0.0);
     double phia = 1.0, sx2 = 0.0;

@@ -349,14 +349,14 @@ const std::vector<BdVariant>& bd_variants(int n) {
 template <typename T>
 fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
   const int n = p->n;
-  const cx<T>* What = (const cx<T>*)p->What;
+  const z64* What = (const z64*)p->What;
   const auto& vs = bd_variants(n);
   if (p->bd_var < 0 || p->bd_var >= (int)vs.size())
     return fail(FL_EUNSUPPORTED, "nz = %d has no solver schedule %d", n, p->bd_var);
   const BdVariant v = vs[p->bd_var];
 #define BD(TR, TC, WPE)                                                                     \
   if (v.tr == TR && v.tc == TC && v.wpe == WPE) {                                           \
-    hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, T, WPE>), dim3(grid), dim3(TR * TC), 0, \
+    hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, double, WPE>), dim3(grid), dim3(TR * TC), 0, \
                        p->st, p->gsys, p->TP, What, p->N, p->list, p->count, chunk0, p->C, o); \
     LAUNCHCHK();                                                                            \
     return FL_OK;                                                                           \
@@ -411,7 +411,7 @@ fl_status solve_prepare(fl_plan* p) {
   const long FN = (long)p->F * p->N;
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
-  hipLaunchKernelGGL(k_classify<T>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const cx<T>*)p->What,
+  hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const z64*)p->What,
                      p->nd, p->N, p->F, p->thr2, p->wn2, p->flag);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
@@ -621,10 +621,6 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  const cx<T>* twx = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_x32 : (const void*)p->tw_x);
-  const cx<T>* twy = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_y32 : (const void*)p->tw_y);
-  const cx<T>* twz = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->tw_z32 : (const void*)p->tw_z);
-  const cx<T>* ktab = (const cx<T>*)(sizeof(T) == 4 ? (const void*)p->ktab32 : (const void*)p->ktab);
   RUN(mark(p, FL_STAGE_NORM));
   // noise thresholds: thr2[f] = (tau delta ||W_f||)^2
   {
@@ -649,13 +645,15 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   // (a) FFT2 of W: rows, then columns -> W^ plane-major [F][nd][py][px]
   {
     RUN(mark(p, FL_STAGE_FFT_ROWS));
-    FftArgs g = rows_args(W, p->w1, twx, px, (long)F * nd * py);
+    // in FP64 in both precisions: the regularized solves amplify the
+    // rounding of w^ by their conditioning
+    FftArgs g = rows_args(W, p->w1, p->tw_x, px, (long)F * nd * py);
     if (p->opts.input_dtype == 0)
-      RUN((run_fft<double, T, T, -1>(g, st)));
+      RUN((run_fft<double, double, double, -1>(g, st)));
     else
-      RUN((run_fft<float, T, T, -1>(g, st)));
+      RUN((run_fft<float, double, double, -1>(g, st)));
     RUN(mark(p, FL_STAGE_FFT_COLS));
-    RUN((run_fft<T, T, T, -1>(cols_args(p->w1, p->What, twy, py, px, F * nd), st)));
+    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
   }
   // (b) regularized solves of the active systems -> v^ plane-major
   RUN(solve_systems<T>(p));
@@ -714,6 +712,7 @@ AdjArgs adj_args(fl_plan* p) {
   a.What = p->What;
   a.Vh = p->Vh;
   a.single = p->prec;
+  a.x_single = p->prec;
   return a;
 }
 
@@ -811,7 +810,6 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
   RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
-  const Tw<T> tw = twiddles_of<T>(p);
   // T'_f = 2 tau^2 delta^2 Re <W_f, W'_f>
   {
     dim3 g(256, F);
@@ -828,18 +826,20 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   }
   // W^' = FFT2(W')
   {
-    FftArgs g = rows_args(dW, p->w1, tw.x, px, (long)F * nd * py);
+    // FP64 in both precisions, like W^ itself
+    FftArgs g = rows_args(dW, p->w1, p->tw_x, px, (long)F * nd * py);
     if (p->opts.input_dtype == 0)
-      RUN((run_fft<double, T, T, -1>(g, st)));
+      RUN((run_fft<double, double, double, -1>(g, st)));
     else
-      RUN((run_fft<float, T, T, -1>(g, st)));
-    RUN((run_fft<T, T, T, -1>(cols_args(p->w1, p->Xb, tw.y, py, px, F * nd), st)));
+      RUN((run_fft<float, double, double, -1>(g, st)));
+    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->Xb, p->tw_y, py, px, F * nd), st)));
   }
   const long FN = (long)F * N;
   hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * nz, 256)), dim3(256), 0, st, (cx<T>*)p->Yb, FN * nz);
   LAUNCHCHK();
   AdjArgs a = adj_args(p);
   a.X = p->Xb;
+  a.x_single = 0;
   a.Y = p->Yb;
   a.Tdot = p->Tb;
   RUN((launch_sys_adjoint<1, T>(p, a)));
@@ -1017,7 +1017,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   const size_t esz = p->prec ? sizeof(z32) : sizeof(z64);
   {
     fl_status s;
-    if ((s = dalloc_bytes(p, &p->What, (size_t)(F * nd * N) * esz)) != FL_OK) return bail(s);
+    if ((s = dalloc_bytes(p, &p->What, (size_t)(F * nd * N) * sizeof(z64))) != FL_OK) return bail(s);
     if ((s = dalloc_bytes(p, &p->Vh, (size_t)(F * nz * N) * esz)) != FL_OK) return bail(s);
     // the work arrays also serve fl_forward, which runs in FP64
     if ((s = dalloc_bytes(p, &p->w1, (size_t)big * sizeof(z64))) != FL_OK) return bail(s);
@@ -1373,7 +1373,7 @@ fl_status fl_debug_read(fl_plan* p, int tap, void* dst, size_t bytes) {
   const void* src = nullptr;
   size_t need = 0;
   switch (tap) {
-    case FL_TAP_WHAT: src = p->What; need = F * p->nd * N * (p->prec ? sizeof(z32) : sizeof(z64)); break;
+    case FL_TAP_WHAT: src = p->What; need = F * p->nd * N * sizeof(z64); break;
     case FL_TAP_VHAT: src = p->Vh; need = F * p->nz * N * (p->prec ? sizeof(z32) : sizeof(z64)); break;
     case FL_TAP_V: src = p->vX; need = F * nvox * sizeof(z64); break;
     case FL_TAP_U: src = p->u; need = F * nvox * sizeof(z64); break;

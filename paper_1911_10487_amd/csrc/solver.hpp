@@ -548,7 +548,6 @@ template <int NMAX>
 __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
   __shared__ double sd[NMAX], se[NMAX], srho[NMAX], soff[NMAX];
   __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
-  __shared__ double sx[2];
   const int lane = threadIdx.x;
   const int n = a.n;
   const int total = *a.count;

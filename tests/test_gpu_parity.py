@@ -59,7 +59,7 @@ def gpu_run(p, W, u0, delta, **kw):
     F, N = p.n_omega, p.px * p.py
     cw = np.complex64 if kw.get("precision", 0) == 1 else np.complex128
     st = {
-        "What": plan.tap(TAP_WHAT, cw, (F, p.nd, p.py, p.px)),
+        "What": plan.tap(TAP_WHAT, np.complex128, (F, p.nd, p.py, p.px)),
         "Vhat": plan.tap(TAP_VHAT, cw, (F, p.nz, p.py, p.px)),
         "v": plan.tap(TAP_V, np.complex128, (F, p.nz, p.ny, p.nx)),
         "u": plan.tap(TAP_U, np.complex128, (F, p.nz, p.ny, p.nx)),
