@@ -145,8 +145,14 @@ fl_status fl_invert_jvp(fl_plan *plan, const void *W, const void *u0, double del
 /*
  * Synthetic data (the role of Algorithm 1, Section 3): v = xi u in X, then
  * W = omega^2 G * v on the data planes (eq. 7, second line) over the torus.
- * maxit = 0 takes u = u0 (Born data); maxit > 0 is reserved for the
- * Lippmann-Schwinger solve and returns FL_EUNSUPPORTED in this build.
+ * maxit = 0 takes u = u0 (Born data). maxit > 0 solves the second-kind
+ * equation u - omega^2 K(xi u) = u0 in X (system (2), first line; K the
+ * zero-padded 3D convolution of stage (c), FP64) by BiCGSTAB from u = 0,
+ * every frequency at once, stopping a frequency when its residual is within
+ * tol ||u0|| (tol = 0 means 1e-12); FL_ENOCONV if one has not converged
+ * after maxit iterations (W_out is then untouched). The Krylov vectors
+ * (eight arrays shaped like u0, complex128) are allocated by the first such
+ * call and kept by the plan.
  *   xi     [nz][ny][nx] real float64, device; u0 as in fl_invert (device)
  *   W_out  [n_omega][nd][py][px] complex128, device
  */

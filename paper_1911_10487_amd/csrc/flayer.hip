@@ -99,6 +99,13 @@ struct fl_plan {
   double *cm = nullptr, *Tb = nullptr;
   double* alpha = nullptr;
   signed char* branch = nullptr;
+  // Lippmann-Schwinger solve (allocated by the first fl_forward with maxit > 0)
+  bool has_ls = false;
+  z64* bv[7] = {};          // x, r, r^, p, v, s, t  [F][nvox]
+  z64 *lsw = nullptr, *dpart = nullptr, *dots = nullptr;
+  z64 *b_rho = nullptr, *b_alpha = nullptr, *b_omega = nullptr, *b_beta = nullptr;
+  double* b_bn2 = nullptr;
+  int* b_active = nullptr;
   std::vector<void*> allocs;
   size_t bytes = 0;
   int last_active = -1;
@@ -907,6 +914,134 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
   (void)hipEventDestroy(e1);
   return st;
 }
+// ------------------------------------------------------------ forward solve
+
+fl_status ensure_ls_buffers(fl_plan* p) {
+  if (p->has_ls) return FL_OK;
+  const long F = p->F, nvox = (long)p->nx * p->ny * p->nz;
+  for (auto& b : p->bv) ALLOC(b, F * nvox);
+  ALLOC(p->lsw, F * nvox);
+  ALLOC(p->dpart, F * 256);
+  ALLOC(p->dots, F * 8);
+  ALLOC(p->b_rho, F);
+  ALLOC(p->b_alpha, F);
+  ALLOC(p->b_omega, F);
+  ALLOC(p->b_beta, F);
+  ALLOC(p->b_bn2, F);
+  ALLOC(p->b_active, F);
+  p->has_ls = true;
+  return FL_OK;
+}
+
+// out = y - omega^2 K(xi y), every frequency (K: the zero-padded 3D FFT
+// convolution of stage (c), in FP64)
+fl_status ls_apply(fl_plan* p, const double* xi, const z64* y, z64* out) {
+  const long nvox = (long)p->nx * p->ny * p->nz;
+  hipLaunchKernelGGL(k_neg_xi, dim3(nblk(p->F * nvox, 256)), dim3(256), 0, p->st, xi, y, nvox, p->F,
+                     p->lsw);
+  LAUNCHCHK();
+  FftArgs r = rows_args(p->lsw, p->w2, p->tw_x, p->px, (long)p->F * p->nz * p->ny);
+  r.lin = p->nx;
+  r.in_sb = p->nx;
+  RUN((run_fft<double, double, double, -1>(r, p->st)));
+  return conv_tail<double>(p, out, y, 0);
+}
+
+// dots[slot][f] = <a_f, b_f> = sum conj(a) b
+fl_status cdot(fl_plan* p, const z64* a, const z64* b, int slot) {
+  const long nvox = (long)p->nx * p->ny * p->nz;
+  hipLaunchKernelGGL(k_cdot, dim3(256, p->F), dim3(256), 0, p->st, a, b, nvox, p->dpart);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_cdot_finish, dim3(p->F), dim3(64), 0, p->st, p->dpart, 256, p->F,
+                     p->dots + (long)slot * p->F);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
+__global__ void k_bicg_init(BicgScalars S, const z64* __restrict__ bb, int F) {
+  const int f = threadIdx.x;
+  if (f < F) {
+    S.bn2[f] = bb[f].x;
+    S.rho[f] = bb[f];
+    S.alpha[f] = mk(1.0, 0.0);
+    S.omega[f] = mk(1.0, 0.0);
+    S.active[f] = bb[f].x > 0.0;
+  }
+}
+
+// BiCGSTAB from x0 = 0 on u - omega^2 K(xi u) = b; stops each frequency at
+// ||s|| or ||r|| <= tol ||b||. Leaves u in bv[0].
+fl_status ls_solve(fl_plan* p, const double* xi, const z64* b, double tol, int maxit, int* iters) {
+  RUN(ensure_ls_buffers(p));
+  hipStream_t st = p->st;
+  const int F = p->F;
+  const long nvox = (long)p->nx * p->ny * p->nz, n = F * nvox;
+  const size_t bytes = (size_t)n * sizeof(z64);
+  z64 *X = p->bv[0], *R = p->bv[1], *Rh = p->bv[2], *P = p->bv[3], *V = p->bv[4], *S = p->bv[5],
+      *T = p->bv[6];
+  BicgScalars sc{p->b_rho, p->b_alpha, p->b_omega, p->b_beta, p->b_bn2, p->b_active};
+  z64* D = p->dots;  // slots: 0 <rh,v>, 1 <s,s>, 2 <t,s>, 3 <t,t>, 4 <r,r>, 5 <rh,r>
+  const dim3 g(nblk(n, 256)), blk(256);
+  hipLaunchKernelGGL(k_zero<double>, g, blk, 0, st, X, n);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(R, b, bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(Rh, b, bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P, b, bytes, hipMemcpyDeviceToDevice, st));
+  RUN(cdot(p, b, b, 0));
+  hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(64), 0, st, sc, D, F);
+  LAUNCHCHK();
+  std::vector<double> bn2(F);
+  std::vector<int> act(F);
+  std::vector<z64> hd(2 * F);
+  HIPCHK(hipMemcpyAsync(bn2.data(), p->b_bn2, F * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(act.data(), p->b_active, F * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double tol2 = tol * tol;
+  int it = 0;
+  bool any = false;
+  for (int f = 0; f < F; ++f) any = any || act[f];
+  while (any && it < maxit) {
+    ++it;
+    RUN(ls_apply(p, xi, P, V));
+    RUN(cdot(p, Rh, V, 0));
+    hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(64), 0, st, sc, D, F);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_bicg_s, g, blk, 0, st, sc, R, V, nvox, F, S);
+    LAUNCHCHK();
+    RUN(cdot(p, S, S, 1));
+    RUN(ls_apply(p, xi, S, T));
+    RUN(cdot(p, T, S, 2));
+    RUN(cdot(p, T, T, 3));
+    hipLaunchKernelGGL(k_bicg_omega, dim3(1), dim3(64), 0, st, sc, D + 2 * F, D + 3 * F, D + F, tol2,
+                       F);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_bicg_xr, g, blk, 0, st, sc, P, S, T, nvox, F, X, R);
+    LAUNCHCHK();
+    RUN(cdot(p, R, R, 4));
+    // convergence of each frequency: ||s|| (then x took only the alpha p
+    // step) or ||r|| within tol ||b||
+    HIPCHK(hipMemcpyAsync(hd.data(), D + F, F * sizeof(z64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hd.data() + F, D + 4 * F, F * sizeof(z64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    any = false;
+    for (int f = 0; f < F; ++f) {
+      if (act[f] && (hd[f].x <= tol2 * bn2[f] || hd[F + f].x <= tol2 * bn2[f])) act[f] = 0;
+      any = any || act[f];
+    }
+    HIPCHK(hipMemcpyAsync(p->b_active, act.data(), F * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!any) break;
+    RUN(cdot(p, Rh, R, 5));
+    hipLaunchKernelGGL(k_bicg_beta, dim3(1), dim3(64), 0, st, sc, D + 5 * F, F);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_bicg_p, g, blk, 0, st, sc, R, V, nvox, F, P);
+    LAUNCHCHK();
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  *iters = it;
+  if (any) return fail(FL_ENOCONV, "BiCGSTAB: no convergence to %g in %d iterations", tol, maxit);
+  return FL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1332,26 +1467,36 @@ fl_status fl_invert_jvp(fl_plan* p, const void* W, const void* u0, double delta,
 
 fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, int maxit,
                      void* W_out) {
-  (void)tol;
   if (!p) return fail(FL_EINVAL, "NULL plan");
   if (!xi || !u0 || !W_out) return fail(FL_EINVAL, "NULL array argument");
   if (maxit < 0) return fail(FL_EINVAL, "maxit must be >= 0");
-  if (maxit > 0) return fail(FL_EUNSUPPORTED, "the Lippmann-Schwinger solve is not in this build");
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(FL_EINVAL, "tol must be >= 0 and finite");
+  if (tol == 0) tol = 1e-12;
   hipStream_t st = p->st;
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, px = p->px, py = p->py;
   const long nvox = (long)p->nx * p->ny * nz;
+  const z64* u = (const z64*)u0;
+  if (p->opts.input_dtype == 1) {
+    hipLaunchKernelGGL(k_widen<float>, dim3(nblk(F * nvox, 256)), dim3(256), 0, st, (const z32*)u0,
+                       p->u0w, (long)F * nvox);
+    LAUNCHCHK();
+    u = p->u0w;
+  }
+  if (maxit > 0) {
+    // total field: u - omega^2 K(xi u) = u0 in X (system (2), first line)
+    int it = 0;
+    RUN(ls_solve(p, xi, u, tol, maxit, &it));
+    u = p->bv[0];
+  }
+  // W = omega^2 G * (xi u) on the data planes (eq. 3; eq. 7, second line)
   z64* w1 = (z64*)p->w1;
   z64* w2 = (z64*)p->w2;
   hipLaunchKernelGGL(k_zero<double>, dim3(nblk((long)F * nz * N, 256)), dim3(256), 0, st, w1,
                      (long)F * nz * N);
   LAUNCHCHK();
-  if (p->opts.input_dtype == 0)
-    hipLaunchKernelGGL((k_current<double, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
-                       (const z64*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, w1);
-  else
-    hipLaunchKernelGGL((k_current<float, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi,
-                       (const z32*)u0, p->nx, p->ny, nz, F, px, py, p->ox, p->oy, w1);
+  hipLaunchKernelGGL((k_current<double, double>), dim3(nblk(F * nvox, 256)), dim3(256), 0, st, xi, u,
+                     p->nx, p->ny, nz, F, px, py, p->ox, p->oy, w1);
   LAUNCHCHK();
   RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
   RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));

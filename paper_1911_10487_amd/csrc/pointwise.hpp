@@ -214,3 +214,122 @@ __global__ __launch_bounds__(256) void k_apply_systems(const cx<T>* __restrict__
 }
 
 }  // namespace fl
+
+namespace fl {
+
+// ---------------------------------------------------------------- BiCGSTAB
+// Stabilized biconjugate gradients (van der Vorst) for the second-kind
+// equation u - omega^2 K(xi u) = u0 in X (system (2), first line), every
+// frequency at once: vectors are [F][nvox] complex128, scalars per frequency.
+
+// out[f][v] = -xi[v] y[f][v]
+__global__ __launch_bounds__(256) void k_neg_xi(const double* __restrict__ xi, const z64* __restrict__ y,
+                                                long nvox, int F, z64* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * F) return;
+  const double x = xi[i % nvox];
+  out[i] = mk(-x * y[i].x, -x * y[i].y);
+}
+
+// partial[f][blk] = sum conj(a) b over frequency f's block-strided segment
+__global__ __launch_bounds__(256) void k_cdot(const z64* __restrict__ a, const z64* __restrict__ b,
+                                              long n, z64* __restrict__ partial) {
+  __shared__ double rx[4], ry[4];
+  const int f = blockIdx.y, nb = gridDim.x;
+  const z64* af = a + (long)f * n;
+  const z64* bf = b + (long)f * n;
+  z64 s = mk(0.0, 0.0);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)nb * blockDim.x)
+    s = cfmac(s, af[i], bf[i]);
+  s.x = group_sum<64>(s.x);
+  s.y = group_sum<64>(s.y);
+  if ((threadIdx.x & 63) == 0) {
+    rx[threadIdx.x >> 6] = s.x;
+    ry[threadIdx.x >> 6] = s.y;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[f * nb + blockIdx.x] = mk((rx[0] + rx[1]) + (rx[2] + rx[3]), (ry[0] + ry[1]) + (ry[2] + ry[3]));
+}
+
+__global__ void k_cdot_finish(const z64* __restrict__ partial, int nb, int F, z64* __restrict__ out) {
+  const int f = blockIdx.x;
+  if (f >= F) return;
+  z64 s = mk(0.0, 0.0);
+  for (int b = threadIdx.x; b < nb; b += 64) s = s + partial[f * nb + b];
+  s.x = group_sum<64>(s.x);
+  s.y = group_sum<64>(s.y);
+  if (threadIdx.x == 0) out[f] = s;
+}
+
+struct BicgScalars {
+  z64 *rho, *alpha, *omega, *beta;
+  double* bn2;
+  int* active;
+};
+
+__device__ __forceinline__ z64 cdiv(z64 a, z64 b) {
+  const double d = nrm2(b);
+  if (!(d > 0.0)) return mk(0.0, 0.0);
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// alpha = rho / <rh, v>
+__global__ void k_bicg_alpha(BicgScalars S, const z64* __restrict__ d, int F) {
+  const int f = threadIdx.x;
+  if (f < F && S.active[f]) S.alpha[f] = cdiv(S.rho[f], d[f]);
+}
+
+// omega = <t, s> / <t, t>, or 0 when ||s|| already meets the tolerance
+__global__ void k_bicg_omega(BicgScalars S, const z64* __restrict__ ts, const z64* __restrict__ tt,
+                             const z64* __restrict__ ss, double tol2, int F) {
+  const int f = threadIdx.x;
+  if (f < F && S.active[f]) S.omega[f] = ss[f].x <= tol2 * S.bn2[f] ? mk(0.0, 0.0) : cdiv(ts[f], tt[f]);
+}
+
+// beta = (rho' / rho)(alpha / omega), rho = rho'
+__global__ void k_bicg_beta(BicgScalars S, const z64* __restrict__ rho_new, int F) {
+  const int f = threadIdx.x;
+  if (f < F && S.active[f]) {
+    S.beta[f] = cdiv(rho_new[f], S.rho[f]) * cdiv(S.alpha[f], S.omega[f]);
+    S.rho[f] = rho_new[f];
+  }
+}
+
+// s = r - alpha v
+__global__ __launch_bounds__(256) void k_bicg_s(BicgScalars S, const z64* __restrict__ r,
+                                                const z64* __restrict__ v, long nvox, int F,
+                                                z64* __restrict__ s) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * F) return;
+  const int f = (int)(i / nvox);
+  if (!S.active[f]) return;
+  s[i] = cfms(r[i], S.alpha[f], v[i]);
+}
+
+// x += alpha p + omega s; r = s - omega t
+__global__ __launch_bounds__(256) void k_bicg_xr(BicgScalars S, const z64* __restrict__ p,
+                                                 const z64* __restrict__ s, const z64* __restrict__ t,
+                                                 long nvox, int F, z64* __restrict__ x,
+                                                 z64* __restrict__ r) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * F) return;
+  const int f = (int)(i / nvox);
+  if (!S.active[f]) return;
+  const z64 a = S.alpha[f], w = S.omega[f];
+  x[i] = cfma(cfma(x[i], a, p[i]), w, s[i]);
+  r[i] = cfms(s[i], w, t[i]);
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(256) void k_bicg_p(BicgScalars S, const z64* __restrict__ r,
+                                                const z64* __restrict__ v, long nvox, int F,
+                                                z64* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * F) return;
+  const int f = (int)(i / nvox);
+  if (!S.active[f]) return;
+  p[i] = cfma(r[i], S.beta[f], cfms(p[i], S.omega[f], v[i]));
+}
+
+}  // namespace fl

@@ -568,10 +568,15 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     // r_i = rho_i r_{i-1} (or restart at a zero entry), an affine recurrence
     // evaluated by a parallel prefix over the lanes (elements lane, lane + 64).
     {
+      constexpr int H = (NMAX + 63) / 64;  // elements per lane
       z64 ra[2], rb[2], pd[2];
       bool dz[2];
+      ra[1] = mk(1.0, 0.0);
+      rb[1] = mk(0.0, 0.0);
+      pd[1] = mk(1.0, 0.0);
+      dz[1] = true;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < H; ++h) {
         const int i = lane + 64 * h;
         z64 am = mk(1.0, 0.0), bm = mk(0.0, 0.0), ph = mk(1.0, 0.0);
         dz[h] = true;
@@ -608,7 +613,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       }
       // inclusive scan of x -> a x + b within each half (Hillis-Steele)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < H; ++h) {
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
           const double ax = __shfl_up(ra[h].x, o), ay = __shfl_up(ra[h].y, o);
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       }
       const z64 xin[2] = {in0, in1};
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < H; ++h) {
         const int i = lane + 64 * h;
         if (i < n) {
           sdr[i] = xin[h];
@@ -737,7 +742,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     __syncthreads();
     // v^ = V (D_R y'), V = P_0 P_1 ... P_{n-3}
     z64 y0 = lane < n ? sdr[lane] * sy[lane] : mk(0.0, 0.0);
-    z64 y1 = lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
+    z64 y1 = NMAX > 64 && lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
     const z64* R = a.refl + (long)sl * n * n;
     const double* G = a.gam + (long)sl * n;
     // reflector k has entries k+1..n-1; rows are prefetched one step ahead
@@ -747,7 +752,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       const int k = n - 3;
       ng = G[k];
       if (lane > k && lane < n) n0 = R[(long)k * n + lane];
-      if (lane + 64 > k && lane + 64 < n) n1 = R[(long)k * n + lane + 64];
+      if (NMAX > 64 && lane + 64 > k && lane + 64 < n) n1 = R[(long)k * n + lane + 64];
     }
     for (int k = n - 3; k >= 0; --k) {
       const double g = ng;
@@ -756,7 +761,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
         const int kk = k - 1;
         ng = G[kk];
         n0 = (lane > kk && lane < n) ? R[(long)kk * n + lane] : mk(0.0, 0.0);
-        n1 = (lane + 64 > kk && lane + 64 < n) ? R[(long)kk * n + lane + 64] : mk(0.0, 0.0);
+        n1 = (NMAX > 64 && lane + 64 > kk && lane + 64 < n) ? R[(long)kk * n + lane + 64] : mk(0.0, 0.0);
       }
       z64 s = cmulc(v0, y0);
       s = cfmac(s, v1, y1);

@@ -219,14 +219,16 @@ class Plan:
                                    ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(out.data_ptr())))
         return out
 
-    def forward(self, xi, u0, W_out=None):
-        """Born data: W = omega^2 G * (xi u0) on the data planes' torus."""
+    def forward(self, xi, u0, W_out=None, maxit=0, tol=1e-12):
+        """W = omega^2 G * (xi u) on the data planes' torus: Born data
+        (u = u0) for maxit = 0, else u from the BiCGSTAB solve of
+        u - omega^2 K(xi u) = u0 (relative residual tol)."""
         import torch
         if W_out is None:
             W_out = torch.empty((self.n_omega, self.nd, self.py, self.px), dtype=torch.complex128,
                                 device=u0.device)
         _check(lib().fl_forward(self._h, ctypes.c_void_p(xi.data_ptr()),
-                                ctypes.c_void_p(u0.data_ptr()), 0.0, 0,
+                                ctypes.c_void_p(u0.data_ptr()), float(tol), int(maxit),
                                 ctypes.c_void_p(W_out.data_ptr())))
         return W_out
 
