@@ -745,31 +745,36 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     z64 y1 = NMAX > 64 && lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
     const z64* R = a.refl + (long)sl * n * n;
     const double* G = a.gam + (long)sl * n;
-    // reflector k has entries k+1..n-1; rows are prefetched one step ahead
-    z64 n0 = mk(0.0, 0.0), n1 = mk(0.0, 0.0);
-    double ng = 0.0;
-    if (n >= 3) {
-      const int k = n - 3;
-      ng = G[k];
-      if (lane > k && lane < n) n0 = R[(long)k * n + lane];
-      if (NMAX > 64 && lane + 64 > k && lane + 64 < n) n1 = R[(long)k * n + lane + 64];
-    }
-    for (int k = n - 3; k >= 0; --k) {
-      const double g = ng;
-      const z64 v0 = n0, v1 = n1;
-      if (k > 0) {
-        const int kk = k - 1;
-        ng = G[kk];
-        n0 = (lane > kk && lane < n) ? R[(long)kk * n + lane] : mk(0.0, 0.0);
-        n1 = (NMAX > 64 && lane + 64 > kk && lane + 64 < n) ? R[(long)kk * n + lane + 64] : mk(0.0, 0.0);
+    // reflector k has entries k+1..n-1; rows are loaded eight at a time so
+    // that their global-memory latency overlaps
+    constexpr int GR = 8;
+    for (int k0 = n - 3; k0 >= 0; k0 -= GR) {
+      z64 v0[GR], v1[GR];
+      double gg[GR];
+#pragma unroll
+      for (int g = 0; g < GR; ++g) {
+        const int k = k0 - g;
+        gg[g] = 0.0;
+        v0[g] = mk(0.0, 0.0);
+        v1[g] = mk(0.0, 0.0);
+        if (k >= 0) {
+          gg[g] = G[k];
+          if (lane > k && lane < n) v0[g] = R[(long)k * n + lane];
+          if constexpr (NMAX > 64)
+            if (lane + 64 > k && lane + 64 < n) v1[g] = R[(long)k * n + lane + 64];
+        }
       }
-      z64 s = cmulc(v0, y0);
-      s = cfmac(s, v1, y1);
-      s.x = lanes_sum<64>(s.x);
-      s.y = lanes_sum<64>(s.y);
-      s = g * s;
-      y0 = y0 - v0 * s;
-      y1 = y1 - v1 * s;
+#pragma unroll
+      for (int g = 0; g < GR; ++g) {
+        if (k0 - g < 0) break;
+        z64 s = cmulc(v0[g], y0);
+        if constexpr (NMAX > 64) s = cfmac(s, v1[g], y1);
+        s.x = lanes_sum<64>(s.x);
+        s.y = lanes_sum<64>(s.y);
+        s = gg[g] * s;
+        y0 = y0 - v0[g] * s;
+        if constexpr (NMAX > 64) y1 = y1 - v1[g] * s;
+      }
     }
     const long o0 = (long)f * n * a.N + m;
     if (a.vh_single) {
