@@ -81,6 +81,13 @@ typedef struct {
                           systems factorized per solver launch (the workspace
                           holds one chunk of n x n reflectors; derivative calls
                           re-factorize chunk by chunk when there are several) */
+  int kernel_mode;     /* table of A: 0 = FFT of G sampled on the torus
+                          (Section 5, default); 1 = the continuous transform
+                          -i exp(i gamma |zeta|) / (2 gamma) at the torus
+                          wavenumbers, gamma = sqrt(k0^2 - |k|^2), Im >= 0 */
+  double damping;      /* kernel_mode 1 only: k0 -> k0 (1 + i damping), >= 0;
+                          with damping = 0 a wavenumber on |k| = k0 gives
+                          FL_ENUMERIC (gamma = 0) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);

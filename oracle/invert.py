@@ -32,11 +32,11 @@ def system_noise_level(W_f: np.ndarray, delta: float) -> float:
 
 
 def solve_systems(p, f, What_f, delta, tau=TAU, eta=ETA, rule="tikhonov",
-                  chunk=2048, tab=None, idx=None):
+                  chunk=2048, tab=None, idx=None, kernel_mode=0, damping=0.0):
     """Algorithm 2 item 1 for one frequency. What_f: (nd, py, px) transformed
     data. Returns (Vhat (nz, py, px), alpha (py*px,), branch (py*px,))."""
     if tab is None:
-        tab, idx = model.system_table(p, f)
+        tab, idx = model.system_table(p, f, kernel_mode, damping)
     N = p.px * p.py
     wsys = What_f.reshape(p.nd, N).T                      # (N, nd)
     dm = system_noise_level_hat(What_f, delta, N)
@@ -63,9 +63,10 @@ def system_noise_level_hat(What_f, delta, N):
 
 
 def invert(p, W, u0, delta, tau=TAU, eta=ETA, combine="lsq", rule="tikhonov",
-           stages=False):
+           stages=False, kernel_mode=0, damping=0.0):
     """W -> xi. With stages=True also returns a dict of per-frequency
-    intermediates (What, Vhat, v, u, alpha, branch)."""
+    intermediates (What, Vhat, v, u, alpha, branch). kernel_mode / damping
+    select the table of A (model.system_table)."""
     W = np.asarray(W, np.complex128)
     u0 = np.asarray(u0, np.complex128)
     nf = p.n_omega
@@ -75,7 +76,8 @@ def invert(p, W, u0, delta, tau=TAU, eta=ETA, combine="lsq", rule="tikhonov",
     keep = {k: [] for k in ("What", "Vhat", "v", "u", "alpha", "branch")}
     for f in range(nf):
         What = np.fft.fft2(W[f])                                  # item 1 input
-        Vhat, alpha, branch = solve_systems(p, f, What, delta, tau, eta, rule)
+        Vhat, alpha, branch = solve_systems(p, f, What, delta, tau, eta, rule,
+                                            kernel_mode=kernel_mode, damping=damping)
         v = model.crop(p, np.fft.ifft2(Vhat))                      # item 2
         u = u0[f] + model.volume_potential(p, f, v)
         num += np.conj(u) * v                                      # item 3

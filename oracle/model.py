@@ -82,12 +82,27 @@ def zeta_index(p):
     return zetas, inv.reshape(zeta.shape)
 
 
-def system_table(p, f: int):
+def torus_wavenumbers(p):
+    """(kx, ky) of every DFT index on the torus, (py, px) each: 2 pi m / (P h)
+    with m the signed index."""
+    kx = 2.0 * np.pi * min_image(p.px) / (p.px * p.h)
+    ky = 2.0 * np.pi * min_image(p.py) / (p.py * p.h)
+    return np.broadcast_to(kx[None, :], (p.py, p.px)), np.broadcast_to(ky[:, None], (p.py, p.px))
+
+
+def system_table(p, f: int, kernel_mode: int = 0, damping: float = 0.0):
     """Ĝ for every distinct zeta at frequency f: (n_zeta, py, px), plus the
-    (nd, nz) index map of zeta_index."""
+    (nd, nz) index map of zeta_index. kernel_mode 0: the FFT of G sampled on
+    the torus (Section 5); 1: the continuous transform (closed form) at the
+    torus wavenumbers, with k0 -> k0 (1 + i damping)."""
     k0 = k0_of(p, f)
     zetas, idx = zeta_index(p)
-    tab = np.stack([plane_kernel_hat(p, k0, z) for z in zetas])
+    if kernel_mode == 0:
+        tab = np.stack([plane_kernel_hat(p, k0, z) for z in zetas])
+    else:
+        kx, ky = torus_wavenumbers(p)
+        k0c = k0 * (1.0 + 1j * damping)
+        tab = np.stack([closed_form_ghat(kx, ky, z, k0c) for z in zetas])
     return tab, idx
 
 
@@ -168,7 +183,7 @@ def volume_potential(p, f: int, vX: np.ndarray) -> np.ndarray:
 def closed_form_ghat(kx, ky, zeta, k0):
     """Continuous 2D transform of G at height difference zeta:
     -i exp(i gamma |zeta|) / (2 gamma), gamma = sqrt(k0^2 - |k|^2), Im gamma >= 0
-    (Weyl expansion of the point-source field). Used by pins only."""
+    (Weyl expansion of the point-source field); k0 may be complex (damping)."""
     g = np.sqrt(np.asarray(k0 * k0 - kx * kx - ky * ky, np.complex128))
     g = np.where(g.imag < 0, -g, g)
     return -1j * np.exp(1j * g * abs(zeta)) / (2.0 * g)

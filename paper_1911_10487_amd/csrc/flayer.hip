@@ -266,16 +266,23 @@ fl_status build_tables(fl_plan* p) {
   for (int f = 0; f < F; ++f) {
     const double om = p->omegas[f];
     const double k0 = om / p->c0;
-    // sampled omega^2 h^3 G on every height plane, then FFT2 -> A's entries
     const double zeta0 = p->planes[0] - 0.5 * p->h - (p->nz - 1) * p->h;
     z64* gt = p->gtab + (long)f * p->nzeta * N;
-    hipLaunchKernelGGL((k_gplanes<double>), dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt,
-                       p->nzeta, p->px, p->py, p->h, zeta0, k0, om * om * p->h * p->h * p->h);
-    LAUNCHCHK();
-    RUN((run_fft<double, double, double, -1>(rows_args(gt, gt, p->tw_x, p->px, (long)p->nzeta * p->py),
-                                             p->st)));
-    RUN((run_fft<double, double, double, -1>(cols_args(gt, gt, p->tw_y, p->py, p->px, p->nzeta),
-                                             p->st)));
+    if (p->opts.kernel_mode == 1) {
+      // closed-form transform of G at the torus wavenumbers, times omega^2 h
+      hipLaunchKernelGGL(k_gclosed, dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt, p->nzeta,
+                         p->px, p->py, p->h, zeta0, k0, p->opts.damping, om * om * p->h);
+      LAUNCHCHK();
+    } else {
+      // sampled omega^2 h^3 G on every height plane, then FFT2 -> A's entries
+      hipLaunchKernelGGL((k_gplanes<double>), dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt,
+                         p->nzeta, p->px, p->py, p->h, zeta0, k0, om * om * p->h * p->h * p->h);
+      LAUNCHCHK();
+      RUN((run_fft<double, double, double, -1>(
+          rows_args(gt, gt, p->tw_x, p->px, (long)p->nzeta * p->py), p->st)));
+      RUN((run_fft<double, double, double, -1>(cols_args(gt, gt, p->tw_y, p->py, p->px, p->nzeta),
+                                               p->st)));
+    }
     // volume kernel on (2nz, py, px), scaled by omega^2 / (2 nz px py): the
     // inverse transforms of the convolution are unnormalized
     const int nz2 = 2 * p->nz;
@@ -1097,6 +1104,24 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (!(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
     return fail(FL_EUNSUPPORTED, "nz = %d: this build solves nz in {16,32,48,64,80,96,128}", nz);
   if (o.precision != 0 && o.precision != 1) return fail(FL_EUNSUPPORTED, "precision must be 0 or 1");
+  if (o.kernel_mode != 0 && o.kernel_mode != 1) return fail(FL_EINVAL, "kernel_mode must be 0 or 1");
+  if (!(o.damping >= 0) || !std::isfinite(o.damping)) return fail(FL_EINVAL, "damping must be >= 0");
+  if (o.kernel_mode == 1 && o.damping == 0.0) {
+    // the closed form is singular where |k_m| = k0 (gamma = 0)
+    for (int f = 0; f < n_omega; ++f) {
+      const double k0 = omegas[f] / c0;
+      for (int my = 0; my < py; ++my)
+        for (int mx = 0; mx < px; ++mx) {
+          const double sx = mx <= px / 2 ? mx : mx - px, sy = my <= py / 2 ? my : my - py;
+          const double kx = 2.0 * M_PI * sx / (px * h), ky = 2.0 * M_PI * sy / (py * h);
+          if (std::fabs(k0 * k0 - kx * kx - ky * ky) <= 1e-12 * k0 * k0)
+            return fail(FL_ENUMERIC,
+                        "closed-form kernel: |k| = k0 at wavenumber (%d, %d) of frequency %d "
+                        "(gamma = 0); use damping > 0",
+                        mx, my, f);
+        }
+    }
+  }
   if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
   if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
 

@@ -27,6 +27,50 @@ __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nz
   out[idx] = mk((T)(a * c), (T)(a * s));
 }
 
+// Closed-form table (kernel_mode 1): out[d][m] = wgt * Ĝ(k_m, zeta_d) with
+// Ĝ = -i exp(i gamma |zeta|) / (2 gamma), gamma = sqrt(k0c^2 - |k|^2),
+// Im gamma >= 0, k0c = k0 (1 + i damping), k_m = 2 pi m / (P h) for the
+// signed DFT index m (the continuous 2D transform of G at the torus
+// wavenumbers).
+__global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzeta, int px, int py,
+                                                 double h, double zeta0, double k0, double damping,
+                                                 double wgt) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long N = (long)px * py;
+  if (idx >= N * nzeta) return;
+  const int d = (int)(idx / N);
+  const long p = idx - (long)d * N;
+  const int iy = (int)(p / px), ix = (int)(p - (long)iy * px);
+  const double kx = 2.0 * M_PI * min_image(ix, px) / (px * h);
+  const double ky = 2.0 * M_PI * min_image(iy, py) / (py * h);
+  // gamma^2 = k0^2 (1 + i damping)^2 - |k|^2
+  const double gx = k0 * k0 * (1.0 - damping * damping) - (kx * kx + ky * ky);
+  const double gy = 2.0 * k0 * k0 * damping;
+  // principal square root (stable forms), then the branch with Im >= 0
+  const double r = hypot(gx, gy);
+  double sr, si;
+  if (gx >= 0.0) {
+    sr = sqrt(0.5 * (r + gx));
+    si = sr > 0.0 ? gy / (2.0 * sr) : 0.0;
+  } else {
+    si = copysign(sqrt(0.5 * (r - gx)), gy);
+    sr = gy / (2.0 * si);
+  }
+  if (si < 0.0) {
+    sr = -sr;
+    si = -si;
+  }
+  const double z = fabs(zeta0 + d * h);
+  double sn, cs;
+  sincos(sr * z, &sn, &cs);
+  const double ex = exp(-si * z);
+  // -i e / (2 gamma), e = ex (cs + i sn)
+  const z64 num = mk(ex * sn, -ex * cs);
+  const double den = 2.0 * (sr * sr + si * si);
+  const z64 val = mk((num.x * sr + num.y * si) / den, (num.y * sr - num.x * si) / den);
+  out[idx] = mk(wgt * val.x, wgt * val.y);
+}
+
 // Volume kernel on the (2nz) x py x px torus with minimum-image offsets:
 // h^3 G(h |d|) for d != 0 and the integral of G over the ball of volume h^3 at
 // d = 0, all times wgt.

@@ -89,3 +89,15 @@ def test_tuning_calls_reject_null_arguments():
     assert L.fl_tuning_describe(None, 0, ctypes.byref(i), ctypes.byref(i),
                                 ctypes.byref(i)) == flayer.FL_EINVAL
     assert L.fl_plan_tune(None, None, None, 0.0, 1, None, None) == flayer.FL_EINVAL
+
+
+def test_closed_form_kernel_needs_damping_on_the_k0_circle():
+    # 32x32x16 on the 64^2 torus, h = 0.125, omega = 2 pi: k0 / (2 pi / (64 h))
+    # = 8, so the wavenumber (8, 0) lies on |k| = k0 and gamma = 0 there
+    st, msg, out = _create(kernel_mode=1, damping=0.0)
+    assert st == flayer.FL_ENUMERIC, msg
+    assert "gamma = 0" in msg and not out.value
+    st, msg, out = _create(kernel_mode=2)
+    assert st == flayer.FL_EINVAL and "kernel_mode" in msg
+    st, msg, out = _create(kernel_mode=1, damping=-1.0)
+    assert st == flayer.FL_EINVAL and "damping" in msg

@@ -318,3 +318,20 @@ def test_every_solver_schedule_matches_oracle():
     err = rel(plan.invert(Wt, ut, 0.02).cpu().numpy(), ref)
     assert err <= TOL
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_closed_form_kernel_matches_oracle(small, precision):
+    """kernel_mode 1 (A from the continuous transform of G at the torus
+    wavenumbers, damped) against the oracle in the same mode. Its A_m have
+    rank one, so the other singular directions carry rounding only; eta is
+    raised to 1e-4 so that the floor filters them (at eta = 1e-10 they
+    contribute u / eta ~ 1e-6 to v^ in any FP64 implementation)."""
+    p, xi_true, u0, W = small
+    Wd = synth.add_noise(p, W, 0.01)
+    kw = dict(kernel_mode=1, damping=0.02, eta=1e-4)
+    ref_xi, ref = invert.invert(p, Wd, u0, 0.01, stages=True, **kw)
+    xi, st = gpu_run(p, Wd, u0, 0.01, precision=precision, **kw)
+    e = rel(xi, ref_xi)
+    say("closed form precision", precision, "xi error", e, "Vhat", rel(st["Vhat"], ref["Vhat"]))
+    assert e <= (TOL if precision == 0 else MIXED_TOL)

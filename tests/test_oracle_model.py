@@ -179,3 +179,25 @@ def test_noise_has_exact_relative_level_and_parseval():
     eh = np.fft.fft2(e)
     N = p.px * p.py
     assert abs(np.sum(abs(eh) ** 2) - N * np.sum(abs(e) ** 2)) < 1e-12 * N
+
+
+def test_closed_form_table_matches_sampled_table_and_is_rank_one():
+    # kernel_mode 1 puts the continuous transform at the torus wavenumbers
+    # (pinned above by quadrature); with damping the sampled table converges
+    # to it, so the two modes agree at low wavenumbers on a fine grid, and
+    # every closed-form A_m = omega^2 h (-i/(2 gamma)) e^{i gamma z_j}
+    # e^{-i gamma z'_l} has rank one (data planes above X)
+    p = synth.make_problem("cf", 128, 128, 4, [2 * np.pi], 1, (0, 0), h=0.125)
+    damping = 0.3
+    f = 0
+    tc, idx = model.system_table(p, f, kernel_mode=1, damping=damping)
+    k0 = model.k0_of(p, f) * (1 + 1j * damping)
+    ts = np.stack([model.plane_kernel_hat(p, k0, z) for z in model.zeta_index(p)[0]])
+    for (my, mx) in ((0, 0), (0, 3), (2, 5), (p.py - 1, 1)):
+        e = np.max(np.abs(tc[:, my, mx] - ts[:, my, mx]) / np.abs(tc[:, my, mx]))
+        assert e < 1e-6, (my, mx, e)
+    ms = np.array([0, 7, 129, 4000])
+    A = model.system_matrices(p, f, tc, idx, ms)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert np.all(s[:, 1] <= 1e-12 * s[:, 0])
+    assert np.all(s[:, 0] > 0)
