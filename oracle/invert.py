@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import model
-from .regularize import TAU, ETA, tikhonov_dp, tsvd_dp
+from .regularize import TAU, ETA, FLOOR, ROOT, tikhonov_dp, tikhonov_fixed, tsvd_dp
 
 
 def system_noise_level(W_f: np.ndarray, delta: float) -> float:
@@ -43,6 +43,9 @@ def solve_systems(p, f, What_f, delta, tau=TAU, eta=ETA, rule="tikhonov",
     V = np.zeros((N, p.nz), np.complex128)
     alpha = np.full(N, np.inf)
     branch = np.zeros(N, np.int8)
+    if rule == "global":
+        V, alpha, branch = _solve_global(p, f, tab, idx, wsys, dm, tau, eta, chunk)
+        return V.T.reshape(p.nz, p.py, p.px), alpha, branch
     for s0 in range(0, N, chunk):
         ms = np.arange(s0, min(N, s0 + chunk))
         A = model.system_matrices(p, f, tab, idx, ms)
@@ -54,6 +57,61 @@ def solve_systems(p, f, What_f, delta, tau=TAU, eta=ETA, rule="tikhonov",
         else:
             raise ValueError(rule)
     return V.T.reshape(p.nz, p.py, p.px), alpha, branch
+
+
+def _solve_global(p, f, tab, idx, wsys, dm, tau, eta, chunk, bisect_steps=240):
+    """One alpha for every system of the frequency (the paper's single noise
+    level delta for the whole data set): the total discrepancy
+    sum_m ||A_m v_m(alpha) - w_m||^2 = tau^2 N delta_m^2 (= tau^2 times the
+    noise energy of all N transformed systems, Parseval), solved by bisection
+    on log(alpha); alpha >= eta max_m ||A_m||_F^2, which is also the value for
+    noise-free data. Systems with w_m = 0 get v_m = 0 (branch zero)."""
+    N = wsys.shape[0]
+    live = np.linalg.norm(wsys, axis=1) > 0
+    ms_live = np.nonzero(live)[0]
+    s2s, b2s, rho2s, fro = [], [], [], []
+    for s0 in range(0, len(ms_live), chunk):
+        ms = ms_live[s0:s0 + chunk]
+        A = model.system_matrices(p, f, tab, idx, ms)
+        U, s, _ = np.linalg.svd(A, full_matrices=False)
+        b = np.einsum("sji,sj->si", U.conj(), wsys[ms])
+        rho2s.append(np.sum(np.abs(wsys[ms] - np.einsum("sji,si->sj", U, b)) ** 2, axis=1))
+        s2s.append(s * s)
+        b2s.append(np.abs(b) ** 2)
+        fro.append(np.sum(np.abs(A) ** 2, axis=(1, 2)))
+    V = np.zeros((N, p.nz), np.complex128)
+    alpha = np.full(N, np.inf)
+    branch = np.zeros(N, np.int8)
+    if len(ms_live) == 0:
+        return V, alpha, branch
+    s2, b2 = np.concatenate(s2s), np.concatenate(b2s)
+    rho2 = np.concatenate(rho2s)
+    amin = eta * float(np.max(np.concatenate(fro)))
+
+    def total(a):
+        t = a / (s2 + a)
+        return float(np.sum(t * t * b2) + np.sum(rho2))
+
+    target = tau * tau * N * dm * dm
+    if dm > 0 and total(amin) < target:
+        lo, hi = np.log(amin), np.log(float(np.max(s2))) + 1.0
+        while total(np.exp(hi)) < target:
+            hi += 4.0
+        for _ in range(bisect_steps):
+            mid = 0.5 * (lo + hi)
+            if total(np.exp(mid)) >= target:
+                hi = mid
+            else:
+                lo = mid
+        al, br = float(np.exp(0.5 * (lo + hi))), ROOT
+    else:
+        al, br = amin, FLOOR
+    for s0 in range(0, len(ms_live), chunk):
+        ms = ms_live[s0:s0 + chunk]
+        V[ms] = tikhonov_fixed(model.system_matrices(p, f, tab, idx, ms), wsys[ms], al)
+    alpha[ms_live] = al
+    branch[ms_live] = br
+    return V, alpha, branch
 
 
 def system_noise_level_hat(What_f, delta, N):

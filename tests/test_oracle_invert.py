@@ -124,3 +124,46 @@ def test_noise_free_inversion_is_fft_rounding_limited(small, eta, monkeypatch):
     monkeypatch.setattr(np.fft, "ifft2", lambda a, *k, **kw: sf.ifft2(a, *k, **kw, workers=1))
     y2 = invert.invert(p, Wd, u0, 0.01)
     assert np.linalg.norm(y2 - y1) / np.linalg.norm(y1) < 1e-12
+
+
+# ------------------------------------------------ one alpha per frequency
+
+def test_global_rule_with_one_nonzero_system_is_the_per_system_rule():
+    # data with a single nonzero wavenumber: the only live system sees the
+    # same target under both rules once tau_global = tau / sqrt(N)
+    p = synth.tiny_problem(nx=6, ny=5, nz=4, px=12, py=10)
+    rng = np.random.default_rng([8, 1])
+    What = np.zeros((1, p.nd, p.py, p.px), np.complex128)
+    What[0, :, 3, 7] = rng.standard_normal(p.nd) + 1j * rng.standard_normal(p.nd)
+    W = np.fft.ifft2(What)
+    N = p.px * p.py
+    tab, idx = model.system_table(p, 0)
+    Vs, a_s, b_s = invert.solve_systems(p, 0, What[0], 0.3, tau=1.5, tab=tab, idx=idx)
+    Vg, a_g, b_g = invert.solve_systems(p, 0, What[0], 0.3, tau=1.5 / np.sqrt(N), rule="global",
+                                        tab=tab, idx=idx)
+    m0 = 3 * p.px + 7
+    assert b_s[m0] == 2 and b_g[m0] == 2
+    assert np.count_nonzero(b_g) == 1 and np.count_nonzero(b_s) == 1
+    assert abs(a_g[m0] - a_s[m0]) <= 1e-13 * a_s[m0]
+    assert np.linalg.norm(Vg - Vs) <= 1e-13 * np.linalg.norm(Vs)
+    assert np.isfinite(W).all()
+
+
+def test_global_rule_meets_the_total_discrepancy(small):
+    # sum_m ||A_m v_m - w_m||^2 at the returned alpha, from the matrices
+    # themselves (not the SVD), equals tau^2 N delta_m^2; more noise gives a
+    # larger alpha
+    p, xi, u0, W, U, V = small
+    Wd = synth.add_noise(p, W, 0.02)
+    What = np.fft.fft2(Wd[0])
+    N = p.px * p.py
+    tab, idx = model.system_table(p, 0)
+    Vg, a, br = invert.solve_systems(p, 0, What, 0.02, tau=1.0, rule="global", tab=tab, idx=idx)
+    live = br > 0
+    assert live.sum() == N and np.all(br[live] == 2) and np.ptp(a[live]) == 0
+    A = model.system_matrices(p, 0, tab, idx, np.arange(N))
+    r = np.einsum("sjl,sl->sj", A, Vg.reshape(p.nz, N).T) - What.reshape(p.nd, N).T
+    dm = invert.system_noise_level_hat(What, 0.02, N)
+    assert abs(np.sum(np.abs(r) ** 2) / (N * dm * dm) - 1.0) <= 1e-10
+    _, a2, _ = invert.solve_systems(p, 0, What, 0.04, tau=1.0, rule="global", tab=tab, idx=idx)
+    assert a2[0] > a[0]
