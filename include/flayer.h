@@ -88,6 +88,15 @@ typedef struct {
   double damping;      /* kernel_mode 1 only: k0 -> k0 (1 + i damping), >= 0;
                           with damping = 0 a wavenumber on |k| = k0 gives
                           FL_ENUMERIC (gamma = 0) */
+  int alpha_rule;      /* Tikhonov parameter of item 1 (Section 4; Section 5.1
+                          gives one noise level for the whole data set):
+                          0 = per system: ||A_m v_m - w_m|| = tau delta_m
+                          (default); 1 = one alpha per frequency:
+                          sum_m ||A_m v_m - w_m||^2 = tau^2 N delta_m^2 over
+                          its N systems, alpha >= eta max_m ||A_m||_F^2, v = 0
+                          when sum_m ||w_m||^2 <= tau^2 N delta_m^2. Rule 1
+                          keeps every phase-scaled bidiagonal (32 nz bytes per
+                          system) and has no derivatives (FL_EUNSUPPORTED) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);
@@ -135,8 +144,7 @@ fl_status fl_invert(fl_plan *plan, const void *W, const void *u0, double delta,
  * forward factorization, the implicit derivative of the discrepancy-chosen
  * alpha (including the dependence of delta_m on ||W||). Runs the forward
  * first (same inputs as fl_invert). Errors: FL_EINVAL, FL_EUNSUPPORTED
- * (combine = 1, or more systems than the plan's factorization workspace
- * holds), FL_EDEVICE.
+ * (combine = 1, alpha_rule = 1), FL_EDEVICE.
  */
 fl_status fl_invert_vjp(fl_plan *plan, const void *W, const void *u0, double delta,
                         const void *grad_xi, void *grad_W, void *grad_u0);

@@ -65,7 +65,9 @@ def _solve_global(p, f, tab, idx, wsys, dm, tau, eta, chunk, bisect_steps=240):
     sum_m ||A_m v_m(alpha) - w_m||^2 = tau^2 N delta_m^2 (= tau^2 times the
     noise energy of all N transformed systems, Parseval), solved by bisection
     on log(alpha); alpha >= eta max_m ||A_m||_F^2, which is also the value for
-    noise-free data. Systems with w_m = 0 get v_m = 0 (branch zero)."""
+    noise-free data. Systems with w_m = 0 get v_m = 0 (branch zero), and so
+    do all systems when sum_m ||w_m||^2 <= tau^2 N delta_m^2 (v = 0 already
+    meets the total discrepancy: the per-system rule's zero branch)."""
     N = wsys.shape[0]
     live = np.linalg.norm(wsys, axis=1) > 0
     ms_live = np.nonzero(live)[0]
@@ -93,6 +95,8 @@ def _solve_global(p, f, tab, idx, wsys, dm, tau, eta, chunk, bisect_steps=240):
         return float(np.sum(t * t * b2) + np.sum(rho2))
 
     target = tau * tau * N * dm * dm
+    if dm > 0 and np.sum(np.abs(wsys[live]) ** 2) <= target:
+        return V, alpha, branch
     if dm > 0 and total(amin) < target:
         lo, hi = np.log(amin), np.log(float(np.max(s2))) + 1.0
         while total(np.exp(hi)) < target:

@@ -92,6 +92,14 @@ struct fl_plan {
   double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
   double *bd_d = nullptr, *bd_e = nullptr;
   z64* bd_dr = nullptr;
+  // one alpha per frequency (alpha_rule 1): phase-scaled bidiagonals of every
+  // compacted system, the search state and per-block partial sums
+  double *gd = nullptr, *ge = nullptr, *gfro = nullptr, *gpart = nullptr, *galpha = nullptr;
+  z64* gq = nullptr;
+  int *gf = nullptr, *gstart = nullptr;
+  GState* gst = nullptr;
+  signed char* gbranch = nullptr;
+  int gB = 0;
   // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
   bool has_adj = false;
   z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;
@@ -426,7 +434,7 @@ fl_status solve_prepare(fl_plan* p) {
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
   hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const z64*)p->What,
-                     p->nd, p->N, p->F, p->thr2, p->wn2, p->flag);
+                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), p->wn2, p->flag);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
   LAUNCHCHK();
@@ -451,9 +459,10 @@ fl_status run_bidiag(fl_plan* p, long c0) {
   return launch_bidiag<T>(p, (int)c0, gb, o);
 }
 
-// Discrepancy root, Tikhonov solve and back-transform of the same chunk.
+// Discrepancy root, Tikhonov solve and back-transform of the same chunk;
+// fixed: take alpha and the branch per frequency from the global search.
 template <typename T>
-fl_status run_dp(fl_plan* p, long c0) {
+fl_status run_dp(fl_plan* p, long c0, bool fixed = false) {
   DpArgs a{};
   a.dg = p->dg;
   a.sp = p->sp;
@@ -476,6 +485,8 @@ fl_status run_dp(fl_plan* p, long c0) {
   a.bd_e = p->bd_e;
   a.bd_dr = p->bd_dr;
   a.chunk0 = (int)c0;
+  a.alpha_fixed = fixed ? p->galpha : nullptr;
+  a.branch_fixed = fixed ? p->gbranch : nullptr;
   const unsigned gd = (unsigned)std::min<long>(p->C, p->dp_grid > 0 ? p->dp_grid : 16384);
   RUN(mark(p, FL_STAGE_DP));
   if (p->n <= 64)
@@ -494,10 +505,63 @@ fl_status solve_chunk(fl_plan* p, long c0) {
   return run_dp<T>(p, c0);
 }
 
+// Rounds of the per-frequency search: first spread, upward probe and the
+// multisection rounds of the per-system search.
+constexpr int kGlobalRounds = 26;
+
+// One alpha per frequency: factorize every compacted system and keep its
+// phase-scaled bidiagonal, search alpha on the summed discrepancy of each
+// frequency on the device (a fixed number of rounds; finished frequencies
+// skip theirs), then solve every system at its frequency's alpha,
+// re-factorizing chunk by chunk when the systems span several chunks.
+template <typename T>
+fl_status solve_global(fl_plan* p) {
+  const long FN = (long)p->F * p->N;
+  hipStream_t st = p->st;
+  const int F = p->F, n = p->n;
+  for (long c0 = 0; c0 < FN; c0 += p->C) {
+    RUN(run_bidiag<T>(p, c0));
+    GlobalArgs g{p->dg, p->sp, p->q, p->fro, p->list, p->count, (int)c0, p->C, n, p->N,
+                 p->gd, p->ge, p->gq, p->gfro, p->gf};
+    RUN(mark(p, FL_STAGE_DP));
+    const unsigned gp = (unsigned)std::min<long>(p->C, 16384);
+    if (n <= 64)
+      hipLaunchKernelGGL(k_global_prep<64>, dim3(gp), dim3(64), 0, st, g);
+    else
+      hipLaunchKernelGGL(k_global_prep<128>, dim3(gp), dim3(64), 0, st, g);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_global_ranges, dim3(std::min<unsigned>(nblk(FN, 256), 1024)), dim3(256), 0,
+                     st, p->gf, p->count, F, p->gstart);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_global_init, dim3(F), dim3(64), 0, st, p->gstart, p->gfro, p->wn2, p->list,
+                     p->thr2, p->N, p->opts.eta, p->gst, p->galpha, p->gbranch);
+  LAUNCHCHK();
+  for (int r = 0; r < kGlobalRounds; ++r) {
+    if (n <= 64)
+      hipLaunchKernelGGL(k_global_eval<64>, dim3(p->gB, F), dim3(64), 0, st, p->gst, p->gstart,
+                         p->gd, p->ge, p->gq, n, p->gpart);
+    else
+      hipLaunchKernelGGL(k_global_eval<128>, dim3(p->gB, F), dim3(64), 0, st, p->gst, p->gstart,
+                         p->gd, p->ge, p->gq, n, p->gpart);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_global_update, dim3(F), dim3(64), 0, st, p->gst, p->gpart, p->gB,
+                       (int)(r == kGlobalRounds - 1), p->galpha, p->gbranch);
+    LAUNCHCHK();
+  }
+  const bool refactor = FN > p->C;
+  for (long c0 = 0; c0 < FN; c0 += p->C) {
+    if (refactor) RUN(run_bidiag<T>(p, c0));
+    RUN(run_dp<T>(p, c0, true));
+  }
+  return FL_OK;
+}
+
 template <typename T>
 fl_status solve_systems(fl_plan* p) {
   const long FN = (long)p->F * p->N;
   RUN(solve_prepare<T>(p));
+  if (p->opts.alpha_rule == 1) return solve_global<T>(p);
   for (long c0 = 0; c0 < FN; c0 += p->C) RUN(solve_chunk<T>(p, c0));
   return FL_OK;
 }
@@ -704,6 +768,8 @@ fl_status ensure_adjoint_buffers(fl_plan* p) {
 fl_status adjoint_preconditions(fl_plan* p) {
   if (p->opts.combine != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the least-squares xi (combine 0)");
+  if (p->opts.alpha_rule != 0)
+    return fail(FL_EUNSUPPORTED, "derivatives are implemented for the per-system alpha (alpha_rule 0)");
   return ensure_adjoint_buffers(p);
 }
 
@@ -1124,6 +1190,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   }
   if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
   if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
+  if (o.alpha_rule != 0 && o.alpha_rule != 1) return fail(FL_EINVAL, "alpha_rule must be 0 or 1");
 
   fl_plan* p = new fl_plan();
   p->nx = nx;
@@ -1215,6 +1282,19 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->bd_dr, C * nz);
   PALLOC(p->alpha, FN);
   PALLOC(p->branch, FN);
+  if (o.alpha_rule == 1) {
+    p->gB = (int)std::min<long>(2048, N);
+    PALLOC(p->gd, FN * nz);
+    PALLOC(p->ge, FN * nz);
+    PALLOC(p->gq, FN * nz);
+    PALLOC(p->gfro, FN);
+    PALLOC(p->gf, FN);
+    PALLOC(p->gstart, F + 1);
+    PALLOC(p->gst, F);
+    PALLOC(p->galpha, F);
+    PALLOC(p->gbranch, F);
+    PALLOC(p->gpart, (long)F * p->gB * 64);
+  }
 #undef PALLOC
   fl_status s = build_tables(p);
   if (s != FL_OK) return bail(s);

@@ -30,7 +30,8 @@ namespace fl {
 template <typename T>
 __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What, int nd, long N,
                                                   int F, const double* __restrict__ thr2,
-                                                  double* __restrict__ wn2, int* __restrict__ flag) {
+                                                  int solve_all, double* __restrict__ wn2,
+                                                  int* __restrict__ flag) {
   long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (fm >= (long)F * N) return;
   int f = (int)(fm / N);
@@ -53,9 +54,10 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   }
   const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   wn2[fm] = s;
-  // thr2[f] < 0 marks noise-free data: every nonzero system is solved
+  // thr2[f] < 0 marks noise-free data, solve_all the rule with one alpha per
+  // frequency: then every nonzero system is solved
   double t = thr2[f];
-  flag[fm] = (t < 0.0) ? (s > 0.0) : (s > t);
+  flag[fm] = (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
 }
 
 __device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
@@ -467,6 +469,8 @@ struct DpArgs {
   double* bd_d;        // [C][n] real bidiagonal and right phases, kept for
   double* bd_e;        //        the derivative kernels
   z64* bd_dr;
+  const double* alpha_fixed;       // per frequency, or NULL: alpha given (one per
+  const signed char* branch_fixed; // frequency) instead of the per-system search
 };
 
 // phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
@@ -540,6 +544,98 @@ __device__ void elden_solve(const double* __restrict__ d, const double* __restri
   }
 }
 
+// Phase scaling of one system's complex bidiagonal (sy: diagonal, srr:
+// superdiagonal, sq: q in LDS) to B = D_L B' D_R^H with B' real and
+// nonnegative: writes sd, se (B'), sdr (right phases) and q' = D_L^H q into sq.
+// One wave; the caller synchronizes afterwards.
+template <int NMAX>
+__device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, double* se, z64* sq,
+                                               const z64* srr, const z64* sy, z64* sdr) {
+  // B = D_L B' D_R^H with B' real nonnegative. The right phases obey
+  // r_i = rho_i r_{i-1} (or restart at a zero entry), an affine recurrence
+  // evaluated by a parallel prefix over the lanes (elements lane, lane + 64).
+  {
+    constexpr int H = (NMAX + 63) / 64;  // elements per lane
+    z64 ra[2], rb[2], pd[2];
+    bool dz[2];
+    ra[1] = mk(1.0, 0.0);
+    rb[1] = mk(0.0, 0.0);
+    pd[1] = mk(1.0, 0.0);
+    dz[1] = true;
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int i = lane + 64 * h;
+      z64 am = mk(1.0, 0.0), bm = mk(0.0, 0.0), ph = mk(1.0, 0.0);
+      dz[h] = true;
+      if (i < n) {
+        const z64 dgi = sy[i];
+        const double d2 = nrm2(dgi);
+        const double idd = d2 > 0.0 ? rsq_nr(d2) : 0.0;
+        sd[i] = d2 * idd;
+        dz[h] = !(d2 > 0.0);
+        if (d2 > 0.0) ph = mk(dgi.x * idd, dgi.y * idd);
+        z64 cs = mk(1.0, 0.0);  // conj(phase(sp_i))
+        double ei = 0.0;
+        if (i < n - 1) {
+          const z64 spi = srr[i];
+          const double s2 = nrm2(spi);
+          const double is = s2 > 0.0 ? rsq_nr(s2) : 0.0;
+          ei = s2 * is;
+          if (s2 > 0.0) cs = mk(spi.x * is, -spi.y * is);
+          if (!(s2 > 0.0)) {
+            am = mk(0.0, 0.0);
+            bm = mk(1.0, 0.0);
+          } else if (!(d2 > 0.0)) {
+            am = mk(0.0, 0.0);
+            bm = cs;
+          } else {
+            am = ph * cs;
+          }
+        }
+        se[i] = ei;
+      }
+      pd[h] = ph;
+      ra[h] = am;
+      rb[h] = bm;
+    }
+    // inclusive scan of x -> a x + b within each half (Hillis-Steele)
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const double ax = __shfl_up(ra[h].x, o), ay = __shfl_up(ra[h].y, o);
+        const double bx = __shfl_up(rb[h].x, o), by = __shfl_up(rb[h].y, o);
+        if (lane >= o) {
+          // (a, b) o (a', b') = (a a', a b' + b)
+          const z64 ap = mk(ax, ay), bp = mk(bx, by);
+          rb[h] = cfma(rb[h], ra[h], bp);
+          ra[h] = ra[h] * ap;
+        }
+      }
+    }
+    // right phase entering element i: x_{i-1}, with x_{-1} = 1
+    const z64 x0 = ra[0] + rb[0];                       // x_lane
+    const z64 end0 = mk(__shfl(x0.x, 63), __shfl(x0.y, 63));
+    const z64 x1 = cfma(rb[1], ra[1], end0);            // x_{lane+64}
+    z64 in0 = mk(__shfl_up(x0.x, 1), __shfl_up(x0.y, 1));
+    z64 in1 = mk(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));
+    if (lane == 0) {
+      in0 = mk(1.0, 0.0);
+      in1 = end0;
+    }
+    const z64 xin[2] = {in0, in1};
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const int i = lane + 64 * h;
+      if (i < n) {
+        sdr[i] = xin[h];
+        const z64 dl = dz[h] ? mk(1.0, 0.0) : pd[h] * xin[h];
+        sq[i] = cmulc(dl, sq[i]);
+      }
+    }
+  }
+}
+
 // One single-wave workgroup per active system: phase-scale the bidiagonal to
 // a real one, choose alpha by the discrepancy principle with a 64-way
 // multisection on log(alpha), solve at that alpha (Elden), apply the right
@@ -564,89 +660,7 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       sq[i] = a.q[(long)sl * n + i];
     }
     __syncthreads();
-    // B = D_L B' D_R^H with B' real nonnegative. The right phases obey
-    // r_i = rho_i r_{i-1} (or restart at a zero entry), an affine recurrence
-    // evaluated by a parallel prefix over the lanes (elements lane, lane + 64).
-    {
-      constexpr int H = (NMAX + 63) / 64;  // elements per lane
-      z64 ra[2], rb[2], pd[2];
-      bool dz[2];
-      ra[1] = mk(1.0, 0.0);
-      rb[1] = mk(0.0, 0.0);
-      pd[1] = mk(1.0, 0.0);
-      dz[1] = true;
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int i = lane + 64 * h;
-        z64 am = mk(1.0, 0.0), bm = mk(0.0, 0.0), ph = mk(1.0, 0.0);
-        dz[h] = true;
-        if (i < n) {
-          const z64 dgi = sy[i];
-          const double d2 = nrm2(dgi);
-          const double idd = d2 > 0.0 ? rsq_nr(d2) : 0.0;
-          sd[i] = d2 * idd;
-          dz[h] = !(d2 > 0.0);
-          if (d2 > 0.0) ph = mk(dgi.x * idd, dgi.y * idd);
-          z64 cs = mk(1.0, 0.0);  // conj(phase(sp_i))
-          double ei = 0.0;
-          if (i < n - 1) {
-            const z64 spi = srr[i];
-            const double s2 = nrm2(spi);
-            const double is = s2 > 0.0 ? rsq_nr(s2) : 0.0;
-            ei = s2 * is;
-            if (s2 > 0.0) cs = mk(spi.x * is, -spi.y * is);
-            if (!(s2 > 0.0)) {
-              am = mk(0.0, 0.0);
-              bm = mk(1.0, 0.0);
-            } else if (!(d2 > 0.0)) {
-              am = mk(0.0, 0.0);
-              bm = cs;
-            } else {
-              am = ph * cs;
-            }
-          }
-          se[i] = ei;
-        }
-        pd[h] = ph;
-        ra[h] = am;
-        rb[h] = bm;
-      }
-      // inclusive scan of x -> a x + b within each half (Hillis-Steele)
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const double ax = __shfl_up(ra[h].x, o), ay = __shfl_up(ra[h].y, o);
-          const double bx = __shfl_up(rb[h].x, o), by = __shfl_up(rb[h].y, o);
-          if (lane >= o) {
-            // (a, b) o (a', b') = (a a', a b' + b)
-            const z64 ap = mk(ax, ay), bp = mk(bx, by);
-            rb[h] = cfma(rb[h], ra[h], bp);
-            ra[h] = ra[h] * ap;
-          }
-        }
-      }
-      // right phase entering element i: x_{i-1}, with x_{-1} = 1
-      const z64 x0 = ra[0] + rb[0];                       // x_lane
-      const z64 end0 = mk(__shfl(x0.x, 63), __shfl(x0.y, 63));
-      const z64 x1 = cfma(rb[1], ra[1], end0);            // x_{lane+64}
-      z64 in0 = mk(__shfl_up(x0.x, 1), __shfl_up(x0.y, 1));
-      z64 in1 = mk(__shfl_up(x1.x, 1), __shfl_up(x1.y, 1));
-      if (lane == 0) {
-        in0 = mk(1.0, 0.0);
-        in1 = end0;
-      }
-      const z64 xin[2] = {in0, in1};
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int i = lane + 64 * h;
-        if (i < n) {
-          sdr[i] = xin[h];
-          const z64 dl = dz[h] ? mk(1.0, 0.0) : pd[h] * xin[h];
-          sq[i] = cmulc(dl, sq[i]);
-        }
-      }
-    }
+    dp_phase_scale<NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
     __syncthreads();
     for (int i = lane; i < n; i += 64) {
       a.bd_d[(long)sl * n + i] = sd[i];
@@ -658,7 +672,10 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     const double amin = a.eta * fro;
     double al = amin;
     signed char br = 1;
-    if (T >= 0.0) {
+    if (a.alpha_fixed) {
+      al = a.alpha_fixed[f];
+      br = a.branch_fixed[f];
+    } else if (T >= 0.0) {
       // round 0: lane 0 tests the floor alpha_min; lanes 1..63 spread over
       // (log alpha_min, log ||A||_F^2 + 1], where the root almost always is
       const double h0 = log(fro) + 1.0;
@@ -738,6 +755,15 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
         al = exp(xr);
       }
     }
+    if (br == 0) {
+      // one alpha per frequency with the data inside the noise level: v^ = 0
+      if (lane == 0) {
+        a.alpha[fm] = INFINITY;
+        a.branch[fm] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
     if (lane == 0) elden_solve(sd, se, sq, n, al, srho, soff, srr, sy);
     __syncthreads();
     // v^ = V (D_R y'), V = P_0 P_1 ... P_{n-3}
@@ -792,6 +818,264 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------- one alpha per frequency
+
+struct GlobalArgs {
+  const z64* dg;        // chunk workspace as for k_dp_solve
+  const z64* sp;
+  const z64* q;
+  const double* fro;
+  const int* list;
+  const int* count;
+  int chunk0, C, n;
+  long N;
+  double* gd;           // [FN][n] phase-scaled real bidiagonal, by compacted index
+  double* ge;
+  z64* gq;              // [FN][n] q' = D_L^H U^H w
+  double* gfro;         // [FN] ||A||_F^2
+  int* gf;              // [FN] frequency
+};
+
+// Phase-scale every system of a chunk and keep its real bidiagonal, q' and
+// ||A||_F^2 under its compacted index (one wave per system).
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_global_prep(GlobalArgs a) {
+  __shared__ double sd[NMAX], se[NMAX];
+  __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
+  const int lane = threadIdx.x;
+  const int n = a.n;
+  const int total = *a.count;
+  for (int sl = blockIdx.x; sl < a.C; sl += gridDim.x) {
+    const int gs = a.chunk0 + sl;
+    if (gs >= total) break;
+    for (int i = lane; i < n; i += 64) {
+      sy[i] = a.dg[(long)sl * n + i];
+      srr[i] = a.sp[(long)sl * n + i];
+      sq[i] = a.q[(long)sl * n + i];
+    }
+    __syncthreads();
+    dp_phase_scale<NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) {
+      a.gd[(long)gs * n + i] = sd[i];
+      a.ge[(long)gs * n + i] = se[i];
+      a.gq[(long)gs * n + i] = sq[i];
+    }
+    if (lane == 0) {
+      a.gfro[gs] = a.fro[sl];
+      a.gf[gs] = (int)(a.list[gs] / a.N);
+    }
+    __syncthreads();
+  }
+}
+
+// start[f] = first compacted index of frequency f (systems are compacted in
+// increasing f * N + m), start[F] = total
+__global__ void k_global_ranges(const int* __restrict__ gf, const int* __restrict__ count, int F,
+                                int* __restrict__ start) {
+  const int total = *count;
+  for (int gs = blockIdx.x * blockDim.x + threadIdx.x; gs < total; gs += gridDim.x * blockDim.x) {
+    const int f = gf[gs];
+    const int fp = gs > 0 ? gf[gs - 1] : -1;
+    for (int g = fp + 1; g <= f; ++g) start[g] = gs;  // also frequencies with no system
+    if (gs == total - 1)
+      for (int g = f + 1; g <= F; ++g) start[g] = total;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && total == 0)
+    for (int g = 0; g <= F; ++g) start[g] = 0;
+}
+
+// Search state of one frequency: the total discrepancy
+// Phi(x) = sum_m phi_m(exp x) is evaluated at x0 + step (l + 1), l = 0..63,
+// per round; [lo, hi] brackets the root of Phi = target.
+struct GState {
+  double lo, hi, flo, fhi;  // bracket and Phi at its ends (NaN: unknown)
+  double x0, step, a1;      // this round's points and the window's right end
+  double h0, target, amin;
+  int phase;                // 0 first spread, 1 upward probe, 2 multisection, 3 done
+  int miss;
+};
+
+// Per frequency (one wave): alpha_min = eta max_m ||A_m||_F^2, the target
+// tau^2 N delta_m^2 = N thr2[f], and the cases settled without a search:
+// no system, noise-free data (floor), or sum_m ||w_m||^2 <= target (v = 0).
+__global__ __launch_bounds__(64) void k_global_init(const int* __restrict__ start,
+                                                    const double* __restrict__ gfro,
+                                                    const double* __restrict__ wn2,
+                                                    const int* __restrict__ list,
+                                                    const double* __restrict__ thr2, long N,
+                                                    double eta, GState* __restrict__ S,
+                                                    double* __restrict__ alpha_f,
+                                                    signed char* __restrict__ branch_f) {
+  const int f = blockIdx.x, lane = threadIdx.x;
+  const int s0 = start[f], s1 = start[f + 1];
+  double mx = 0.0, ws = 0.0;
+  for (int gs = s0 + lane; gs < s1; gs += 64) {
+    mx = fmax(mx, gfro[gs]);
+    ws += wn2[list[gs]];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  ws = group_sum<64>(ws);
+  if (lane != 0) return;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  GState g;
+  g.flo = g.fhi = nan;
+  g.miss = 0;
+  g.amin = eta * mx;
+  g.target = thr2[f] < 0.0 ? -1.0 : thr2[f] * (double)N;
+  g.h0 = mx > 0.0 ? log(mx) + 1.0 : 0.0;
+  g.lo = g.hi = g.a1 = 0.0;
+  g.x0 = g.step = 0.0;
+  g.phase = 3;
+  double al = INFINITY;
+  signed char br = 0;
+  if (s1 > s0 && mx > 0.0) {
+    if (g.target < 0.0) {
+      al = g.amin;
+      br = 1;
+    } else if (ws > g.target) {
+      // lane 0 tests the floor; lanes 1..63 spread over (log alpha_min, h0]
+      g.lo = log(g.amin);
+      g.step = (g.h0 - g.lo) / 63.0;
+      g.x0 = g.lo - g.step;
+      g.phase = 0;
+    }
+  }
+  S[f] = g;
+  alpha_f[f] = al;
+  branch_f[f] = br;
+}
+
+// Phi at this round's 64 points, partial sums per block: grid (B, F), one
+// wave per block; block b takes a contiguous slice of frequency f's systems,
+// one system after another, so the summation order is fixed.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_global_eval(const GState* __restrict__ S,
+                                                    const int* __restrict__ start,
+                                                    const double* __restrict__ gd,
+                                                    const double* __restrict__ ge,
+                                                    const z64* __restrict__ gq, int n,
+                                                    double* __restrict__ part) {
+  __shared__ double sd[NMAX], se[NMAX];
+  __shared__ z64 sq[NMAX];
+  const int f = blockIdx.y, b = blockIdx.x, B = gridDim.x, lane = threadIdx.x;
+  if (S[f].phase == 3) return;
+  const int s0 = start[f], s1 = start[f + 1];
+  const int K = (s1 - s0 + B - 1) / B;
+  const int a = s0 + b * K, e = min(a + K, s1);
+  const double al = exp(S[f].x0 + S[f].step * (lane + 1));
+  double acc = 0.0;
+  for (int gs = a; gs < e; ++gs) {
+    for (int i = lane; i < n; i += 64) {
+      sd[i] = gd[(long)gs * n + i];
+      se[i] = ge[(long)gs * n + i];
+      sq[i] = gq[(long)gs * n + i];
+    }
+    __syncthreads();
+    acc += phi_fwd(sd, se, sq, n, al);
+    __syncthreads();
+  }
+  part[((long)f * B + b) * 64 + lane] = acc;
+}
+
+// One round of the search per frequency (one wave): Phi from the partial
+// sums in block order, then the bracket update of the per-system search
+// (first spread, upward probe in steps of 4, 64-point multisection with
+// secant windows); a converged bracket, or the last round, fixes alpha at
+// the secant point.
+__global__ __launch_bounds__(64) void k_global_update(GState* __restrict__ S,
+                                                      const double* __restrict__ part, int B,
+                                                      int last, double* __restrict__ alpha_f,
+                                                      signed char* __restrict__ branch_f) {
+  const int f = blockIdx.x, lane = threadIdx.x;
+  GState g = S[f];
+  if (g.phase == 3) return;
+  double ph = 0.0;
+  for (int b = 0; b < B; ++b) ph += part[((long)f * B + b) * 64 + lane];
+  const double T = g.target;
+  const unsigned long long bal = __ballot(ph >= T);
+  if (g.phase == 0) {
+    if (bal & 1ull) {
+      g.phase = 3;
+      if (lane == 0) {
+        S[f] = g;
+        alpha_f[f] = g.amin;
+        branch_f[f] = 1;
+      }
+      return;
+    }
+    if (bal) {
+      const int l1 = __ffsll((long long)bal) - 1;
+      g.hi = g.x0 + g.step * (l1 + 1);
+      g.fhi = __shfl(ph, l1);
+      g.lo = g.x0 + g.step * l1;
+      g.flo = __shfl(ph, l1 - 1);
+    } else {
+      g.lo = g.h0;
+      g.flo = __shfl(ph, 63);
+      g.x0 = g.h0;
+      g.step = 4.0;
+      g.phase = 1;
+      if (lane == 0) S[f] = g;
+      return;
+    }
+  } else if (g.phase == 1) {
+    if (bal) {
+      const int l1 = __ffsll((long long)bal) - 1;
+      g.hi = g.x0 + 4.0 * (l1 + 1);
+      g.fhi = __shfl(ph, l1);
+      if (l1 > 0) {
+        g.lo = g.x0 + 4.0 * l1;
+        g.flo = __shfl(ph, l1 - 1);
+      }
+    } else {
+      g.hi = g.lo = g.h0 + 4.0 * 64;
+    }
+  } else {
+    const double a0 = g.x0;
+    if (bal) {
+      const int l1 = __ffsll((long long)bal) - 1;
+      g.miss = l1 == 0 && a0 > g.lo;
+      g.hi = a0 + g.step * (l1 + 1);
+      g.fhi = __shfl(ph, l1);
+      if (l1 > 0) {
+        g.lo = a0 + g.step * l1;
+        g.flo = __shfl(ph, l1 - 1);
+      }
+    } else {
+      g.miss = g.a1 < g.hi;
+      g.lo = a0 + g.step * 64;
+      g.flo = __shfl(ph, 63);
+    }
+  }
+  const bool known = g.flo == g.flo && g.fhi == g.fhi && g.fhi > g.flo;
+  const double wdt = g.hi - g.lo;
+  if (last || !(wdt > 1e-13 * fmax(1.0, fabs(g.hi)))) {
+    double xr = 0.5 * (g.lo + g.hi);
+    if (known) xr = fmin(g.hi, fmax(g.lo, g.lo + (T - g.flo) / (g.fhi - g.flo) * wdt));
+    g.phase = 3;
+    if (lane == 0) {
+      S[f] = g;
+      alpha_f[f] = exp(xr);
+      branch_f[f] = 2;
+    }
+    return;
+  }
+  double a0 = g.lo, a1 = g.hi;
+  if (!g.miss && known) {
+    const double xs = g.lo + (T - g.flo) / (g.fhi - g.flo) * wdt;
+    const double hw = fmax(0.25 * wdt * wdt, 1e-5 * wdt);
+    a0 = fmax(g.lo, xs - hw);
+    a1 = fmin(g.hi, xs + hw);
+  }
+  g.x0 = a0;
+  g.a1 = a1;
+  g.step = (a1 - a0) / (a1 < g.hi ? 64.0 : 65.0);
+  g.phase = 2;
+  if (lane == 0) S[f] = g;
 }
 
 }  // namespace fl

@@ -38,6 +38,7 @@ class FlOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("max_chunk", ctypes.c_int),
         ("kernel_mode", ctypes.c_int), ("damping", ctypes.c_double),
+        ("alpha_rule", ctypes.c_int),
     ]
 
 
@@ -147,12 +148,13 @@ class Plan:
 
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
                  tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0,
-                 kernel_mode=0, damping=0.0):
+                 kernel_mode=0, damping=0.0, alpha_rule=0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
         o.max_chunk = max_chunk
         o.kernel_mode, o.damping = kernel_mode, damping
+        o.alpha_rule = alpha_rule
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)

@@ -101,3 +101,8 @@ def test_closed_form_kernel_needs_damping_on_the_k0_circle():
     assert st == flayer.FL_EINVAL and "kernel_mode" in msg
     st, msg, out = _create(kernel_mode=1, damping=-1.0)
     assert st == flayer.FL_EINVAL and "damping" in msg
+
+
+def test_alpha_rule_is_validated():
+    st, msg, out = _create(alpha_rule=2)
+    assert st == flayer.FL_EINVAL and "alpha_rule" in msg and not out.value

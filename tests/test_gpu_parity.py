@@ -335,3 +335,65 @@ def test_closed_form_kernel_matches_oracle(small, precision):
     e = rel(xi, ref_xi)
     say("closed form precision", precision, "xi error", e, "Vhat", rel(st["Vhat"], ref["Vhat"]))
     assert e <= (TOL if precision == 0 else MIXED_TOL)
+
+
+def _global_case(name):
+    if name == "small":
+        p = synth.workload("small")[0]
+        W, u0 = _born_data(p, 0.0)
+        return p, W, u0
+    p, u0, W = _ragged()
+    return p, W, u0
+
+
+@pytest.mark.parametrize("case,delta,tau,kw", [
+    ("small", 0.01, 1.5, {}),
+    ("small", 0.01, 1.5, {"precision": 1}),
+    ("small", 0.0, 1.5, {}),
+    ("ragged", 0.02, 1.0, {}),
+    ("ragged", 0.02, 1.0, {"max_chunk": 300}),
+    ("ragged", 0.7, 1.5, {}),
+])
+def test_one_alpha_per_frequency_matches_oracle(case, delta, tau, kw):
+    """alpha_rule 1 (one alpha per frequency from the summed discrepancy)
+    against the oracle's rule "global": the same branch and alpha for every
+    system, and the stages; with max_chunk the systems span several chunks
+    (factorized twice); tau delta >= 1 leaves v = 0 everywhere."""
+    p, W, u0 = _global_case(case)
+    Wd = synth.add_noise(p, W, delta)
+    ref_xi, ref = invert.invert(p, Wd, u0, delta, tau=tau, rule="global", stages=True)
+    xi, st = gpu_run(p, Wd, u0, delta, tau=tau, alpha_rule=1, **kw)
+    br_ref = ref["branch"].reshape(st["branch"].shape)
+    assert np.count_nonzero(br_ref != st["branch"]) == 0
+    a_ref = ref["alpha"].reshape(st["alpha"].shape)
+    fin = np.isfinite(a_ref)
+    assert np.array_equal(fin, np.isfinite(st["alpha"]))
+    if fin.any():
+        ra = np.max(np.abs(st["alpha"][fin] - a_ref[fin]) / a_ref[fin])
+        say("global rule", case, delta, kw, "alpha err", ra, "branches", np.unique(br_ref))
+        assert ra <= (tol_for(delta) if kw.get("precision", 0) == 0 else 1e-8)
+    if kw.get("precision", 0) == 1:
+        e = mixed_errors(ref_xi, ref, xi, st)
+        say("global rule mixed errors", e)
+        assert e["xi"] <= MIXED_TOL
+        return
+    tol = tol_for(delta)
+    assert rel(st["Vhat"], ref["Vhat"]) <= tol
+    assert rel(st["v"], ref["v"]) <= tol
+    assert rel(st["u"], ref["u"]) <= tol
+    assert rel(xi, ref_xi) <= tol
+    if case == "ragged" and delta == 0.7:
+        assert np.all(br_ref == 0) and not st["Vhat"].any()
+
+
+def test_one_alpha_per_frequency_has_no_derivatives(small):
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import FlError, Plan
+    p, xi_true, u0, W = small
+    plan = Plan.from_problem(p, alpha_rule=1)
+    Wt = torch.from_numpy(W).cuda()
+    ut = torch.from_numpy(u0).cuda()
+    with pytest.raises(FlError, match="alpha_rule"):
+        plan.vjp(Wt, ut, 0.01, torch.ones((p.nz, p.ny, p.nx), dtype=torch.complex128,
+                                           device="cuda"))
+    plan.close()

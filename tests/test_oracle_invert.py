@@ -167,3 +167,16 @@ def test_global_rule_meets_the_total_discrepancy(small):
     assert abs(np.sum(np.abs(r) ** 2) / (N * dm * dm) - 1.0) <= 1e-10
     _, a2, _ = invert.solve_systems(p, 0, What, 0.04, tau=1.0, rule="global", tab=tab, idx=idx)
     assert a2[0] > a[0]
+
+
+def test_global_rule_data_inside_the_noise_level_give_zero(small):
+    # tau delta >= 1: v = 0 meets the total discrepancy (sum_m ||w_m||^2 =
+    # N ||W||^2 by Parseval); just below, a root with a large alpha
+    p, xi, u0, W, U, V = small
+    What = np.fft.fft2(W[0])
+    tab, idx = model.system_table(p, 0)
+    Vg, a, br = invert.solve_systems(p, 0, What, 1.0, tau=1.0 + 1e-9, rule="global", tab=tab,
+                                     idx=idx)
+    assert not Vg.any() and np.all(br == 0) and np.all(np.isinf(a))
+    Vg, a, br = invert.solve_systems(p, 0, What, 0.9, tau=1.0, rule="global", tab=tab, idx=idx)
+    assert np.all(br == 2) and Vg.any()
