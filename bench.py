@@ -32,10 +32,12 @@ WORKLOAD_TEXT = {
 }
 
 
-def stage_units(p, active, n, b=16):
+def stage_units(p, active, factorized, n, b=16):
     """Algorithmic work per timed step and stage: HBM bytes that the stage
     must move at least (b bytes per complex element of the FFT-side arrays,
-    16 for the complex128 input W, the FP64 v, u, u0 and xi), or FP64 flops."""
+    16 for the complex128 input W, the FP64 v, u, u0 and xi), or FP64 flops.
+    active: systems solved; factorized: matrices bidiagonalized (one per
+    active symmetry orbit when factorizations are shared)."""
     F, N, nd, nz = p.n_omega, p.px * p.py, p.nd, p.nz
     nvox = p.nx * p.ny * p.nz
     rows_y = F * nz * p.ny * p.px      # rows of X's y-window on the padded x axis
@@ -56,9 +58,11 @@ def stage_units(p, active, n, b=16):
         "conv_irows": ("GB/s", rows_y * b + 2 * F * nvox * 16),
         "xi": ("GB/s", 2 * F * nvox * 16 + nvox * 16),
         # complex Householder bidiagonalization of an n x n matrix: 4 x (8/3) n^3
-        "bidiag": ("TFLOP/s", active * 32.0 / 3.0 * n ** 3),
-        # per system: about 60 Newton trials of ~60 flops per row (estimate)
-        "dp": ("TFLOP/s", active * 60.0 * 60.0 * n),
+        "bidiag": ("TFLOP/s", factorized * 32.0 / 3.0 * n ** 3),
+        # per system: 4 multisection rounds x 64 trial alphas x 20 flops per
+        # row of the discrepancy recurrence, q = U^H w and v^ = V y (8 n^2
+        # flops each), the bidiagonal Tikhonov solve (about 40 n)
+        "dp": ("TFLOP/s", active * (4 * 64 * 20.0 * n + 16.0 * n * n + 40.0 * n)),
         "backtransform": ("GB/s", 0),
     }
     return u
@@ -207,6 +211,7 @@ def main():
                 "blobs, seeded complex noise of relative level delta",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}",
                    "delta": delta, "precision": head, "active_systems": h["active"],
+                   "factorized_systems": h["factorized"],
                    "systems": p.n_omega * p.px * p.py, "n": p.nz, "plan_ms": h["plan_ms"],
                    "tune_ms": h["tune_ms"], "schedule": h["tuning"]},
         "roofline": h["roofline"],
@@ -245,6 +250,7 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
         plan.invert(Wd, u0, delta, xi)
     torch.cuda.synchronize()
     active = plan.active_systems()
+    factorized = plan.factorized_systems()
     plan.profile(True)
     plan.profile_read()
     st = torch.cuda.current_stream()
@@ -261,7 +267,7 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
     plan.profile(False)
     ms = total_ms / args.steps
     esz = 8 if prec else 16
-    units = stage_units(p, active, p.nz, esz)
+    units = stage_units(p, active, factorized, p.nz, esz)
     dom = max(stages, key=lambda k: stages[k][0])
     dms, dcount = stages[dom]
     per_launch_ms = dms / max(dcount, 1)
@@ -276,8 +282,9 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
     kname = dom
     if dom == "bidiag":
         tr, tc, wpe = tuning["schedule"]
-        kname = (f"k_bidiag<{tr}, {tc}, {p.nz // tr}, {p.nz // tc}, "
-                 f"{'float' if prec else 'double'}, {wpe}>")
+        kname = (f"k_bidiag<{tr}, {tc}, {p.nz // tr}, {p.nz // tc}, double, {wpe}>")
+    elif dom == "dp":
+        kname = f"k_dp_solve<{64 if p.nz <= 64 else 128}>"
     tr_ = profiled_traffic(args.workload, prec, kname)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": tr_["bytes"] if tr_ else None,
@@ -298,7 +305,8 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev):
                "frac": round(fb / (fms * 1e-3) / 1e9 / PEAK_HBM_GBS, 3),
                "ms_per_step": fms / args.steps}
     out = {"ms": ms, "plan_ms": plan_ms, "tune_ms": tune_ms, "tuning": tuning,
-           "hbm_stages": hbm, "fft_stages": fft_all, "active": active, "roofline": roof,
+           "hbm_stages": hbm, "fft_stages": fft_all, "active": active,
+           "factorized": factorized, "roofline": roof,
            "stages": {k: v[0] / args.steps for k, v in stages.items()},
            "xi": xi.cpu().numpy()}
     plan.close()

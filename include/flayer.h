@@ -97,6 +97,14 @@ typedef struct {
                           when sum_m ||w_m||^2 <= tau^2 N delta_m^2. Rule 1
                           keeps every phase-scaled bidiagonal (32 nz bytes per
                           system) and has no derivatives (FL_EUNSUPPORTED) */
+  int factor_per_system; /* 0 (default): the kernel G is radial, so A_m is the
+                          same for wavenumbers related by the torus symmetries
+                          (kx -> -kx, ky -> -ky, and kx <-> ky when px = py):
+                          fl_invert factorizes each such orbit once (about N/8
+                          systems on a square torus) and applies the orbit's
+                          left reflectors to every member's data; 1 = one
+                          factorization per system (always so for alpha_rule 1
+                          and the derivative calls) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);
@@ -181,12 +189,14 @@ typedef struct {
   int last_active;         /* systems solved by the last fl_invert (all
                               frequencies); valid after the stream syncs and
                               a call to fl_plan_refresh_info */
+  int last_factorized;     /* matrices A_m it factorized: the active orbits
+                              with shared factorizations, else last_active */
 } fl_plan_info_t;
 
 fl_status fl_plan_info(const fl_plan *plan, fl_plan_info_t *info);
 
-/* Copy the active-system count of the last fl_invert into the info block
- * (synchronizes the plan's stream). */
+/* Copy the active-system and factorization counts of the last fl_invert into
+ * the info block (synchronizes the plan's stream). */
 fl_status fl_plan_refresh_info(fl_plan *plan);
 
 /*

@@ -100,6 +100,15 @@ struct fl_plan {
   GState* gst = nullptr;
   signed char* gbranch = nullptr;
   int gB = 0;
+  // shared factorizations: orbits of the wavenumber symmetries (orep [N]
+  // representative, omem [N][8] members of a representative's orbit), the
+  // active orbits compacted like the systems, and the left reflectors
+  bool orbits = false;
+  int n_orb = 0;
+  int *orep = nullptr, *omem = nullptr, *oflag = nullptr, *olist = nullptr, *ocount = nullptr,
+      *oslot = nullptr;
+  z64* refl_l = nullptr;
+  double* gam_l = nullptr;
   // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
   bool has_adj = false;
   z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;
@@ -116,7 +125,8 @@ struct fl_plan {
   int* b_active = nullptr;
   std::vector<void*> allocs;
   size_t bytes = 0;
-  int last_active = -1;
+  int last_active = -1, last_factorized = -1;
+  bool last_shared = false;  // the last solve used orbit factorizations
   // stage tracing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -369,7 +379,8 @@ const std::vector<BdVariant>& bd_variants(int n) {
 }
 
 template <typename T>
-fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
+fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk0, int C,
+                        unsigned grid, BidiagOut& o) {
   const int n = p->n;
   const z64* What = (const z64*)p->What;
   const auto& vs = bd_variants(n);
@@ -379,7 +390,7 @@ fl_status launch_bidiag(fl_plan* p, int chunk0, unsigned grid, BidiagOut& o) {
 #define BD(TR, TC, WPE)                                                                     \
   if (v.tr == TR && v.tc == TC && v.wpe == WPE) {                                           \
     hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, double, WPE>), dim3(grid), dim3(TR * TC), 0, \
-                       p->st, p->gsys, p->TP, What, p->N, p->list, p->count, chunk0, p->C, o); \
+                       p->st, p->gsys, p->TP, What, p->N, list, count, chunk0, C, o); \
     LAUNCHCHK();                                                                            \
     return FL_OK;                                                                           \
   }
@@ -452,17 +463,17 @@ fl_status solve_prepare(fl_plan* p) {
 // workspace (reflectors, bidiagonal, q = U^H w, ||A||_F^2).
 template <typename T>
 fl_status run_bidiag(fl_plan* p, long c0) {
-  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam};
+  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, nullptr, nullptr};
   const long gdef = p->n <= 64 ? 8192 : 2048;
   const unsigned gb = (unsigned)std::min<long>(p->C, p->bd_grid > 0 ? p->bd_grid : gdef);
   RUN(mark(p, FL_STAGE_BIDIAG));
-  return launch_bidiag<T>(p, (int)c0, gb, o);
+  return launch_bidiag<T>(p, p->list, p->count, (int)c0, p->C, gb, o);
 }
 
 // Discrepancy root, Tikhonov solve and back-transform of the same chunk;
 // fixed: take alpha and the branch per frequency from the global search.
 template <typename T>
-fl_status run_dp(fl_plan* p, long c0, bool fixed = false) {
+fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
   DpArgs a{};
   a.dg = p->dg;
   a.sp = p->sp;
@@ -487,7 +498,16 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false) {
   a.chunk0 = (int)c0;
   a.alpha_fixed = fixed ? p->galpha : nullptr;
   a.branch_fixed = fixed ? p->gbranch : nullptr;
-  const unsigned gd = (unsigned)std::min<long>(p->C, p->dp_grid > 0 ? p->dp_grid : 16384);
+  if (shared) {
+    // every active system in one launch, factorizations by orbit slot
+    a.C = (int)((long)p->F * p->N);
+    a.oslot = p->oslot;
+    a.orep = p->orep;
+    a.What = (const z64*)p->What;
+    a.refl_l = p->refl_l;
+    a.gam_l = p->gam_l;
+  }
+  const unsigned gd = (unsigned)std::min<long>(a.C, p->dp_grid > 0 ? p->dp_grid : 16384);
   RUN(mark(p, FL_STAGE_DP));
   if (p->n <= 64)
     hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, p->st, a);
@@ -557,11 +577,45 @@ fl_status solve_global(fl_plan* p) {
   return FL_OK;
 }
 
+// One factorization per active orbit: flag the orbits with an active
+// member, compact them, factorize each representative's A keeping its left
+// reflectors, then solve every active system against its orbit's
+// factorization (q = U^H w from the left reflectors).
 template <typename T>
-fl_status solve_systems(fl_plan* p) {
+fl_status solve_orbits(fl_plan* p) {
+  const long FN = (long)p->F * p->N;
+  const long FO = (long)p->F * p->n_orb;
+  hipStream_t st = p->st;
+  hipLaunchKernelGGL(k_orbit_flag, dim3(nblk(FN, 256)), dim3(256), 0, st, p->flag, p->orep, p->omem,
+                     p->N, p->F, p->oflag);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->cnt);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->ocount);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->cnt,
+                     p->olist);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_orbit_slot, dim3(nblk(FO, 256)), dim3(256), 0, st, p->olist, p->ocount,
+                     p->oslot);
+  LAUNCHCHK();
+  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, p->refl_l, p->gam_l};
+  const long gdef = p->n <= 64 ? 8192 : 2048;
+  const unsigned gb = (unsigned)std::min<long>(FO, p->bd_grid > 0 ? p->bd_grid : gdef);
+  RUN(mark(p, FL_STAGE_BIDIAG));
+  RUN(launch_bidiag<T>(p, p->olist, p->ocount, 0, (int)FO, gb, o));
+  return run_dp<T>(p, 0, false, true);
+}
+
+// shared: allow one factorization per orbit (the derivative calls need the
+// per-system factorizations and pass false)
+template <typename T>
+fl_status solve_systems(fl_plan* p, bool shared = true) {
   const long FN = (long)p->F * p->N;
   RUN(solve_prepare<T>(p));
+  p->last_shared = p->opts.alpha_rule == 0 && shared && p->orbits;
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
+  if (p->last_shared) return solve_orbits<T>(p);
   for (long c0 = 0; c0 < FN; c0 += p->C) RUN(solve_chunk<T>(p, c0));
   return FL_OK;
 }
@@ -694,7 +748,8 @@ fl_status stage_c(fl_plan* p, const void* Vin, z64* vout, z64* uout, const z64* 
 
 // The inversion launch sequence; T is the FFT / storage precision.
 template <typename T>
-fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out) {
+fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out,
+                      bool shared = true) {
   hipStream_t st = p->st;
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
@@ -734,7 +789,7 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
     RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
   }
   // (b) regularized solves of the active systems -> v^ plane-major
-  RUN(solve_systems<T>(p));
+  RUN(solve_systems<T>(p, shared));
   // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
   RUN(stage_c<T>(p, p->Vh, p->vX, p->u, u0d));
   // (d) xi, in FP64
@@ -824,7 +879,7 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp, false));
   const Tw<T> tw = twiddles_of<T>(p);
   // (d) reversed
   hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, p->xi_tmp, p->u, p->vX,
@@ -889,7 +944,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp, false));
   // T'_f = 2 tau^2 delta^2 Re <W_f, W'_f>
   {
     dim3 g(256, F);
@@ -1191,6 +1246,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
   if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
   if (o.alpha_rule != 0 && o.alpha_rule != 1) return fail(FL_EINVAL, "alpha_rule must be 0 or 1");
+  if (o.factor_per_system != 0 && o.factor_per_system != 1)
+    return fail(FL_EINVAL, "factor_per_system must be 0 or 1");
 
   fl_plan* p = new fl_plan();
   p->nx = nx;
@@ -1294,6 +1351,54 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     PALLOC(p->galpha, F);
     PALLOC(p->gbranch, F);
     PALLOC(p->gpart, (long)F * p->gB * 64);
+  }
+  {
+    // symmetry orbits of the wavenumber lattice: mx -> -mx, my -> -my, and
+    // mx <-> my on a square torus; the sampled kernel is radial, so Ghat and
+    // every A_m are invariant under them
+    std::vector<int> orep(N), omem(N * 8, -1);
+    int n_orb = 0;
+    for (int my = 0; my < py; ++my)
+      for (int mx = 0; mx < px; ++mx) {
+        const int m = my * px + mx;
+        int img[8], ni = 0;
+        auto add = [&](int x, int y) {
+          const int v = y * px + x;
+          for (int j = 0; j < ni; ++j)
+            if (img[j] == v) return;
+          img[ni++] = v;
+        };
+        const int xs[2] = {mx, (px - mx) % px}, ys[2] = {my, (py - my) % py};
+        for (int x : xs)
+          for (int y : ys) {
+            add(x, y);
+            if (px == py) add(y, x);
+          }
+        int r = m;
+        for (int j = 0; j < ni; ++j) r = std::min(r, img[j]);
+        orep[m] = r;
+        if (r == m) {
+          ++n_orb;
+          for (int j = 0; j < ni; ++j) omem[(long)m * 8 + j] = img[j];
+        }
+      }
+    p->n_orb = n_orb;
+    const long FO = (long)F * n_orb;
+    p->orbits = o.factor_per_system == 0 && o.alpha_rule == 0 && FO <= C;
+    if (p->orbits) {
+      PALLOC(p->orep, N);
+      PALLOC(p->omem, N * 8);
+      PALLOC(p->oflag, FN);
+      PALLOC(p->olist, FO);
+      PALLOC(p->ocount, 1);
+      PALLOC(p->oslot, FN);
+      PALLOC(p->refl_l, FO * nz * nz);
+      PALLOC(p->gam_l, FO * nz);
+      hipError_t e = hipMemcpy(p->orep, orep.data(), N * sizeof(int), hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(p->omem, omem.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return bail(fail(FL_EDEVICE, "orbit tables: %s", hipGetErrorString(e)));
+    }
   }
 #undef PALLOC
   fl_status s = build_tables(p);
@@ -1477,15 +1582,20 @@ fl_status fl_plan_info(const fl_plan* p, fl_plan_info_t* info) {
   info->precision = p->opts.precision;
   info->device_bytes = p->bytes;
   info->last_active = p->last_active;
+  info->last_factorized = p->last_factorized;
   return FL_OK;
 }
 
 fl_status fl_plan_refresh_info(fl_plan* p) {
   if (!p) return fail(FL_EINVAL, "NULL plan");
   int c = 0;
+  int o = 0;
   HIPCHK(hipMemcpyAsync(&c, p->count, sizeof(int), hipMemcpyDeviceToHost, p->st));
+  if (p->last_shared)
+    HIPCHK(hipMemcpyAsync(&o, p->ocount, sizeof(int), hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipStreamSynchronize(p->st));
   p->last_active = c;
+  p->last_factorized = p->last_shared ? o : c;
   return FL_OK;
 }
 

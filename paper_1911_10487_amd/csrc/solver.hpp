@@ -60,6 +60,37 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   flag[fm] = (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
 }
 
+// Wavenumbers related by the torus's mirror (and, on a square torus, swap)
+// symmetries share A_m: thread per (f, m); a representative m (orep[m] = m)
+// is flagged when any member of its orbit (omem[m][0..7], -1 padded) needs
+// a solve, every other m is not.
+__global__ __launch_bounds__(256) void k_orbit_flag(const int* __restrict__ flag,
+                                                    const int* __restrict__ orep,
+                                                    const int* __restrict__ omem, long N, int F,
+                                                    int* __restrict__ oflag) {
+  const long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (fm >= (long)F * N) return;
+  const int f = (int)(fm / N);
+  const long m = fm - (long)f * N;
+  int any = 0;
+  if (orep[m] == m) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int mj = omem[m * 8 + j];
+      if (mj >= 0) any |= flag[(long)f * N + mj];
+    }
+  }
+  oflag[fm] = any;
+}
+
+// oslot[olist[o]] = o for the compacted orbits
+__global__ __launch_bounds__(256) void k_orbit_slot(const int* __restrict__ olist,
+                                                    const int* __restrict__ ocount,
+                                                    int* __restrict__ oslot) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o < *ocount) oslot[olist[o]] = o;
+}
+
 __device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
   // 1024-thread block: ballot-based exclusive scan of 0/1 values
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -146,6 +177,8 @@ struct BidiagOut {
   double* wn2;  // [C] ||w||^2
   z64* refl;    // [C][n][n] right reflector k in row k, entries k+1..n-1
   double* gam;  // [C][n]
+  z64* refl_l;  // [C][n][n] left reflector k in row k, entries k..n-1; NULL: not kept
+  double* gam_l;
 };
 
 // Exchange areas of one bidiagonalization workgroup (index = step parity).
@@ -159,6 +192,7 @@ struct BdShared {
   z64 dg[n], sp[n];
   z64 qv[n];          // q = U^H w (row i kept by the column-class-0 thread of row class i % TR)
   double gm[n];
+  double gl[n];       // left gamma of every step
   double red[2][NW];
 };
 
@@ -208,7 +242,9 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
         if (i >= k) S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
       }
       if (r == kr) {
-        S.lg[par] = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
+        const double gl = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
+        S.lg[par] = gl;
+        S.gl[k] = gl;
         S.dg[k] = beta;
       }
     }
@@ -320,9 +356,11 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
 #pragma unroll
         for (int b = SB; b < NB; ++b) A[a][b] = cfmsc(A[a][b], z, vr[b]);
       } else if (i == k) {
-        // row k is finished: keep the reflector in its place (LAPACK style)
+        // row k is finished: keep the right reflector in its place (LAPACK
+        // style); entries j <= k keep the left reflectors of columns j
 #pragma unroll
-        for (int b = SB; b < NB; ++b) A[a][b] = vr[b];
+        for (int b = SB; b < NB; ++b)
+          if (c + TC * b > k) A[a][b] = vr[b];
       }
     }
   } else {
@@ -443,6 +481,19 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
 #pragma unroll
       for (int a = 0; a < NA; ++a) o.q[(long)sl * n + r + TR * a] = S.qv[r + TR * a];
     }
+    if (o.refl_l) {
+      // left reflector j: column j from the diagonal down (the pivot minus
+      // beta on the diagonal), as it was when step j formed it
+      z64* rl = o.refl_l + (long)sl * n * n;
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int i = r + TR * a, j = c + TC * b;
+          if (i >= j && j + 1 < n) rl[(long)j * n + i] = (i == j) ? A[a][b] - S.dg[j] : A[a][b];
+        }
+      for (int t = tid; t < n; t += NT) o.gam_l[(long)sl * n + t] = (t + 1 < n) ? S.gl[t] : 0.0;
+    }
     __syncthreads();
   }
 }
@@ -471,6 +522,14 @@ struct DpArgs {
   z64* bd_dr;
   const double* alpha_fixed;       // per frequency, or NULL: alpha given (one per
   const signed char* branch_fixed; // frequency) instead of the per-system search
+  // shared factorizations (NULL: one per system): system (f, m) uses slot
+  // oslot[f N + orep[m]] of dg, sp, fro, refl, gam, and q = U^H w from the
+  // slot's left reflectors and w in What
+  const int* oslot;
+  const int* orep;
+  const z64* What;
+  const z64* refl_l;
+  const double* gam_l;
 };
 
 // phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
@@ -636,6 +695,51 @@ __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, doub
   }
 }
 
+// q = U^H w = H_{n-2} ... H_0 w for the left reflectors H_k = I - g_k u_k u_k^H
+// of a shared factorization (lane i holds w_i and w_{i+64}); rows are loaded
+// eight at a time so that their global-memory latency overlaps.
+template <int NMAX>
+__device__ __forceinline__ void dp_left_apply(const z64* __restrict__ w, long N, int n,
+                                              const z64* __restrict__ L,
+                                              const double* __restrict__ GL, int lane, z64* sq) {
+  z64 q0 = lane < n ? w[(long)lane * N] : mk(0.0, 0.0);
+  z64 q1 = mk(0.0, 0.0);
+  if constexpr (NMAX > 64)
+    if (lane + 64 < n) q1 = w[(long)(lane + 64) * N];
+  constexpr int GR = 8;
+  for (int k0 = 0; k0 + 1 < n; k0 += GR) {
+    z64 v0[GR], v1[GR];
+    double gg[GR];
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+      const int k = k0 + g;
+      gg[g] = 0.0;
+      v0[g] = mk(0.0, 0.0);
+      v1[g] = mk(0.0, 0.0);
+      if (k + 1 < n) {
+        gg[g] = GL[k];
+        if (lane >= k && lane < n) v0[g] = L[(long)k * n + lane];
+        if constexpr (NMAX > 64)
+          if (lane + 64 >= k && lane + 64 < n) v1[g] = L[(long)k * n + lane + 64];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GR; ++g) {
+      if (k0 + g + 1 >= n) break;
+      z64 s = cmulc(v0[g], q0);
+      if constexpr (NMAX > 64) s = cfmac(s, v1[g], q1);
+      s.x = lanes_sum<64>(s.x);
+      s.y = lanes_sum<64>(s.y);
+      s = gg[g] * s;
+      q0 = q0 - v0[g] * s;
+      if constexpr (NMAX > 64) q1 = q1 - v1[g] * s;
+    }
+  }
+  if (lane < n) sq[lane] = q0;
+  if constexpr (NMAX > 64)
+    if (lane + 64 < n) sq[lane + 64] = q1;
+}
+
 // One single-wave workgroup per active system: phase-scale the bidiagonal to
 // a real one, choose alpha by the discrepancy principle with a 64-way
 // multisection on log(alpha), solve at that alpha (Elden), apply the right
@@ -653,22 +757,30 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     const int fm = a.list[gs];
     const int f = (int)(fm / a.N);
     const long m = fm - (long)f * a.N;
+    // factorization slot: the system's own, or its orbit's
+    const long fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
     // stage the complex bidiagonal and q
     for (int i = lane; i < n; i += 64) {
-      sy[i] = a.dg[(long)sl * n + i];
-      srr[i] = a.sp[(long)sl * n + i];
-      sq[i] = a.q[(long)sl * n + i];
+      sy[i] = a.dg[fs * n + i];
+      srr[i] = a.sp[fs * n + i];
+      if (!a.oslot) sq[i] = a.q[(long)sl * n + i];
     }
+    if (a.oslot)
+      dp_left_apply<NMAX>(a.What + (long)f * n * a.N + m, a.N, n, a.refl_l + fs * n * n,
+                          a.gam_l + fs * n, lane, sq);
     __syncthreads();
     dp_phase_scale<NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
     __syncthreads();
-    for (int i = lane; i < n; i += 64) {
-      a.bd_d[(long)sl * n + i] = sd[i];
-      a.bd_e[(long)sl * n + i] = se[i];
-      a.bd_dr[(long)sl * n + i] = sdr[i];
+    if (!a.oslot) {
+      // kept for the derivative kernels (per-system factorizations only)
+      for (int i = lane; i < n; i += 64) {
+        a.bd_d[(long)sl * n + i] = sd[i];
+        a.bd_e[(long)sl * n + i] = se[i];
+        a.bd_dr[(long)sl * n + i] = sdr[i];
+      }
     }
     const double T = a.thr2[f];
-    const double fro = a.fro[sl];
+    const double fro = a.fro[fs];
     const double amin = a.eta * fro;
     double al = amin;
     signed char br = 1;
@@ -769,8 +881,8 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
     // v^ = V (D_R y'), V = P_0 P_1 ... P_{n-3}
     z64 y0 = lane < n ? sdr[lane] * sy[lane] : mk(0.0, 0.0);
     z64 y1 = NMAX > 64 && lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
-    const z64* R = a.refl + (long)sl * n * n;
-    const double* G = a.gam + (long)sl * n;
+    const z64* R = a.refl + fs * n * n;
+    const double* G = a.gam + fs * n;
     // reflector k has entries k+1..n-1; rows are loaded eight at a time so
     // that their global-memory latency overlaps
     constexpr int GR = 8;

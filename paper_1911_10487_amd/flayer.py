@@ -38,7 +38,7 @@ class FlOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("max_chunk", ctypes.c_int),
         ("kernel_mode", ctypes.c_int), ("damping", ctypes.c_double),
-        ("alpha_rule", ctypes.c_int),
+        ("alpha_rule", ctypes.c_int), ("factor_per_system", ctypes.c_int),
     ]
 
 
@@ -52,7 +52,7 @@ class FlPlanInfo(ctypes.Structure):
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("nd", ctypes.c_int),
         ("px", ctypes.c_int), ("py", ctypes.c_int), ("n_omega", ctypes.c_int),
         ("precision", ctypes.c_int), ("device_bytes", ctypes.c_size_t),
-        ("last_active", ctypes.c_int),
+        ("last_active", ctypes.c_int), ("last_factorized", ctypes.c_int),
     ]
 
 
@@ -148,13 +148,13 @@ class Plan:
 
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
                  tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0,
-                 kernel_mode=0, damping=0.0, alpha_rule=0):
+                 kernel_mode=0, damping=0.0, alpha_rule=0, factor_per_system=0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
         o.max_chunk = max_chunk
         o.kernel_mode, o.damping = kernel_mode, damping
-        o.alpha_rule = alpha_rule
+        o.alpha_rule, o.factor_per_system = alpha_rule, factor_per_system
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)
@@ -183,6 +183,12 @@ class Plan:
     def active_systems(self) -> int:
         _check(lib().fl_plan_refresh_info(self._h))
         return self.info().last_active
+
+    def factorized_systems(self) -> int:
+        """Matrices factorized by the last invert (active symmetry orbits
+        when factorizations are shared)."""
+        _check(lib().fl_plan_refresh_info(self._h))
+        return self.info().last_factorized
 
     def invert(self, W, u0, delta, xi_out=None):
         """W (n_omega, nd, py, px) and u0 (n_omega, nz, ny, nx): complex

@@ -146,7 +146,8 @@ def test_mixed_precision_derivatives(case):
 def test_chunked_factorization_matches_resident(case, precision):
     """A plan whose solver workspace holds a few dozen systems (so that the
     derivative passes re-factorize chunk by chunk) gives bitwise the same
-    xi, VJP and JVP as a plan holding every system at once."""
+    xi, VJP and JVP as a plan holding every system at once (one
+    factorization per system in both, as the derivative calls use)."""
     import torch
     p, W, u0, d = case
     g = synth.random_field((p.nz, p.ny, p.nx), (45,))
@@ -156,7 +157,7 @@ def test_chunked_factorization_matches_resident(case, precision):
     outs = []
     for mc in (0, 37):
         say("chunk", mc, "precision", precision)
-        plan = _plan(p, precision=precision, max_chunk=mc)
+        plan = _plan(p, precision=precision, max_chunk=mc, factor_per_system=1)
         xi = plan.invert(Wt, ut, d).cpu().numpy()
         n_act = plan.active_systems()
         gW, gu = plan.vjp(Wt, ut, d, gt, want_u0=True)

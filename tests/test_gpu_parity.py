@@ -397,3 +397,21 @@ def test_one_alpha_per_frequency_has_no_derivatives(small):
         plan.vjp(Wt, ut, 0.01, torch.ones((p.nz, p.ny, p.nx), dtype=torch.complex128,
                                            device="cuda"))
     plan.close()
+
+
+@pytest.mark.parametrize("case,delta", [("small", 0.01), ("small", 0.0), ("ragged", 0.02)])
+def test_orbit_and_per_system_factorizations_match_oracle(case, delta):
+    """factor_per_system 0 (one factorization per symmetry orbit of the
+    wavenumbers, the default) and 1 (one per system) both meet the oracle;
+    the square 64^2 torus has orbits of up to 8 members, the 40x30 one of up
+    to 4."""
+    p, W, u0 = _global_case(case)
+    Wd = synth.add_noise(p, W, delta)
+    ref_xi, ref = invert.invert(p, Wd, u0, delta, stages=True)
+    out = []
+    for fps in (0, 1):
+        xi, st = gpu_run(p, Wd, u0, delta, factor_per_system=fps)
+        compare(p, ref_xi, ref, xi, st, tol=tol_for(delta))
+        out.append(xi)
+    say("orbit vs per-system", case, delta, rel(out[0], out[1]))
+    assert rel(out[0], out[1]) <= tol_for(delta)

@@ -201,3 +201,22 @@ def test_closed_form_table_matches_sampled_table_and_is_rank_one():
     s = np.linalg.svd(A, compute_uv=False)
     assert np.all(s[:, 1] <= 1e-12 * s[:, 0])
     assert np.all(s[:, 0] > 0)
+
+
+@pytest.mark.parametrize("px,py", [(64, 64), (40, 30), (45, 45)])
+def test_table_is_invariant_under_the_torus_symmetries(px, py):
+    # G is radial, and the min-image samples of the torus are symmetric under
+    # x -> -x, y -> -y (and x <-> y when px = py): so is G^, and every A_m
+    # depends on the orbit of m only (the GPU path factorizes one A per orbit)
+    p = synth.make_problem("sym", px // 2, py // 2, 4, [2 * np.pi], 3, (0, 0), (0.0,),
+                           px=px, py=py)
+    tab, _ = model.system_table(p, 0)
+    scale = np.abs(tab).max()
+    ix = (-np.arange(px)) % px
+    iy = (-np.arange(py)) % py
+    assert np.abs(tab[:, :, ix] - tab).max() <= 1e-13 * scale
+    assert np.abs(tab[:, iy, :] - tab).max() <= 1e-13 * scale
+    if px == py:
+        assert np.abs(tab.transpose(0, 2, 1) - tab).max() <= 1e-13 * scale
+    # and the symmetry is not vacuous: G^ does vary across the wavenumbers
+    assert np.abs(tab - tab[:, :1, :1]).max() > 0.1 * scale
