@@ -577,6 +577,18 @@ fl_status solve_global(fl_plan* p) {
   return FL_OK;
 }
 
+// Bidiagonalization of the compacted orbit representatives, keeping their
+// left reflectors.
+template <typename T>
+fl_status run_bidiag_orbits(fl_plan* p) {
+  const long FO = (long)p->F * p->n_orb;
+  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, p->refl_l, p->gam_l};
+  const long gdef = p->n <= 64 ? 8192 : 2048;
+  const unsigned gb = (unsigned)std::min<long>(FO, p->bd_grid > 0 ? p->bd_grid : gdef);
+  RUN(mark(p, FL_STAGE_BIDIAG));
+  return launch_bidiag<T>(p, p->olist, p->ocount, 0, (int)FO, gb, o);
+}
+
 // One factorization per active orbit: flag the orbits with an active
 // member, compact them, factorize each representative's A keeping its left
 // reflectors, then solve every active system against its orbit's
@@ -599,11 +611,7 @@ fl_status solve_orbits(fl_plan* p) {
   hipLaunchKernelGGL(k_orbit_slot, dim3(nblk(FO, 256)), dim3(256), 0, st, p->olist, p->ocount,
                      p->oslot);
   LAUNCHCHK();
-  BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, p->refl_l, p->gam_l};
-  const long gdef = p->n <= 64 ? 8192 : 2048;
-  const unsigned gb = (unsigned)std::min<long>(FO, p->bd_grid > 0 ? p->bd_grid : gdef);
-  RUN(mark(p, FL_STAGE_BIDIAG));
-  RUN(launch_bidiag<T>(p, p->olist, p->ocount, 0, (int)FO, gb, o));
+  RUN(run_bidiag_orbits<T>(p));
   return run_dp<T>(p, 0, false, true);
 }
 
@@ -1014,7 +1022,8 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
       p->bd_var = v;
       p->bd_grid = g;
       float ms = 0.f;
-      st = time_it([&] { return run_bidiag<T>(p, 0); }, &ms);
+      st = time_it([&] { return p->last_shared ? run_bidiag_orbits<T>(p) : run_bidiag<T>(p, 0); },
+                   &ms);
       if (st != FL_OK) break;
       if (ms < bt) {
         bt = ms;
@@ -1030,7 +1039,7 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
     if (st != FL_OK) break;
     p->dp_grid = g;
     float ms = 0.f;
-    st = time_it([&] { return run_dp<T>(p, 0); }, &ms);
+    st = time_it([&] { return run_dp<T>(p, 0, false, p->last_shared); }, &ms);
     if (st == FL_OK && ms < dt) {
       dt = ms;
       best->dp_grid = g;

@@ -533,7 +533,7 @@ struct DpArgs {
 };
 
 // phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
-// bidiagonal B (d, e), evaluated in one forward pass without storage:
+// bidiagonal B (d, e; e[n-1] = 0), evaluated in one forward pass without storage:
 // phi = -alpha^2 g'(alpha) with g = q^H (B B^T + alpha I)^{-1} q, g from the
 // LDL^T recurrence of the tridiagonal B B^T + alpha I and g' by forward-mode
 // differentiation of the same recurrence.
@@ -547,7 +547,7 @@ __device__ __forceinline__ double phi_fwd(const double* __restrict__ d, const do
   for (int i = 1; i < n; ++i) {
     const double b = e[i - 1] * d[i];
     const double l = b * rD;
-    const double ei = (i < n - 1) ? e[i] : 0.0;
+    const double ei = e[i];
     const double Dn = d[i] * d[i] + ei * ei + alpha - l * b;
     const double Dpn = 1.0 + l * l * Dp;
     const double c1 = l * Dp * rD;
@@ -832,8 +832,10 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
         // the square of the bracket). A window that misses the root still
         // leaves a valid, smaller bracket; the round after a miss spreads
         // its points over the whole bracket again.
+        // The search stops once the bracket is below 3e-8 in log(alpha): the
+        // secant point is then within about curvature * 1e-16 of the root.
         bool miss = false;
-        for (int round = 0; round < 24 && hi - lo > 1e-13 * fmax(1.0, fabs(hi)); ++round) {
+        for (int round = 0; round < 24 && hi - lo > 3e-8; ++round) {
           const double wdt = hi - lo;
           double a0 = lo, a1 = hi;
           if (!miss && flo == flo && fhi == fhi && fhi > flo) {
