@@ -105,6 +105,18 @@ typedef struct {
                           left reflectors to every member's data; 1 = one
                           factorization per system (always so for alpha_rule 1
                           and the derivative calls) */
+  int forward_method;  /* fl_forward with maxit > 0: 0 = BiCGSTAB (default);
+                          1 = Algorithm 1's fixed point u <- u0 + omega^2 K(xi u)
+                          from u0, stopped per frequency when the change is
+                          within tol ||u0|| (converges for small omega xi only;
+                          FL_ENOCONV otherwise) */
+  int prefactor;       /* 1: A_m does not depend on the data, so fl_plan_create
+                          factorizes every orbit representative of every
+                          frequency once (F x about N/8 matrices kept in the
+                          plan) and fl_invert only classifies and solves;
+                          needs factor_per_system 0 and alpha_rule 0
+                          (FL_EUNSUPPORTED otherwise). 0 (default): each
+                          fl_invert factorizes the orbits it needs */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);
@@ -288,11 +300,15 @@ void fl_batch_destroy(fl_batch *batch);
  *   bidiag_grid     workgroups of the persistent bidiagonalization launch
  *                   (0 = 8192 for n <= 64, else 2048)
  *   dp_grid         one-wave workgroups of the discrepancy launch (0 = 16384)
+ *   dp_systems_per_wave  systems one discrepancy wave takes: the alpha search
+ *                   runs over the whole wave per system, the reflector passes
+ *                   and the Elden solve for all of them at once in groups of
+ *                   64 / w lanes; 1, 2, 4 (4 for nz <= 64 only), 0 = 2
  * Schedules sum in different orders, so their results agree to rounding, not
- * bitwise; a plan starts with schedule {0, 0, 0}.
+ * bitwise; a plan starts with schedule {0, 0, 0, 0}.
  */
 typedef struct {
-  int bidiag_variant, bidiag_grid, dp_grid;
+  int bidiag_variant, bidiag_grid, dp_grid, dp_systems_per_wave;
 } fl_tuning;
 fl_status fl_tuning_get(const fl_plan *plan, fl_tuning *t);
 fl_status fl_tuning_set(fl_plan *plan, const fl_tuning *t); /* FL_EINVAL if out of range */

@@ -87,7 +87,7 @@ struct fl_plan {
   // solver chunk
   int C = 0;
   // launch schedule (fl_tuning): bidiagonalization variant and grid sizes
-  int bd_var = 0, bd_grid = 0, dp_grid = 0;
+  int bd_var = 0, bd_grid = 0, dp_grid = 0, dp_spw = 0;
   z64 *dg = nullptr, *sp = nullptr, *q = nullptr, *refl = nullptr;
   double *fro = nullptr, *wnc = nullptr, *gam = nullptr;
   double *bd_d = nullptr, *bd_e = nullptr;
@@ -127,6 +127,7 @@ struct fl_plan {
   size_t bytes = 0;
   int last_active = -1, last_factorized = -1;
   bool last_shared = false;  // the last solve used orbit factorizations
+  bool prefactored = false;  // every orbit factorized at plan creation
   // stage tracing
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
@@ -470,6 +471,10 @@ fl_status run_bidiag(fl_plan* p, long c0) {
   return launch_bidiag<T>(p, p->list, p->count, (int)c0, p->C, gb, o);
 }
 
+// Systems per wave of the discrepancy kernel (fl_tuning.dp_systems_per_wave;
+// 0 = 2).
+int dp_spw_of(const fl_plan* p) { return p->dp_spw > 0 ? p->dp_spw : 2; }
+
 // Discrepancy root, Tikhonov solve and back-transform of the same chunk;
 // fixed: take alpha and the branch per frequency from the global search.
 template <typename T>
@@ -507,12 +512,23 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
     a.refl_l = p->refl_l;
     a.gam_l = p->gam_l;
   }
-  const unsigned gd = (unsigned)std::min<long>(a.C, p->dp_grid > 0 ? p->dp_grid : 16384);
+  const int spw = dp_spw_of(p);
+  const long ngr = ((long)a.C + spw - 1) / spw;
+  const unsigned gd = (unsigned)std::min<long>(ngr, p->dp_grid > 0 ? p->dp_grid : 16384);
   RUN(mark(p, FL_STAGE_DP));
-  if (p->n <= 64)
-    hipLaunchKernelGGL(k_dp_solve<64>, dim3(gd), dim3(64), 0, p->st, a);
-  else
-    hipLaunchKernelGGL(k_dp_solve<128>, dim3(gd), dim3(64), 0, p->st, a);
+  if (p->n <= 64) {
+    if (spw == 4)
+      hipLaunchKernelGGL((k_dp_solve<64, 4>), dim3(gd), dim3(64), 0, p->st, a);
+    else if (spw == 2)
+      hipLaunchKernelGGL((k_dp_solve<64, 2>), dim3(gd), dim3(64), 0, p->st, a);
+    else
+      hipLaunchKernelGGL((k_dp_solve<64, 1>), dim3(gd), dim3(64), 0, p->st, a);
+  } else {
+    if (spw == 2)
+      hipLaunchKernelGGL((k_dp_solve<128, 2>), dim3(gd), dim3(64), 0, p->st, a);
+    else
+      hipLaunchKernelGGL((k_dp_solve<128, 1>), dim3(gd), dim3(64), 0, p->st, a);
+  }
   LAUNCHCHK();
   return FL_OK;
 }
@@ -615,6 +631,32 @@ fl_status solve_orbits(fl_plan* p) {
   return run_dp<T>(p, 0, false, true);
 }
 
+// Plan-time factorization of every orbit representative of every frequency
+// (A_m does not depend on the data): slot f * n_orb + r in the orbit
+// workspace, so that fl_invert only classifies and solves.
+fl_status prefactor(fl_plan* p, const std::vector<int>& reps) {
+  const long N = p->N, F = p->F, FO = F * p->n_orb;
+  std::vector<int> list(FO), slot(F * N, 0);
+  for (long f = 0; f < F; ++f)
+    for (int r = 0; r < p->n_orb; ++r) {
+      list[f * p->n_orb + r] = (int)(f * N + reps[r]);
+      slot[f * N + reps[r]] = (int)(f * p->n_orb + r);
+    }
+  const int fo = (int)FO;
+  HIPCHK(hipMemcpy(p->olist, list.data(), FO * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->oslot, slot.data(), F * N * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->ocount, &fo, sizeof(int), hipMemcpyHostToDevice));
+  // the bidiagonalization also transforms the representative's own data
+  // column (unused here): give it zeros
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(F * p->nd * N, 256)), dim3(256), 0, p->st,
+                     (z64*)p->What, F * p->nd * N);
+  LAUNCHCHK();
+  RUN(run_bidiag_orbits<double>(p));
+  HIPCHK(hipStreamSynchronize(p->st));
+  p->prefactored = true;
+  return FL_OK;
+}
+
 // shared: allow one factorization per orbit (the derivative calls need the
 // per-system factorizations and pass false)
 template <typename T>
@@ -623,6 +665,7 @@ fl_status solve_systems(fl_plan* p, bool shared = true) {
   RUN(solve_prepare<T>(p));
   p->last_shared = p->opts.alpha_rule == 0 && shared && p->orbits;
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
+  if (p->last_shared && p->prefactored) return run_dp<T>(p, 0, false, true);
   if (p->last_shared) return solve_orbits<T>(p);
   for (long c0 = 0; c0 < FN; c0 += p->C) RUN(solve_chunk<T>(p, c0));
   return FL_OK;
@@ -1034,18 +1077,25 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
   p->bd_var = best->bidiag_variant;
   p->bd_grid = best->bidiag_grid;
   float dt = 1e30f;
-  const int dgrids[] = {4096, 8192, 16384};
-  for (int g : dgrids) {
-    if (st != FL_OK) break;
-    p->dp_grid = g;
-    float ms = 0.f;
-    st = time_it([&] { return run_dp<T>(p, 0, false, p->last_shared); }, &ms);
-    if (st == FL_OK && ms < dt) {
-      dt = ms;
-      best->dp_grid = g;
+  const int dgrids[] = {2048, 4096, 8192, 16384};
+  const int spws[] = {1, 2, 4};
+  for (int w : spws) {
+    if (w == 4 && p->n > 64) continue;
+    for (int g : dgrids) {
+      if (st != FL_OK) break;
+      p->dp_grid = g;
+      p->dp_spw = w;
+      float ms = 0.f;
+      st = time_it([&] { return run_dp<T>(p, 0, false, p->last_shared); }, &ms);
+      if (st == FL_OK && ms < dt) {
+        dt = ms;
+        best->dp_grid = g;
+        best->dp_systems_per_wave = w;
+      }
     }
   }
   p->dp_grid = best->dp_grid;
+  p->dp_spw = best->dp_systems_per_wave;
   p->prof = prof;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1108,6 +1158,53 @@ __global__ void k_bicg_init(BicgScalars S, const z64* __restrict__ bb, int F) {
 
 // BiCGSTAB from x0 = 0 on u - omega^2 K(xi u) = b; stops each frequency at
 // ||s|| or ||r|| <= tol ||b||. Leaves u in bv[0].
+// Algorithm 1's fixed point u_{n+1} = u0 + omega^2 K(xi u_n) from u_0 = u0
+// (Section 3), every frequency at once; a frequency stops once its change
+// ||u_{n+1} - u_n|| is within tol ||u0||. Converges when the spectral radius
+// of omega^2 K(xi .) is below one (small omega or contrast).
+fl_status ls_fixed_point(fl_plan* p, const double* xi, const z64* b, double tol, int maxit,
+                         int* iters) {
+  RUN(ensure_ls_buffers(p));
+  hipStream_t st = p->st;
+  const int F = p->F;
+  const long nvox = (long)p->nx * p->ny * p->nz, n = F * nvox;
+  z64 *X = p->bv[0], *T = p->bv[1], *Dl = p->bv[2];
+  z64* D = p->dots;
+  const dim3 g(nblk(n, 256)), blk(256);
+  HIPCHK(hipMemcpyAsync(X, b, (size_t)n * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  RUN(cdot(p, b, b, 0));
+  std::vector<z64> bn2(F), dn2(F);
+  std::vector<int> act(F);
+  HIPCHK(hipMemcpyAsync(bn2.data(), D, F * sizeof(z64), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool any = false;
+  for (int f = 0; f < F; ++f) {
+    act[f] = bn2[f].x > 0.0;
+    any = any || act[f];
+  }
+  const double tol2 = tol * tol;
+  int it = 0;
+  while (any && it < maxit) {
+    ++it;
+    HIPCHK(hipMemcpyAsync(p->b_active, act.data(), F * sizeof(int), hipMemcpyHostToDevice, st));
+    RUN(ls_apply(p, xi, X, T));
+    hipLaunchKernelGGL(k_fp_step, g, blk, 0, st, b, T, nvox, F, p->b_active, X, Dl);
+    LAUNCHCHK();
+    RUN(cdot(p, Dl, Dl, 1));
+    HIPCHK(hipMemcpyAsync(dn2.data(), D + F, F * sizeof(z64), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    any = false;
+    for (int f = 0; f < F; ++f) {
+      if (act[f] && dn2[f].x <= tol2 * bn2[f].x) act[f] = 0;
+      any = any || act[f];
+    }
+  }
+  *iters = it;
+  if (any)
+    return fail(FL_ENOCONV, "fixed point: change above %g after %d iterations", tol, maxit);
+  return FL_OK;
+}
+
 fl_status ls_solve(fl_plan* p, const double* xi, const z64* b, double tol, int maxit, int* iters) {
   RUN(ensure_ls_buffers(p));
   hipStream_t st = p->st;
@@ -1257,6 +1354,12 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (o.alpha_rule != 0 && o.alpha_rule != 1) return fail(FL_EINVAL, "alpha_rule must be 0 or 1");
   if (o.factor_per_system != 0 && o.factor_per_system != 1)
     return fail(FL_EINVAL, "factor_per_system must be 0 or 1");
+  if (o.forward_method != 0 && o.forward_method != 1)
+    return fail(FL_EINVAL, "forward_method must be 0 or 1");
+  if (o.prefactor != 0 && o.prefactor != 1) return fail(FL_EINVAL, "prefactor must be 0 or 1");
+  if (o.prefactor && (o.factor_per_system || o.alpha_rule))
+    return fail(FL_EUNSUPPORTED, "prefactor needs shared factorizations (factor_per_system 0, "
+                                 "alpha_rule 0)");
 
   fl_plan* p = new fl_plan();
   p->nx = nx;
@@ -1361,6 +1464,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     PALLOC(p->gbranch, F);
     PALLOC(p->gpart, (long)F * p->gB * 64);
   }
+  std::vector<int> reps;  // orbit representatives, increasing
   {
     // symmetry orbits of the wavenumber lattice: mx -> -mx, my -> -my, and
     // mx <-> my on a square torus; the sampled kernel is radial, so Ghat and
@@ -1388,12 +1492,17 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
         orep[m] = r;
         if (r == m) {
           ++n_orb;
+          reps.push_back(m);
           for (int j = 0; j < ni; ++j) omem[(long)m * 8 + j] = img[j];
         }
       }
     p->n_orb = n_orb;
     const long FO = (long)F * n_orb;
     p->orbits = o.factor_per_system == 0 && o.alpha_rule == 0 && FO <= C;
+    if (o.prefactor && !p->orbits)
+      return bail(fail(FL_EUNSUPPORTED,
+                       "prefactor needs shared factorizations (factor_per_system 0, alpha_rule 0) "
+                       "and a workspace of %ld systems (max_chunk)", FO));
     if (p->orbits) {
       PALLOC(p->orep, N);
       PALLOC(p->omem, N * 8);
@@ -1418,6 +1527,10 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(p->st);
     if (e != hipSuccess) return bail(fail(FL_EDEVICE, "table narrowing: %s", hipGetErrorString(e)));
+  }
+  if (o.prefactor) {
+    s = prefactor(p, reps);
+    if (s != FL_OK) return bail(s);
   }
   *out = p;
   return FL_OK;
@@ -1604,7 +1717,7 @@ fl_status fl_plan_refresh_info(fl_plan* p) {
     HIPCHK(hipMemcpyAsync(&o, p->ocount, sizeof(int), hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipStreamSynchronize(p->st));
   p->last_active = c;
-  p->last_factorized = p->last_shared ? o : c;
+  p->last_factorized = p->last_shared ? (p->prefactored ? 0 : o) : c;
   return FL_OK;
 }
 
@@ -1613,6 +1726,7 @@ fl_status fl_tuning_get(const fl_plan* p, fl_tuning* t) {
   t->bidiag_variant = p->bd_var;
   t->bidiag_grid = p->bd_grid;
   t->dp_grid = p->dp_grid;
+  t->dp_systems_per_wave = p->dp_spw;
   return FL_OK;
 }
 
@@ -1622,9 +1736,13 @@ fl_status fl_tuning_set(fl_plan* p, const fl_tuning* t) {
   if (t->bidiag_variant < 0 || t->bidiag_variant >= nv)
     return fail(FL_EINVAL, "bidiag_variant %d out of range [0, %d)", t->bidiag_variant, nv);
   if (t->bidiag_grid < 0 || t->dp_grid < 0) return fail(FL_EINVAL, "grid sizes must be >= 0");
+  const int w = t->dp_systems_per_wave;
+  if (!(w == 0 || w == 1 || w == 2 || (w == 4 && p->n <= 64)))
+    return fail(FL_EINVAL, "dp_systems_per_wave %d: 0, 1, 2 (and 4 for nz <= 64)", w);
   p->bd_var = t->bidiag_variant;
   p->bd_grid = t->bidiag_grid;
   p->dp_grid = t->dp_grid;
+  p->dp_spw = w;
   return FL_OK;
 }
 
@@ -1647,7 +1765,7 @@ fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, 
   if (!W || !u0 || !xi_scratch) return fail(FL_EINVAL, "NULL array argument");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   if (reps < 1) reps = 1;
-  fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid};
+  fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid, p->dp_spw};
   RUN(fl_invert(p, W, u0, delta, xi_scratch));
   fl_tuning best = keep;
   fl_status s = p->prec ? tune_impl<float>(p, reps, &best) : tune_impl<double>(p, reps, &best);
@@ -1655,8 +1773,15 @@ fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, 
     p->bd_var = keep.bidiag_variant;
     p->bd_grid = keep.bidiag_grid;
     p->dp_grid = keep.dp_grid;
-    return s;
+    p->dp_spw = keep.dp_systems_per_wave;
   }
+  // the timing runs overwrote a plan-time factorization: redo it with the
+  // schedule kept
+  if (p->prefactored) {
+    RUN(run_bidiag_orbits<double>(p));
+    HIPCHK(hipStreamSynchronize(p->st));
+  }
+  if (s != FL_OK) return s;
   if (chosen) *chosen = best;
   return FL_OK;
 }
@@ -1710,7 +1835,10 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   if (maxit > 0) {
     // total field: u - omega^2 K(xi u) = u0 in X (system (2), first line)
     int it = 0;
-    RUN(ls_solve(p, xi, u, tol, maxit, &it));
+    if (p->opts.forward_method == 1)
+      RUN(ls_fixed_point(p, xi, u, tol, maxit, &it));
+    else
+      RUN(ls_solve(p, xi, u, tol, maxit, &it));
     u = p->bv[0];
   }
   // W = omega^2 G * (xi u) on the data planes (eq. 3; eq. 7, second line)

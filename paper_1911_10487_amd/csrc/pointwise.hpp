@@ -365,6 +365,24 @@ __global__ __launch_bounds__(256) void k_bicg_xr(BicgScalars S, const z64* __res
   r[i] = cfms(s[i], w, t[i]);
 }
 
+// One step of the fixed point u <- u0 + omega^2 K(xi u) (Algorithm 1) for the
+// frequencies still iterating: t holds u - omega^2 K(xi u), so the new u is
+// u + (u0 - t); d receives the change u0 - t (zero for frozen frequencies).
+__global__ __launch_bounds__(256) void k_fp_step(const z64* __restrict__ b, const z64* __restrict__ t,
+                                                 long nvox, int F, const int* __restrict__ active,
+                                                 z64* __restrict__ x, z64* __restrict__ d) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox * F) return;
+  const int f = (int)(i / nvox);
+  if (!active[f]) {
+    d[i] = mk(0.0, 0.0);
+    return;
+  }
+  const z64 di = b[i] - t[i];
+  x[i] = x[i] + di;
+  d[i] = di;
+}
+
 // p = r + beta (p - omega v)
 __global__ __launch_bounds__(256) void k_bicg_p(BicgScalars S, const z64* __restrict__ r,
                                                 const z64* __restrict__ v, long nvox, int F,

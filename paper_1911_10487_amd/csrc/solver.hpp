@@ -564,9 +564,9 @@ __device__ __forceinline__ double phi_fwd(const double* __restrict__ d, const do
 }
 
 // Elden: Givens QR of [B; sqrt(alpha) I], back substitution; writes y.
-__device__ void elden_solve(const double* __restrict__ d, const double* __restrict__ e,
-                            const z64* __restrict__ q, int n, double alpha, double* rho,
-                            double* off, z64* rr, z64* y) {
+// rho and off may alias d and e (entry i is read before it is written).
+__device__ void elden_solve(const double* d, const double* e, const z64* q, int n, double alpha,
+                            double* rho, double* off, z64* rr, z64* y) {
   const double mu = sqrt(alpha);
   double mt = mu;
   z64 g = mk(0.0, 0.0);
@@ -695,240 +695,304 @@ __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, doub
   }
 }
 
-// q = U^H w = H_{n-2} ... H_0 w for the left reflectors H_k = I - g_k u_k u_k^H
-// of a shared factorization (lane i holds w_i and w_{i+64}); rows are loaded
-// eight at a time so that their global-memory latency overlaps.
-template <int NMAX>
-__device__ __forceinline__ void dp_left_apply(const z64* __restrict__ w, long N, int n,
-                                              const z64* __restrict__ L,
-                                              const double* __restrict__ GL, int lane, z64* sq) {
-  z64 q0 = lane < n ? w[(long)lane * N] : mk(0.0, 0.0);
-  z64 q1 = mk(0.0, 0.0);
-  if constexpr (NMAX > 64)
-    if (lane + 64 < n) q1 = w[(long)(lane + 64) * N];
-  constexpr int GR = 8;
-  for (int k0 = 0; k0 + 1 < n; k0 += GR) {
-    z64 v0[GR], v1[GR];
-    double gg[GR];
-#pragma unroll
-    for (int g = 0; g < GR; ++g) {
-      const int k = k0 + g;
-      gg[g] = 0.0;
-      v0[g] = mk(0.0, 0.0);
-      v1[g] = mk(0.0, 0.0);
-      if (k + 1 < n) {
-        gg[g] = GL[k];
-        if (lane >= k && lane < n) v0[g] = L[(long)k * n + lane];
-        if constexpr (NMAX > 64)
-          if (lane + 64 >= k && lane + 64 < n) v1[g] = L[(long)k * n + lane + 64];
+// Discrepancy choice of alpha for one system (the whole wave): round 0
+// tests the floor alpha_min = eta ||A||_F^2 (lane 0) and spreads lanes 1..63
+// over (log alpha_min, log ||A||_F^2 + 1]; then a multisection on the
+// bracket. T < 0 (noise-free data) keeps the floor. Returns the branch
+// (1 floor, 2 root) and writes alpha.
+__device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd, const double* se,
+                                               const z64* sq, double T, double fro, double eta,
+                                               double* alpha_out) {
+  const double amin = eta * fro;
+  double al = amin;
+  int br = 1;
+  if (T >= 0.0) {
+    // round 0: lane 0 tests the floor alpha_min; lanes 1..63 spread over
+    // (log alpha_min, log ||A||_F^2 + 1], where the root almost always is
+    const double h0 = log(fro) + 1.0;
+    double lo = log(amin);
+    const double st0 = (h0 - lo) / 63.0;
+    double ph = phi_fwd(sd, se, sq, n, exp(lane == 0 ? lo : lo + st0 * lane));
+    unsigned long long bal = __ballot(ph >= T);
+    if (!(bal & 1ull)) {
+      br = 2;
+      // bracket [lo, hi] on x = log(alpha) with phi(lo) < T <= phi(hi);
+      // flo / fhi hold phi at the ends once known (NaN otherwise)
+      const double nan = __longlong_as_double(0x7ff8000000000000ll);
+      double hi, flo, fhi = nan;
+      if (bal) {
+        const int l1 = __ffsll((long long)bal) - 1;
+        hi = lo + st0 * l1;
+        fhi = __shfl(ph, l1);
+        lo = lo + st0 * (l1 - 1);
+        flo = __shfl(ph, l1 - 1);
+      } else {
+        // the root lies above: probe upward in steps of 4
+        lo = h0;
+        flo = __shfl(ph, 63);
+        const double pu = phi_fwd(sd, se, sq, n, exp(h0 + 4.0 * (lane + 1)));
+        const unsigned long long bu = __ballot(pu >= T);
+        if (bu) {
+          const int l1 = __ffsll((long long)bu) - 1;
+          hi = h0 + 4.0 * (l1 + 1);
+          fhi = __shfl(pu, l1);
+          if (l1 > 0) {
+            lo = h0 + 4.0 * l1;
+            flo = __shfl(pu, l1 - 1);
+          }
+        } else {
+          hi = h0 + 4.0 * 64;
+          lo = hi;
+        }
       }
-    }
+      // Multisection with 64 points per round. Once phi is known at both
+      // ends, the points are packed around the secant estimate of the
+      // root (phi is smooth in log alpha, so the secant error shrinks like
+      // the square of the bracket). A window that misses the root still
+      // leaves a valid, smaller bracket; the round after a miss spreads
+      // its points over the whole bracket again.
+      // The search stops once the bracket is below 3e-8 in log(alpha): the
+      // secant point is then within about curvature * 1e-16 of the root.
+      bool miss = false;
+      for (int round = 0; round < 24 && hi - lo > 3e-8; ++round) {
+        const double wdt = hi - lo;
+        double a0 = lo, a1 = hi;
+        if (!miss && flo == flo && fhi == fhi && fhi > flo) {
+          const double xs = lo + (T - flo) / (fhi - flo) * wdt;
+          const double hw = fmax(0.25 * wdt * wdt, 1e-5 * wdt);
+          a0 = fmax(lo, xs - hw);
+          a1 = fmin(hi, xs + hw);
+        }
+        // 64 points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
+        const double step = (a1 - a0) / (a1 < hi ? 64.0 : 65.0);
+        const double pl = phi_fwd(sd, se, sq, n, exp(a0 + step * (lane + 1)));
+        const unsigned long long b2 = __ballot(pl >= T);
+        if (b2) {
+          const int l1 = __ffsll((long long)b2) - 1;
+          if (l1 >= 1 && step <= 2e-3) {
+            // The root lies between two points of this round's grid, spaced
+            // at most 2e-3: the cubic through the four grid points around it
+            // places the root within about step^4 |phi^(4) / phi'| / 24
+            // (below 1e-12 in log alpha), so no further round is needed.
+            // Newton on the cubic in t (grid index from j0), from the secant
+            // point, kept inside the bracketing grid interval.
+            const int j0 = min(max(l1 - 2, 0), 60);
+            const double p0 = __shfl(pl, j0), p1 = __shfl(pl, j0 + 1);
+            const double p2 = __shfl(pl, j0 + 2), p3 = __shfl(pl, j0 + 3);
+            const double d1 = p1 - p0, d2 = p2 - 2.0 * p1 + p0;
+            const double d3 = p3 - 3.0 * p2 + 3.0 * p1 - p0;
+            const double pa = __shfl(pl, l1 - 1), pb = __shfl(pl, l1);
+            const double ta = (double)(l1 - 1 - j0), tb = ta + 1.0;
+            double t = ta + (pb > pa ? (T - pa) / (pb - pa) : 0.5);
 #pragma unroll
-    for (int g = 0; g < GR; ++g) {
-      if (k0 + g + 1 >= n) break;
-      z64 s = cmulc(v0[g], q0);
-      if constexpr (NMAX > 64) s = cfmac(s, v1[g], q1);
-      s.x = lanes_sum<64>(s.x);
-      s.y = lanes_sum<64>(s.y);
-      s = gg[g] * s;
-      q0 = q0 - v0[g] * s;
-      if constexpr (NMAX > 64) q1 = q1 - v1[g] * s;
+            for (int it = 0; it < 3; ++it) {
+              const double pt = p0 + t * (d1 + (t - 1.0) * (0.5 * d2 + (t - 2.0) * d3 / 6.0));
+              const double dp = d1 + (2.0 * t - 1.0) * 0.5 * d2 +
+                                (3.0 * t * t - 6.0 * t + 2.0) * d3 / 6.0;
+              if (dp > 0.0) t = t - (pt - T) / dp;
+              t = fmin(tb, fmax(ta, t));
+            }
+            *alpha_out = exp(a0 + step * ((double)j0 + t + 1.0));
+            return br;
+          }
+          miss = l1 == 0 && a0 > lo;  // the root may lie left of the window
+          hi = a0 + step * (l1 + 1);
+          fhi = __shfl(pl, l1);
+          if (l1 > 0) {
+            lo = a0 + step * l1;
+            flo = __shfl(pl, l1 - 1);
+          }
+        } else {
+          miss = a1 < hi;             // the root lies right of the window
+          lo = a0 + step * 64;
+          flo = __shfl(pl, 63);
+        }
+      }
+      double xr = 0.5 * (lo + hi);
+      if (flo == flo && fhi == fhi && fhi > flo)
+        xr = fmin(hi, fmax(lo, lo + (T - flo) / (fhi - flo) * (hi - lo)));
+      al = exp(xr);
     }
   }
-  if (lane < n) sq[lane] = q0;
-  if constexpr (NMAX > 64)
-    if (lane + 64 < n) sq[lane + 64] = q1;
+  *alpha_out = al;
+  return br;
 }
 
-// One single-wave workgroup per active system: phase-scale the bidiagonal to
-// a real one, choose alpha by the discrepancy principle with a 64-way
-// multisection on log(alpha), solve at that alpha (Elden), apply the right
-// reflectors (v^ = V y) and scatter v^ into the plane-major array.
-template <int NMAX>
+// Householder reflectors applied to one vector by a group of G lanes
+// (element i held by lane i % G in slot i / G): x <- H_k x for k = k0, k0 + dk,
+// ..., with H_k = I - g_k h_k h_k^H and h_k in row k of R (entries from
+// first(k) on). Rows are loaded RG at a time so that their latency overlaps.
+template <int G, int E, int RG>
+__device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict__ R,
+                                              const double* __restrict__ gam, int n, int gl,
+                                              int k0, int kend, int dk, int off) {
+  // reflector k has entries k + off .. n - 1
+  for (int kb = k0; dk > 0 ? kb < kend : kb > kend; kb += dk * RG) {
+    z64 v[RG][E];
+    double gg[RG];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      const int k = kb + dk * g;
+      const bool ok = dk > 0 ? k < kend : k > kend;
+      gg[g] = ok ? gam[k] : 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int i = gl + G * e;
+        v[g][e] = (ok && i >= k + off && i < n) ? R[(long)k * n + i] : mk(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      z64 sm = mk(0.0, 0.0);
+#pragma unroll
+      for (int e = 0; e < E; ++e) sm = cfmac(sm, v[g][e], x[e]);
+      sm.x = lanes_sum<G>(sm.x);
+      sm.y = lanes_sum<G>(sm.y);
+      sm = gg[g] * sm;
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] = x[e] - v[g][e] * sm;
+    }
+  }
+}
+
+// SPW systems per single-wave workgroup. The phase scaling and the alpha
+// search use the whole wave for one system at a time (64 trial alphas per
+// round); q = U^H w (shared factorizations), the Elden solve and the
+// back-transform v^ = V (D_R y) run for the SPW systems at once, each in a
+// group of G = 64 / SPW lanes, so their reductions span G lanes only.
+template <int NMAX, int SPW>
 __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
-  __shared__ double sd[NMAX], se[NMAX], srho[NMAX], soff[NMAX];
-  __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
-  const int lane = threadIdx.x;
+  constexpr int G = 64 / SPW;
+  constexpr int E = (NMAX + G - 1) / G;
+  constexpr int RG = E >= 4 ? 2 : (E == 2 ? 4 : 8);
+  // per system: real bidiagonal (sd, se; the Elden solve overwrites them
+  // with its rho and off), q' (sq), the complex superdiagonal and then the
+  // Elden right-hand side (srr), the complex diagonal and then y (sy), the
+  // right phases (sdr)
+  __shared__ double sd[SPW][NMAX], se[SPW][NMAX];
+  __shared__ z64 sq[SPW][NMAX], srr[SPW][NMAX], sy[SPW][NMAX], sdr[SPW][NMAX];
+  __shared__ double sal[SPW];
+  __shared__ int sbr[SPW];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int n = a.n;
   const int total = *a.count;
-  for (int sl = blockIdx.x; sl < a.C; sl += gridDim.x) {
-    const int gs = a.chunk0 + sl;
-    if (gs >= total) break;
-    const int fm = a.list[gs];
-    const int f = (int)(fm / a.N);
-    const long m = fm - (long)f * a.N;
-    // factorization slot: the system's own, or its orbit's
-    const long fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
-    // stage the complex bidiagonal and q
-    for (int i = lane; i < n; i += 64) {
-      sy[i] = a.dg[fs * n + i];
-      srr[i] = a.sp[fs * n + i];
-      if (!a.oslot) sq[i] = a.q[(long)sl * n + i];
-    }
-    if (a.oslot)
-      dp_left_apply<NMAX>(a.What + (long)f * n * a.N + m, a.N, n, a.refl_l + fs * n * n,
-                          a.gam_l + fs * n, lane, sq);
-    __syncthreads();
-    dp_phase_scale<NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
-    __syncthreads();
-    if (!a.oslot) {
-      // kept for the derivative kernels (per-system factorizations only)
-      for (int i = lane; i < n; i += 64) {
-        a.bd_d[(long)sl * n + i] = sd[i];
-        a.bd_e[(long)sl * n + i] = se[i];
-        a.bd_dr[(long)sl * n + i] = sdr[i];
+  const int ngr = (a.C + SPW - 1) / SPW;
+  for (int sg = blockIdx.x; sg < ngr; sg += gridDim.x) {
+    const int sl0 = sg * SPW;
+    if (a.chunk0 + sl0 >= total) break;
+    // this lane's group system
+    const int sl = sl0 + grp, gs = a.chunk0 + sl;
+    const bool live = sl < a.C && gs < total;
+    int f = 0;
+    long m = 0, fs = 0;
+    if (live) {
+      const int fm = a.list[gs];
+      f = (int)(fm / a.N);
+      m = fm - (long)f * a.N;
+      // factorization slot: the system's own, or its orbit's
+      fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
+      for (int e = 0; e < E; ++e) {
+        const int i = gl + G * e;
+        if (i < n) {
+          sy[grp][i] = a.dg[fs * n + i];
+          srr[grp][i] = a.sp[fs * n + i];
+        }
+      }
+      if (a.oslot) {
+        // q = U^H w = H_{n-2} ... H_0 w from the orbit's left reflectors
+        const z64* w = a.What + (long)f * n * a.N + m;
+        z64 x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          x[e] = i < n ? w[(long)i * a.N] : mk(0.0, 0.0);
+        }
+        group_reflect<G, E, RG>(x, a.refl_l + fs * n * n, a.gam_l + fs * n, n, gl, 0, n - 1, 1,
+                                0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          if (i < n) sq[grp][i] = x[e];
+        }
+      } else {
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          if (i < n) sq[grp][i] = a.q[(long)sl * n + i];
+        }
       }
     }
-    const double T = a.thr2[f];
-    const double fro = a.fro[fs];
-    const double amin = a.eta * fro;
-    double al = amin;
-    signed char br = 1;
-    if (a.alpha_fixed) {
-      al = a.alpha_fixed[f];
-      br = a.branch_fixed[f];
-    } else if (T >= 0.0) {
-      // round 0: lane 0 tests the floor alpha_min; lanes 1..63 spread over
-      // (log alpha_min, log ||A||_F^2 + 1], where the root almost always is
-      const double h0 = log(fro) + 1.0;
-      double lo = log(amin);
-      const double st0 = (h0 - lo) / 63.0;
-      double ph = phi_fwd(sd, se, sq, n, exp(lane == 0 ? lo : lo + st0 * lane));
-      unsigned long long bal = __ballot(ph >= T);
-      if (!(bal & 1ull)) {
-        br = 2;
-        // bracket [lo, hi] on x = log(alpha) with phi(lo) < T <= phi(hi);
-        // flo / fhi hold phi at the ends once known (NaN otherwise)
-        const double nan = __longlong_as_double(0x7ff8000000000000ll);
-        double hi, flo, fhi = nan;
-        if (bal) {
-          const int l1 = __ffsll((long long)bal) - 1;
-          hi = lo + st0 * l1;
-          fhi = __shfl(ph, l1);
-          lo = lo + st0 * (l1 - 1);
-          flo = __shfl(ph, l1 - 1);
-        } else {
-          // the root lies above: probe upward in steps of 4
-          lo = h0;
-          flo = __shfl(ph, 63);
-          const double pu = phi_fwd(sd, se, sq, n, exp(h0 + 4.0 * (lane + 1)));
-          const unsigned long long bu = __ballot(pu >= T);
-          if (bu) {
-            const int l1 = __ffsll((long long)bu) - 1;
-            hi = h0 + 4.0 * (l1 + 1);
-            fhi = __shfl(pu, l1);
-            if (l1 > 0) {
-              lo = h0 + 4.0 * l1;
-              flo = __shfl(pu, l1 - 1);
-            }
-          } else {
-            hi = h0 + 4.0 * 64;
-            lo = hi;
-          }
+    __syncthreads();
+    // phase scaling and alpha, one system at a time over the whole wave
+    for (int s = 0; s < SPW; ++s) {
+      const int sls = sl0 + s, gss = a.chunk0 + sls;
+      if (sls >= a.C || gss >= total) break;
+      const int fms = a.list[gss];
+      const int fsf = (int)(fms / a.N);
+      const long ms = fms - (long)fsf * a.N;
+      const long fss = a.oslot ? a.oslot[(long)fsf * a.N + a.orep[ms]] : sls;
+      dp_phase_scale<NMAX>(n, lane, sd[s], se[s], sq[s], srr[s], sy[s], sdr[s]);
+      __syncthreads();
+      if (!a.oslot) {
+        // kept for the derivative kernels (per-system factorizations only)
+        for (int i = lane; i < n; i += 64) {
+          a.bd_d[(long)sls * n + i] = sd[s][i];
+          a.bd_e[(long)sls * n + i] = se[s][i];
+          a.bd_dr[(long)sls * n + i] = sdr[s][i];
         }
-        // Multisection with 64 points per round. Once phi is known at both
-        // ends, the points are packed around the secant estimate of the
-        // root (phi is smooth in log alpha, so the secant error shrinks like
-        // the square of the bracket). A window that misses the root still
-        // leaves a valid, smaller bracket; the round after a miss spreads
-        // its points over the whole bracket again.
-        // The search stops once the bracket is below 3e-8 in log(alpha): the
-        // secant point is then within about curvature * 1e-16 of the root.
-        bool miss = false;
-        for (int round = 0; round < 24 && hi - lo > 3e-8; ++round) {
-          const double wdt = hi - lo;
-          double a0 = lo, a1 = hi;
-          if (!miss && flo == flo && fhi == fhi && fhi > flo) {
-            const double xs = lo + (T - flo) / (fhi - flo) * wdt;
-            const double hw = fmax(0.25 * wdt * wdt, 1e-5 * wdt);
-            a0 = fmax(lo, xs - hw);
-            a1 = fmin(hi, xs + hw);
-          }
-          // 64 points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
-          const double step = (a1 - a0) / (a1 < hi ? 64.0 : 65.0);
-          const double pl = phi_fwd(sd, se, sq, n, exp(a0 + step * (lane + 1)));
-          const unsigned long long b2 = __ballot(pl >= T);
-          if (b2) {
-            const int l1 = __ffsll((long long)b2) - 1;
-            miss = l1 == 0 && a0 > lo;  // the root may lie left of the window
-            hi = a0 + step * (l1 + 1);
-            fhi = __shfl(pl, l1);
-            if (l1 > 0) {
-              lo = a0 + step * l1;
-              flo = __shfl(pl, l1 - 1);
-            }
-          } else {
-            miss = a1 < hi;             // the root lies right of the window
-            lo = a0 + step * 64;
-            flo = __shfl(pl, 63);
-          }
-        }
-        double xr = 0.5 * (lo + hi);
-        if (flo == flo && fhi == fhi && fhi > flo)
-          xr = fmin(hi, fmax(lo, lo + (T - flo) / (fhi - flo) * (hi - lo)));
-        al = exp(xr);
       }
-    }
-    if (br == 0) {
-      // one alpha per frequency with the data inside the noise level: v^ = 0
+      double al;
+      int br;
+      if (a.alpha_fixed) {
+        al = a.alpha_fixed[fsf];
+        br = a.branch_fixed[fsf];
+      } else {
+        br = dp_choose_alpha(n, lane, sd[s], se[s], sq[s], a.thr2[fsf], a.fro[fss], a.eta, &al);
+      }
       if (lane == 0) {
-        a.alpha[fm] = INFINITY;
-        a.branch[fm] = 0;
+        sal[s] = al;
+        sbr[s] = br;
       }
       __syncthreads();
-      continue;
     }
-    if (lane == 0) elden_solve(sd, se, sq, n, al, srho, soff, srr, sy);
+    // Elden solve of each group's system by the group's first lane
+    const int br = live ? sbr[grp] : 0;
+    const double al = live ? sal[grp] : 0.0;
+    if (br != 0 && gl == 0)
+      elden_solve(sd[grp], se[grp], sq[grp], n, al, sd[grp], se[grp], srr[grp], sy[grp]);
     __syncthreads();
-    // v^ = V (D_R y'), V = P_0 P_1 ... P_{n-3}
-    z64 y0 = lane < n ? sdr[lane] * sy[lane] : mk(0.0, 0.0);
-    z64 y1 = NMAX > 64 && lane + 64 < n ? sdr[lane + 64] * sy[lane + 64] : mk(0.0, 0.0);
-    const z64* R = a.refl + fs * n * n;
-    const double* G = a.gam + fs * n;
-    // reflector k has entries k+1..n-1; rows are loaded eight at a time so
-    // that their global-memory latency overlaps
-    constexpr int GR = 8;
-    for (int k0 = n - 3; k0 >= 0; k0 -= GR) {
-      z64 v0[GR], v1[GR];
-      double gg[GR];
+    if (live) {
+      const int fm = a.list[gs];
+      if (br == 0) {
+        // one alpha per frequency with the data inside the noise level: v^ = 0
+        if (gl == 0) {
+          a.alpha[fm] = INFINITY;
+          a.branch[fm] = 0;
+        }
+      } else {
+        // v^ = V (D_R y), V = P_0 P_1 ... P_{n-3}: apply P_{n-3} first
+        z64 y[E];
 #pragma unroll
-      for (int g = 0; g < GR; ++g) {
-        const int k = k0 - g;
-        gg[g] = 0.0;
-        v0[g] = mk(0.0, 0.0);
-        v1[g] = mk(0.0, 0.0);
-        if (k >= 0) {
-          gg[g] = G[k];
-          if (lane > k && lane < n) v0[g] = R[(long)k * n + lane];
-          if constexpr (NMAX > 64)
-            if (lane + 64 > k && lane + 64 < n) v1[g] = R[(long)k * n + lane + 64];
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          y[e] = i < n ? sdr[grp][i] * sy[grp][i] : mk(0.0, 0.0);
+        }
+        group_reflect<G, E, RG>(y, a.refl + fs * n * n, a.gam + fs * n, n, gl, n - 3, -1, -1, 1);
+        const long o0 = (long)f * n * a.N + m;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          if (i < n) {
+            if (a.vh_single)
+              ((z32*)a.Vh)[o0 + (long)i * a.N] = cast<float>(y[e]);
+            else
+              ((z64*)a.Vh)[o0 + (long)i * a.N] = y[e];
+          }
+        }
+        if (gl == 0) {
+          a.alpha[fm] = al;
+          a.branch[fm] = (signed char)br;
         }
       }
-#pragma unroll
-      for (int g = 0; g < GR; ++g) {
-        if (k0 - g < 0) break;
-        z64 s = cmulc(v0[g], y0);
-        if constexpr (NMAX > 64) s = cfmac(s, v1[g], y1);
-        s.x = lanes_sum<64>(s.x);
-        s.y = lanes_sum<64>(s.y);
-        s = gg[g] * s;
-        y0 = y0 - v0[g] * s;
-        if constexpr (NMAX > 64) y1 = y1 - v1[g] * s;
-      }
-    }
-    const long o0 = (long)f * n * a.N + m;
-    if (a.vh_single) {
-      z32* out = (z32*)a.Vh + o0;
-      if (lane < n) out[(long)lane * a.N] = cast<float>(y0);
-      if (lane + 64 < n) out[(long)(lane + 64) * a.N] = cast<float>(y1);
-    } else {
-      z64* out = (z64*)a.Vh + o0;
-      if (lane < n) out[(long)lane * a.N] = y0;
-      if (lane + 64 < n) out[(long)(lane + 64) * a.N] = y1;
-    }
-    if (lane == 0) {
-      a.alpha[fm] = al;
-      a.branch[fm] = br;
     }
     __syncthreads();
   }

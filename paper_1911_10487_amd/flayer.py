@@ -39,12 +39,13 @@ class FlOpts(ctypes.Structure):
         ("max_chunk", ctypes.c_int),
         ("kernel_mode", ctypes.c_int), ("damping", ctypes.c_double),
         ("alpha_rule", ctypes.c_int), ("factor_per_system", ctypes.c_int),
+        ("forward_method", ctypes.c_int), ("prefactor", ctypes.c_int),
     ]
 
 
 class FlTuning(ctypes.Structure):
     _fields_ = [("bidiag_variant", ctypes.c_int), ("bidiag_grid", ctypes.c_int),
-                ("dp_grid", ctypes.c_int)]
+                ("dp_grid", ctypes.c_int), ("dp_systems_per_wave", ctypes.c_int)]
 
 
 class FlPlanInfo(ctypes.Structure):
@@ -148,13 +149,15 @@ class Plan:
 
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
                  tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0,
-                 kernel_mode=0, damping=0.0, alpha_rule=0, factor_per_system=0):
+                 kernel_mode=0, damping=0.0, alpha_rule=0, factor_per_system=0,
+                 forward_method=0, prefactor=0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
         o.max_chunk = max_chunk
         o.kernel_mode, o.damping = kernel_mode, damping
         o.alpha_rule, o.factor_per_system = alpha_rule, factor_per_system
+        o.forward_method, o.prefactor = forward_method, prefactor
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)
@@ -249,10 +252,10 @@ class Plan:
         t = FlTuning()
         _check(lib().fl_tuning_get(self._h, ctypes.byref(t)))
         return {"bidiag_variant": t.bidiag_variant, "bidiag_grid": t.bidiag_grid,
-                "dp_grid": t.dp_grid}
+                "dp_grid": t.dp_grid, "dp_systems_per_wave": t.dp_systems_per_wave}
 
-    def set_tuning(self, bidiag_variant=0, bidiag_grid=0, dp_grid=0):
-        t = FlTuning(bidiag_variant, bidiag_grid, dp_grid)
+    def set_tuning(self, bidiag_variant=0, bidiag_grid=0, dp_grid=0, dp_systems_per_wave=0):
+        t = FlTuning(bidiag_variant, bidiag_grid, dp_grid, dp_systems_per_wave)
         _check(lib().fl_tuning_set(self._h, ctypes.byref(t)))
 
     def tuning_variants(self):

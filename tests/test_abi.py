@@ -106,3 +106,17 @@ def test_closed_form_kernel_needs_damping_on_the_k0_circle():
 def test_alpha_rule_is_validated():
     st, msg, out = _create(alpha_rule=2)
     assert st == flayer.FL_EINVAL and "alpha_rule" in msg and not out.value
+
+
+def test_forward_method_is_validated():
+    st, msg, out = _create(forward_method=2)
+    assert st == flayer.FL_EINVAL and "forward_method" in msg and not out.value
+
+
+def test_prefactor_is_validated():
+    st, msg, out = _create(prefactor=2)
+    assert st == flayer.FL_EINVAL and "prefactor" in msg and not out.value
+    st, msg, out = _create(prefactor=1, factor_per_system=1)
+    assert st == flayer.FL_EUNSUPPORTED and "prefactor" in msg and not out.value
+    st, msg, out = _create(prefactor=1, alpha_rule=1)
+    assert st == flayer.FL_EUNSUPPORTED and not out.value

@@ -177,6 +177,34 @@ def test_forward_lippmann_schwinger_matches_oracle(input_dtype):
         assert rel(W[f], ref[f]) <= 1e-10
 
 
+def test_forward_fixed_point_matches_oracle():
+    # forward_method 1: the paper's Algorithm 1 fixed point on the GPU (both
+    # frequencies at once) vs the oracle's, to the same change tolerance;
+    # where it does not converge (3x the contrast at omega = 2 pi), FL_ENOCONV
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import FlError, FL_ENOCONV, Plan
+    p = synth.tiny_problem(nx=12, ny=10, nz=16, px=24, py=20, omegas=(np.pi, 2.0))
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    ref = np.stack([model.data_operator(p, f, xi * forward.fixed_point_field(p, f, xi, u0[f],
+                                                                              tol=1e-13)[0])
+                    for f in range(p.n_omega)])
+    plan = Plan.from_problem(p, forward_method=1)
+    W = plan.forward(torch.from_numpy(xi).cuda(), torch.from_numpy(u0).cuda(), maxit=200,
+                     tol=1e-13).cpu().numpy()
+    plan.close()
+    for f in range(p.n_omega):
+        say("fixed point f", f, rel(W[f], ref[f]))
+        assert rel(W[f], ref[f]) <= 1e-10
+    q = synth.tiny_problem(nx=12, ny=10, nz=16, px=24, py=20, omegas=(2 * np.pi,))
+    plan = Plan.from_problem(q, forward_method=1)
+    with pytest.raises(FlError) as e:
+        plan.forward(torch.from_numpy(3.0 * synth.contrast(q)).cuda(),
+                     torch.from_numpy(synth.incident_field(q)).cuda(), maxit=60, tol=1e-13)
+    assert e.value.status == FL_ENOCONV
+    plan.close()
+
+
 def _ragged(delta_list=(0.02,)):
     # non-square window and torus with radix-3 and radix-5 lengths, two
     # frequencies (least squares), ragged edges in every direction
@@ -415,3 +443,30 @@ def test_orbit_and_per_system_factorizations_match_oracle(case, delta):
         out.append(xi)
     say("orbit vs per-system", case, delta, rel(out[0], out[1]))
     assert rel(out[0], out[1]) <= tol_for(delta)
+
+
+@pytest.mark.parametrize("case,delta", [("small", 0.01), ("ragged", 0.02), ("ragged", 0.0)])
+def test_plan_time_factorization_matches_per_call(case, delta):
+    """prefactor 1 (every orbit factorized once at plan creation) gives
+    bitwise the xi of the per-call factorization with the same schedule, and
+    the oracle's; two calls on different data reuse the factorization."""
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import Plan
+    p, W, u0 = _global_case(case)
+    outs = []
+    for pre in (0, 1):
+        plan = Plan.from_problem(p, prefactor=pre)
+        ut = torch.from_numpy(u0).cuda()
+        xs = []
+        for d in (delta, 0.05):
+            Wd = synth.add_noise(p, W, d)
+            xs.append(plan.invert(torch.from_numpy(Wd).cuda(), ut, d).cpu().numpy())
+        if pre:
+            assert plan.factorized_systems() == 0
+        plan.close()
+        outs.append(xs)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    ref = invert.invert(p, synth.add_noise(p, W, delta), u0, delta)
+    say("prefactor", case, delta, rel(outs[1][0], ref))
+    assert rel(outs[1][0], ref) <= tol_for(delta)
