@@ -102,11 +102,14 @@ struct fl_plan {
   int gB = 0;
   // shared factorizations: orbits of the wavenumber symmetries (orep [N]
   // representative, omem [N][8] members of a representative's orbit), the
-  // active orbits compacted like the systems, and the left reflectors
+  // active orbits compacted like the systems (oflag: active members per
+  // representative), the active systems regrouped by orbit (ocnt: the
+  // active members per block of 1024 representatives, then the blocks'
+  // offsets), and the left reflectors
   bool orbits = false;
   int n_orb = 0;
   int *orep = nullptr, *omem = nullptr, *oflag = nullptr, *olist = nullptr, *ocount = nullptr,
-      *oslot = nullptr;
+      *oslot = nullptr, *ocnt = nullptr, *olist_sys = nullptr;
   z64* refl_l = nullptr;
   double* gam_l = nullptr;
   // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
@@ -438,24 +441,23 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
   return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
 }
 
-// Classification, compaction of the systems that need a solve, and the
-// zero fill of v^ (inactive systems keep v^ = 0).
+// Classification (with v^ = 0 written for the systems without a solve) and,
+// unless the systems are grouped by orbit afterwards, their compaction.
 template <typename T>
-fl_status solve_prepare(fl_plan* p) {
+fl_status solve_prepare(fl_plan* p, bool compact) {
   const long FN = (long)p->F * p->N;
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
   hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const z64*)p->What,
-                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), p->wn2, p->flag);
+                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), p->wn2, p->flag,
+                     p->Vh, (int)(sizeof(T) == 4), p->nz);
   LAUNCHCHK();
+  if (!compact) return FL_OK;
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->count);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt, p->list);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * p->nz, 256)), dim3(256), 0, st, (cx<T>*)p->Vh,
-                     FN * p->nz);
   LAUNCHCHK();
   return FL_OK;
 }
@@ -504,7 +506,9 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
   a.alpha_fixed = fixed ? p->galpha : nullptr;
   a.branch_fixed = fixed ? p->gbranch : nullptr;
   if (shared) {
-    // every active system in one launch, factorizations by orbit slot
+    // every active system in one launch, grouped by orbit, factorizations by
+    // orbit slot
+    a.list = p->olist_sys;
     a.C = (int)((long)p->F * p->N);
     a.oslot = p->oslot;
     a.orep = p->orep;
@@ -593,6 +597,32 @@ fl_status solve_global(fl_plan* p) {
   return FL_OK;
 }
 
+// Orbits with an active member, compacted in increasing f N + r (olist,
+// oslot, ocount; kept as they are when every orbit was factorized at plan
+// creation), and the active systems grouped by orbit (olist_sys, count), so
+// that the systems sharing a factorization are solved side by side.
+fl_status group_by_orbit(fl_plan* p) {
+  const long FN = (long)p->F * p->N;
+  hipStream_t st = p->st;
+  hipLaunchKernelGGL(k_orbit_flag, dim3(nblk(FN, 256)), dim3(256), 0, st, p->flag, p->orep, p->omem,
+                     p->N, p->F, p->oflag);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_orbit_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN,
+                     p->cnt, p->ocnt);
+  LAUNCHCHK();
+  if (!p->prefactored) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->ocount);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->ocnt, p->nb_scan, p->count);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_orbit_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->omem,
+                     p->flag, p->N, p->cnt, p->ocnt, p->prefactored ? nullptr : p->olist,
+                     p->prefactored ? nullptr : p->oslot, p->olist_sys);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
 // Bidiagonalization of the compacted orbit representatives, keeping their
 // left reflectors.
 template <typename T>
@@ -611,22 +641,7 @@ fl_status run_bidiag_orbits(fl_plan* p) {
 // factorization (q = U^H w from the left reflectors).
 template <typename T>
 fl_status solve_orbits(fl_plan* p) {
-  const long FN = (long)p->F * p->N;
-  const long FO = (long)p->F * p->n_orb;
-  hipStream_t st = p->st;
-  hipLaunchKernelGGL(k_orbit_flag, dim3(nblk(FN, 256)), dim3(256), 0, st, p->flag, p->orep, p->omem,
-                     p->N, p->F, p->oflag);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->cnt);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->ocount);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->cnt,
-                     p->olist);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_orbit_slot, dim3(nblk(FO, 256)), dim3(256), 0, st, p->olist, p->ocount,
-                     p->oslot);
-  LAUNCHCHK();
+  RUN(group_by_orbit(p));
   RUN(run_bidiag_orbits<T>(p));
   return run_dp<T>(p, 0, false, true);
 }
@@ -662,10 +677,13 @@ fl_status prefactor(fl_plan* p, const std::vector<int>& reps) {
 template <typename T>
 fl_status solve_systems(fl_plan* p, bool shared = true) {
   const long FN = (long)p->F * p->N;
-  RUN(solve_prepare<T>(p));
   p->last_shared = p->opts.alpha_rule == 0 && shared && p->orbits;
+  RUN(solve_prepare<T>(p, !p->last_shared));
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
-  if (p->last_shared && p->prefactored) return run_dp<T>(p, 0, false, true);
+  if (p->last_shared && p->prefactored) {
+    RUN(group_by_orbit(p));
+    return run_dp<T>(p, 0, false, true);
+  }
   if (p->last_shared) return solve_orbits<T>(p);
   for (long c0 = 0; c0 < FN; c0 += p->C) RUN(solve_chunk<T>(p, c0));
   return FL_OK;
@@ -1510,6 +1528,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
       PALLOC(p->olist, FO);
       PALLOC(p->ocount, 1);
       PALLOC(p->oslot, FN);
+      PALLOC(p->ocnt, p->nb_scan);
+      PALLOC(p->olist_sys, FN);
       PALLOC(p->refl_l, FO * nz * nz);
       PALLOC(p->gam_l, FO * nz);
       hipError_t e = hipMemcpy(p->orep, orep.data(), N * sizeof(int), hipMemcpyHostToDevice);

@@ -31,7 +31,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What, int nd, long N,
                                                   int F, const double* __restrict__ thr2,
                                                   int solve_all, double* __restrict__ wn2,
-                                                  int* __restrict__ flag) {
+                                                  int* __restrict__ flag, void* __restrict__ Vh,
+                                                  int vh_single, int nz) {
   long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (fm >= (long)F * N) return;
   int f = (int)(fm / N);
@@ -57,38 +58,130 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   // thr2[f] < 0 marks noise-free data, solve_all the rule with one alpha per
   // frequency: then every nonzero system is solved
   double t = thr2[f];
-  flag[fm] = (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
+  const int act = (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
+  flag[fm] = act;
+  // v^ = 0 for a system without a solve (the solver writes the others)
+  if (!act) {
+    const long o0 = (long)f * nz * N + m;
+    if (vh_single)
+      for (int j = 0; j < nz; ++j) ((cx<float>*)Vh)[o0 + (long)j * N] = mk(0.f, 0.f);
+    else
+      for (int j = 0; j < nz; ++j) ((cx<double>*)Vh)[o0 + (long)j * N] = mk(0.0, 0.0);
+  }
 }
 
 // Wavenumbers related by the torus's mirror (and, on a square torus, swap)
-// symmetries share A_m: thread per (f, m); a representative m (orep[m] = m)
-// is flagged when any member of its orbit (omem[m][0..7], -1 padded) needs
-// a solve, every other m is not.
+// symmetries share A_m: thread per (f, m); for a representative m (orep[m]
+// = m), ocw[f N + m] counts the members of its orbit (omem[m][0..7], -1
+// padded) that need a solve; every other m gets 0.
 __global__ __launch_bounds__(256) void k_orbit_flag(const int* __restrict__ flag,
                                                     const int* __restrict__ orep,
                                                     const int* __restrict__ omem, long N, int F,
-                                                    int* __restrict__ oflag) {
+                                                    int* __restrict__ ocw) {
   const long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (fm >= (long)F * N) return;
   const int f = (int)(fm / N);
   const long m = fm - (long)f * N;
-  int any = 0;
+  int c = 0;
   if (orep[m] == m) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int mj = omem[m * 8 + j];
-      if (mj >= 0) any |= flag[(long)f * N + mj];
+      if (mj >= 0) c += flag[(long)f * N + mj];
     }
   }
-  oflag[fm] = any;
+  ocw[fm] = c;
 }
 
-// oslot[olist[o]] = o for the compacted orbits
-__global__ __launch_bounds__(256) void k_orbit_slot(const int* __restrict__ olist,
-                                                    const int* __restrict__ ocount,
-                                                    int* __restrict__ oslot) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o < *ocount) oslot[olist[o]] = o;
+// Inclusive scan of small ints over a 1024-thread block (wave shuffles, then
+// the wave totals in wsum); returns the thread's inclusive sum, and wsum[15]
+// holds the block's sum afterwards.
+__device__ __forceinline__ int block_incl_sum_scan(int v, int* wsum) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d);
+    if (lane >= d) v += u;
+  }
+  if (lane == 63) wsum[wv] = v;
+  __syncthreads();
+  if (wv == 0) {
+    int w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const int u = __shfl_up(w, d);
+      if (lane >= d) w += u;
+    }
+    if (lane < 16) wsum[lane] = w;
+  }
+  __syncthreads();
+  return v + (wv > 0 ? wsum[wv - 1] : 0);
+}
+
+// Per block of 1024 (f, m): the active orbits (cnt) and their active
+// members (cntw).
+__global__ __launch_bounds__(1024) void k_orbit_block_count(const int* __restrict__ ocw, long n,
+                                                            int* __restrict__ cnt,
+                                                            int* __restrict__ cntw) {
+  __shared__ int wsum[16];
+  __shared__ int wcnt[16];
+  const long i = (long)blockIdx.x * 1024 + threadIdx.x;
+  const int c = i < n ? ocw[i] : 0;
+  const unsigned long long bal = __ballot(c > 0);
+  if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = __popcll(bal);
+  block_incl_sum_scan(c, wsum);
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < 16; ++w) acc += wcnt[w];
+    cnt[blockIdx.x] = acc;
+    cntw[blockIdx.x] = wsum[15];
+  }
+}
+
+// Compaction of the active orbits in increasing f N + m (olist, oslot; NULL
+// keeps them, for factorizations made at plan creation) and of the active
+// systems grouped by orbit (members in omem order) into list, from the
+// exclusive block offsets cnt / cntw (k_scan of the block counts).
+__global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ ocw, long n,
+                                                        const int* __restrict__ omem,
+                                                        const int* __restrict__ flag, long N,
+                                                        const int* __restrict__ cnt,
+                                                        const int* __restrict__ cntw,
+                                                        int* __restrict__ olist,
+                                                        int* __restrict__ oslot,
+                                                        int* __restrict__ list) {
+  __shared__ int wsum[16];
+  __shared__ int wpre[16];
+  const long i = (long)blockIdx.x * 1024 + threadIdx.x;
+  const int c = i < n ? ocw[i] : 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const unsigned long long bal = __ballot(c > 0);
+  if (lane == 0) wpre[wv] = __popcll(bal);
+  const int incl = block_incl_sum_scan(c, wsum);
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int t = wpre[w];
+      wpre[w] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  if (c > 0) {
+    if (olist) {
+      const int o = cnt[blockIdx.x] + wpre[wv] + __popcll(bal & ((1ull << lane) - 1ull));
+      olist[o] = (int)i;
+      oslot[i] = o;
+    }
+    const int f = (int)(i / N);
+    const long m = i - (long)f * N;
+    int pos = cntw[blockIdx.x] + incl - c;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int mj = omem[m * 8 + j];
+      if (mj >= 0 && flag[(long)f * N + mj]) list[pos++] = (int)((long)f * N + mj);
+    }
+  }
 }
 
 __device__ __forceinline__ int block_excl_scan(int v, int* wsum, int* total) {
@@ -876,10 +969,19 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int n = a.n;
   const int total = *a.count;
-  const int ngr = (a.C + SPW - 1) / SPW;
-  for (int sg = blockIdx.x; sg < ngr; sg += gridDim.x) {
+  // groups of SPW systems that hold work in this launch
+  const int nsys = min(a.C, total - a.chunk0);
+  const int nact = nsys > 0 ? (nsys + SPW - 1) / SPW : 0;
+  // Workgroups go to the eight XCDs in turn: XCD x (of V = min(8, grid))
+  // takes the contiguous group range [x per, (x + 1) per), so that systems
+  // sharing an orbit's reflectors meet in one L2.
+  const int NG = gridDim.x, V = NG < 8 ? NG : 8;
+  const int xcd = blockIdx.x % V, nbx = (NG - xcd + V - 1) / V;
+  const int per = (nact + V - 1) / V;
+  for (int k = blockIdx.x / V; k < per; k += nbx) {
+    const int sg = xcd * per + k;
+    if (sg >= nact) break;
     const int sl0 = sg * SPW;
-    if (a.chunk0 + sl0 >= total) break;
     // this lane's group system
     const int sl = sl0 + grp, gs = a.chunk0 + sl;
     const bool live = sl < a.C && gs < total;
@@ -964,6 +1066,16 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       const int fm = a.list[gs];
       if (br == 0) {
         // one alpha per frequency with the data inside the noise level: v^ = 0
+        const long o0 = (long)f * n * a.N + m;
+        for (int e = 0; e < E; ++e) {
+          const int i = gl + G * e;
+          if (i < n) {
+            if (a.vh_single)
+              ((z32*)a.Vh)[o0 + (long)i * a.N] = mk(0.f, 0.f);
+            else
+              ((z64*)a.Vh)[o0 + (long)i * a.N] = mk(0.0, 0.0);
+          }
+        }
         if (gl == 0) {
           a.alpha[fm] = INFINITY;
           a.branch[fm] = 0;
