@@ -30,6 +30,8 @@ struct FftArgs {
   int in_kfast, out_kfast;
   double scale;
   const z64* add;   // optional FP64 addend laid out like the output
+  double* rowsq;    // optional, power-of-two kernels: sum of |input|^2 per
+                    // transform, [plane][b]
 };
 
 template <typename T>
@@ -600,6 +602,16 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_p2(Fft
   p2_stage_twiddles<T, L>((const cx<T>*)g.tw, tws, NT);
   cx<T> e[P2<L>::E];
   p2_load<TI, T, L>(g, e, b, plane, t);
+  if (g.rowsq) {
+    // the row's sum of squares while it is in registers (the threads of a
+    // transform are consecutive lanes on the unit-stride map)
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < P2<L>::E; ++s)
+      sq = fma((double)e[s].x, (double)e[s].x, fma((double)e[s].y, (double)e[s].y, sq));
+    sq = group_sum<L / P2<L>::E>(sq);
+    if (t == 0 && b < g.B) g.rowsq[(long)plane * g.B + b] = sq;
+  }
   p2_fft<T, DIR, L, false>(e, lds + bl * p2_row<L>(), tws, t);
   p2_store<TO, T, L>(g, e, b, plane, t);
 }

@@ -82,6 +82,7 @@ struct fl_plan {
   void *What = nullptr, *Vh = nullptr, *w1 = nullptr, *w2 = nullptr;
   z64 *vX = nullptr, *u = nullptr, *u0w = nullptr;
   double *wn2 = nullptr, *partial = nullptr, *thr2 = nullptr, *norm2 = nullptr;
+  double* rowsq = nullptr;  // per row of W: sum of squares (stage (a) rows)
   int *flag = nullptr, *cnt = nullptr, *list = nullptr, *count = nullptr;
   int nb_scan = 0;
   // solver chunk
@@ -823,17 +824,20 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(mark(p, FL_STAGE_NORM));
-  // noise thresholds: thr2[f] = (tau delta ||W_f||)^2
-  {
+  // noise thresholds thr2[f] = (tau delta ||W_f||)^2: from the sums of
+  // squares that the power-of-two row transform of stage (a) leaves per row,
+  // else from a pass over W of its own
+  const double td = p->opts.tau * delta;
+  const bool fused_norm = p2_supported(px);
+  if (!fused_norm) {
+    RUN(mark(p, FL_STAGE_NORM));
     dim3 g(256, F);
     if (p->opts.input_dtype == 0)
       hipLaunchKernelGGL(k_sumsq<double>, g, dim3(1024), 0, st, (const z64*)W, (long)nd * N, p->partial);
     else
       hipLaunchKernelGGL(k_sumsq<float>, g, dim3(1024), 0, st, (const z32*)W, (long)nd * N, p->partial);
     LAUNCHCHK();
-    double td = p->opts.tau * delta;
-    hipLaunchKernelGGL(k_thresholds, dim3(F), dim3(64), 0, st, p->partial, 256, F, td * td, p->thr2,
+    hipLaunchKernelGGL(k_thresholds, dim3(F), dim3(1024), 0, st, p->partial, 256, F, td * td, p->thr2,
                        p->norm2);
     LAUNCHCHK();
   }
@@ -850,10 +854,17 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
     // in FP64 in both precisions: the regularized solves amplify the
     // rounding of w^ by their conditioning
     FftArgs g = rows_args(W, p->w1, p->tw_x, px, (long)F * nd * py);
+    if (fused_norm) g.rowsq = p->rowsq;
     if (p->opts.input_dtype == 0)
       RUN((run_fft<double, double, double, -1>(g, st)));
     else
       RUN((run_fft<float, double, double, -1>(g, st)));
+    if (fused_norm) {
+      RUN(mark(p, FL_STAGE_NORM));
+      hipLaunchKernelGGL(k_thresholds, dim3(F), dim3(1024), 0, st, p->rowsq, nd * py, F, td * td,
+                         p->thr2, p->norm2);
+      LAUNCHCHK();
+    }
     RUN(mark(p, FL_STAGE_FFT_COLS));
     RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
   }
@@ -1449,6 +1460,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->list, FN);
   PALLOC(p->count, 1);
   PALLOC(p->partial, F * 256);
+  PALLOC(p->rowsq, (long)F * nd * py);
   PALLOC(p->thr2, F);
   PALLOC(p->norm2, F);
   // reflector workspace C * nz^2 complex; up to 24 GiB, so that the

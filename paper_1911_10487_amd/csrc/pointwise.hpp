@@ -152,19 +152,32 @@ __global__ __launch_bounds__(1024) void k_sumsq(const cx<TI>* __restrict__ W, lo
   }
 }
 
-// thr2[f] = (tau delta)^2 ||W_f||^2, or -1 for noise-free data. One wave per
-// frequency: strided partial sums, then a fixed-order lane reduction.
-__global__ __launch_bounds__(64) void k_thresholds(const double* __restrict__ partial, int nb, int F,
-                                                   double td2, double* __restrict__ thr2,
-                                                   double* __restrict__ norm2) {
+// thr2[f] = (tau delta)^2 ||W_f||^2, or -1 for noise-free data, from nb
+// partial sums per frequency. One 1024-thread block per frequency: strided
+// sums with four accumulators, then the lanes and the waves in a fixed order.
+__global__ __launch_bounds__(1024) void k_thresholds(const double* __restrict__ partial, int nb,
+                                                     int F, double td2, double* __restrict__ thr2,
+                                                     double* __restrict__ norm2) {
+  __shared__ double red[16];
   const int f = blockIdx.x;
   if (f >= F) return;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 64) s += partial[f * nb + b];
+  const double* pf = partial + (long)f * nb;
+  double a4[4] = {0.0, 0.0, 0.0, 0.0};
+  int b = threadIdx.x;
+  for (; b + 3 * 1024 < nb; b += 4 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] += pf[b + u * 1024];
+  }
+  for (; b < nb; b += 1024) a4[0] += pf[b];
+  double s = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   s = group_sum<64>(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    norm2[f] = s;
-    thr2[f] = td2 > 0.0 ? td2 * s : -1.0;
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    norm2[f] = t;
+    thr2[f] = td2 > 0.0 ? td2 * t : -1.0;
   }
 }
 
