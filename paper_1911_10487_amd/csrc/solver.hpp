@@ -295,7 +295,7 @@ struct BdShared {
 // time; the partially finished slots keep per-element tests.
 template <int TR, int TC, int NA, int NB, int SA, int SB>
 __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR * TC + 63) / 64>& S,
-                                        int k, int r, int c, int tid, int lane, int wv) {
+                                        int k, int r, int c, int tid, int lane, int wv, bool doq) {
   constexpr int n = TR * NA;
   constexpr int NW = (TR * TC + 63) / 64;
   const int par = k & 1;
@@ -372,7 +372,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
         for (int a = SA; a < NA; ++a) A[a][b] = cfms(A[a][b], ur[a], w);
       }
     }
-    if (c == 0) {
+    if (doq && c == 0) {
       z64 qa[NA];
 #pragma unroll
       for (int a = SA; a < NA; ++a) qa[a] = S.qv[r + TR * a];
@@ -475,14 +475,14 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
 template <int TR, int TC, int NA, int NB, int Q>
 __device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB],
                                           BdShared<TR * NA, (TR * TC + 63) / 64>& S, int r, int c,
-                                          int tid, int lane, int wv) {
+                                          int tid, int lane, int wv, bool doq) {
   constexpr int n = TR * NA;
   constexpr int KB = TR > TC ? TR : TC;
   if constexpr (Q * KB < n) {
     constexpr int SA = Q * KB / TR, SB = Q * KB / TC;
     for (int k = Q * KB; k < (Q + 1) * KB && k < n; ++k)
-      bd_step<TR, TC, NA, NB, SA, SB>(A, S, k, r, c, tid, lane, wv);
-    bd_blocks<TR, TC, NA, NB, Q + 1>(A, S, r, c, tid, lane, wv);
+      bd_step<TR, TC, NA, NB, SA, SB>(A, S, k, r, c, tid, lane, wv, doq);
+    bd_blocks<TR, TC, NA, NB, Q + 1>(A, S, r, c, tid, lane, wv, doq);
   }
 }
 
@@ -504,6 +504,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
   const int r = tid % TR, c = tid / TR;
   const int lane = tid & 63, wv = tid >> 6;
   const int total = *count;
+  const bool doq = o.refl_l == nullptr;
 
   for (int sl = blockIdx.x; sl < C; sl += gridDim.x) {
     const int gs = chunk0 + sl;
@@ -525,9 +526,10 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
         A[a][b] = S.tb[i - j + n - 1];
         fr += nrm2(A[a][b]);
       }
-    // q = U^H w (starts as w), rows r + TR a kept by the column-class-0 threads
+    // q = U^H w (starts as w), rows r + TR a kept by the column-class-0
+    // threads; not formed when the left reflectors are kept instead
     double wq = 0.0;
-    if (c == 0) {
+    if (doq && c == 0) {
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
         const z64 w = cast<double>(What[((long)f * n + r + TR * a) * N + m]);
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
       o.wn2[sl] = s1;
     }
 
-    bd_blocks<TR, TC, NA, NB, 0>(A, S, r, c, tid, lane, wv);
+    bd_blocks<TR, TC, NA, NB, 0>(A, S, r, c, tid, lane, wv, doq);
 
     __syncthreads();
     z64* refl = o.refl + (long)sl * n * n;
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
       o.dg[(long)sl * n + t] = S.dg[t];
       o.sp[(long)sl * n + t] = (t < n - 1) ? S.sp[t] : mk(0.0, 0.0);
     }
-    if (c == 0) {
+    if (doq && c == 0) {
 #pragma unroll
       for (int a = 0; a < NA; ++a) o.q[(long)sl * n + r + TR * a] = S.qv[r + TR * a];
     }

@@ -470,3 +470,26 @@ def test_plan_time_factorization_matches_per_call(case, delta):
     ref = invert.invert(p, synth.add_noise(p, W, delta), u0, delta)
     say("prefactor", case, delta, rel(outs[1][0], ref))
     assert rel(outs[1][0], ref) <= tol_for(delta)
+
+
+def test_odd_square_torus_orbits_match_oracle():
+    # a 45 x 45 torus: odd lengths, so the mirror images (px - mx) % px have
+    # no self-paired Nyquist line, and every orbit of the swap and mirrors
+    # holds 1, 4 or 8 wavenumbers
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import Plan
+    p = synth.make_problem("odd", 20, 20, 16, [2 * np.pi], 3, (31, 16), (0.02,), px=45, py=45)
+    W, u0 = _born_data(p, 0.02)
+    ref = invert.invert(p, W, u0, 0.02)
+    out = []
+    for fps in (0, 1):
+        plan = Plan.from_problem(p, factor_per_system=fps)
+        xi = plan.invert(torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda(), 0.02)
+        out.append(xi.cpu().numpy())
+        if fps == 0:
+            say("odd torus factorized", plan.factorized_systems(), "of", plan.active_systems())
+            assert plan.factorized_systems() < plan.active_systems()
+        plan.close()
+    for x in out:
+        assert rel(x, ref) <= TOL
+    assert rel(out[0], out[1]) <= TOL
