@@ -62,20 +62,22 @@ def _systems(p, f, What_f, Vhat_f, alpha, branch):
     return act, A, w, v, al, branch[act], Minv
 
 
-def vjp(p, W, u0, delta, g_xi, tau=TAU, eta=ETA):
+def vjp(p, W, u0, delta, g_xi, tau=TAU, eta=ETA, weights=None):
     """Cotangents (Wbar, u0bar) of xi = invert(W, u0) for the xi cotangent
-    g_xi (shape of xi; combine = least squares)."""
+    g_xi (shape of xi; combine = least squares, optionally weighted: every
+    frequency's terms carry its weight)."""
     W = np.asarray(W, np.complex128)
-    xi, st = invert(p, W, u0, delta, tau, eta, stages=True)
+    xi, st = invert(p, W, u0, delta, tau, eta, stages=True, weights=weights)
     u, v = st["u"], st["v"]
-    den = np.sum(np.abs(u) ** 2, axis=0)
+    wt = np.ones(p.n_omega) if weights is None else np.asarray(weights, np.float64)
+    den = np.sum(wt[:, None, None, None] * np.abs(u) ** 2, axis=0)
     inv = np.where(den > 0, 1.0 / np.where(den > 0, den, 1.0), 0.0)
     N = p.px * p.py
     Wbar = np.zeros_like(W)
     u0bar = np.zeros_like(u)
     for f in range(p.n_omega):
-        vbar = g_xi * u[f] * inv
-        ubar = (np.conj(g_xi) * (v[f] - xi * u[f]) - g_xi * np.conj(xi) * u[f]) * inv
+        vbar = wt[f] * g_xi * u[f] * inv
+        ubar = wt[f] * (np.conj(g_xi) * (v[f] - xi * u[f]) - g_xi * np.conj(xi) * u[f]) * inv
         u0bar[f] = ubar
         vbar = vbar + _volume_adjoint(p, f, ubar)
         Vbar = np.fft.fft2(model.embed(p, vbar)) / N
@@ -102,12 +104,13 @@ def vjp(p, W, u0, delta, g_xi, tau=TAU, eta=ETA):
     return Wbar, u0bar
 
 
-def jvp(p, W, u0, delta, dW, tau=TAU, eta=ETA):
+def jvp(p, W, u0, delta, dW, tau=TAU, eta=ETA, weights=None):
     """Tangent of xi for a W tangent dW (u0 held fixed)."""
     W = np.asarray(W, np.complex128)
-    xi, st = invert(p, W, u0, delta, tau, eta, stages=True)
+    xi, st = invert(p, W, u0, delta, tau, eta, stages=True, weights=weights)
     u, v = st["u"], st["v"]
-    den = np.sum(np.abs(u) ** 2, axis=0)
+    wt = np.ones(p.n_omega) if weights is None else np.asarray(weights, np.float64)
+    den = np.sum(wt[:, None, None, None] * np.abs(u) ** 2, axis=0)
     inv = np.where(den > 0, 1.0 / np.where(den > 0, den, 1.0), 0.0)
     N = p.px * p.py
     acc = np.zeros_like(xi)
@@ -133,7 +136,8 @@ def jvp(p, W, u0, delta, dW, tau=TAU, eta=ETA):
         dV = dV.T.reshape(p.nz, p.py, p.px)
         dv = model.crop(p, np.fft.ifft2(dV))
         du = model.volume_potential(p, f, dv)
-        acc += np.conj(u[f]) * dv + np.conj(du) * (v[f] - xi * u[f]) - xi * np.conj(u[f]) * du
+        acc += wt[f] * (np.conj(u[f]) * dv + np.conj(du) * (v[f] - xi * u[f])
+                        - xi * np.conj(u[f]) * du)
     return acc * inv
 
 

@@ -9,7 +9,11 @@ Algorithm 2 (Section 4):
   item 3  xi from u xi = V: v/u for one frequency, least squares over the
           frequencies otherwise (Section 5.2, last paragraph):
           xi = sum_f conj(u_f) v_f / sum_f |u_f|^2, xi = 0 where the
-          denominator vanishes.
+          denominator vanishes. Section 5 notes that the frequencies give
+          reconstructions of different accuracy; optional weights w_f >= 0
+          (frequency selection when 0/1) make it the weighted least squares
+          sum_f w_f conj(u_f) v_f / sum_f w_f |u_f|^2, and a frequency of
+          weight 0 is not solved at all.
 
 Shapes: W (n_omega, nd, py, px); u0 (n_omega, nz, ny, nx); xi (nz, ny, nx),
 complex (the physical contrast is its real part).
@@ -125,25 +129,33 @@ def system_noise_level_hat(What_f, delta, N):
 
 
 def invert(p, W, u0, delta, tau=TAU, eta=ETA, combine="lsq", rule="tikhonov",
-           stages=False, kernel_mode=0, damping=0.0):
+           stages=False, kernel_mode=0, damping=0.0, weights=None):
     """W -> xi. With stages=True also returns a dict of per-frequency
     intermediates (What, Vhat, v, u, alpha, branch). kernel_mode / damping
-    select the table of A (model.system_table)."""
+    select the table of A (model.system_table); weights (n_omega,) the
+    weighted least squares of item 3 (combine "lsq" only)."""
     W = np.asarray(W, np.complex128)
     u0 = np.asarray(u0, np.complex128)
     nf = p.n_omega
+    wt = np.ones(nf) if weights is None or combine != "lsq" else np.asarray(weights, np.float64)
     num = np.zeros((p.nz, p.ny, p.nx), np.complex128)
     den = np.zeros((p.nz, p.ny, p.nx), np.float64)
     per_f = []
     keep = {k: [] for k in ("What", "Vhat", "v", "u", "alpha", "branch")}
     for f in range(nf):
         What = np.fft.fft2(W[f])                                  # item 1 input
-        Vhat, alpha, branch = solve_systems(p, f, What, delta, tau, eta, rule,
-                                            kernel_mode=kernel_mode, damping=damping)
+        if wt[f] == 0:
+            # not selected: no solve, v = 0
+            N = p.px * p.py
+            Vhat = np.zeros((p.nz, p.py, p.px), np.complex128)
+            alpha, branch = np.full(N, np.inf), np.zeros(N, np.int8)
+        else:
+            Vhat, alpha, branch = solve_systems(p, f, What, delta, tau, eta, rule,
+                                                kernel_mode=kernel_mode, damping=damping)
         v = model.crop(p, np.fft.ifft2(Vhat))                      # item 2
         u = u0[f] + model.volume_potential(p, f, v)
-        num += np.conj(u) * v                                      # item 3
-        den += np.abs(u) ** 2
+        num += wt[f] * np.conj(u) * v                              # item 3
+        den += wt[f] * np.abs(u) ** 2
         if combine == "per_frequency":
             per_f.append(_divide(np.conj(u) * v, np.abs(u) ** 2))
         if stages:

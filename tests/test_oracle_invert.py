@@ -180,3 +180,58 @@ def test_global_rule_data_inside_the_noise_level_give_zero(small):
     assert not Vg.any() and np.all(br == 0) and np.all(np.isinf(a))
     Vg, a, br = invert.solve_systems(p, 0, What, 0.9, tau=1.0, rule="global", tab=tab, idx=idx)
     assert np.all(br == 2) and Vg.any()
+
+
+# ------------------------------------------------ weighted frequencies
+
+@pytest.fixture(scope="module")
+def two_freq():
+    p = synth.make_problem("w2", 12, 10, 8, [2 * np.pi, 1.5 * 2 * np.pi], 2, (7, 3), (0.02,),
+                           px=24, py=20)
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, _, _, _ = forward.synthesize(p, xi, u0, born=True)
+    return p, synth.add_noise(p, W, 0.02), u0
+
+
+def test_selecting_one_frequency_is_its_quotient(two_freq):
+    # weights (1, 0): the least squares reduces to v_0 / u_0, the first
+    # frequency's per-frequency result, and the second is not solved
+    p, W, u0 = two_freq
+    per = invert.invert(p, W, u0, 0.02, combine="per_frequency")
+    x, st = invert.invert(p, W, u0, 0.02, weights=[1.0, 0.0], stages=True)
+    assert np.linalg.norm(x - per[0]) <= 1e-14 * np.linalg.norm(per[0])
+    assert not st["Vhat"][1].any() and np.all(st["branch"][1] == 0)
+    x2 = invert.invert(p, W, u0, 0.02, weights=[0.0, 3.0])
+    assert np.linalg.norm(x2 - per[1]) <= 1e-14 * np.linalg.norm(per[1])
+
+
+def test_weights_are_scale_free(two_freq):
+    p, W, u0 = two_freq
+    ref = invert.invert(p, W, u0, 0.02)
+    same = invert.invert(p, W, u0, 0.02, weights=[2.5, 2.5])
+    assert np.linalg.norm(same - ref) <= 1e-14 * np.linalg.norm(ref)
+    a = invert.invert(p, W, u0, 0.02, weights=[0.3, 1.7])
+    b = invert.invert(p, W, u0, 0.02, weights=[0.6, 3.4])
+    assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(a)
+    assert np.linalg.norm(a - ref) > 1e-6 * np.linalg.norm(ref)
+
+
+def test_weighted_derivatives_satisfy_the_dot_product_identity(two_freq):
+    from oracle import adjoint
+    p, W, u0 = two_freq
+    g = synth.random_field((p.nz, p.ny, p.nx), (61,))
+    dW = synth.random_field(W.shape, (62,))
+    dW *= np.linalg.norm(W) / np.linalg.norm(dW)
+    wt = [0.3, 1.7]
+    gW, _ = adjoint.vjp(p, W, u0, 0.02, g, weights=wt)
+    jv = adjoint.jvp(p, W, u0, 0.02, dW, weights=wt)
+    lhs = np.real(np.vdot(g, jv))
+    rhs = np.real(np.vdot(gW, dW))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    # and the tangent is the derivative: central differences on the oracle
+    h = 1e-6
+    xp = invert.invert(p, W + h * dW, u0, 0.02, weights=wt)
+    xm = invert.invert(p, W - h * dW, u0, 0.02, weights=wt)
+    fd = (xp - xm) / (2 * h)
+    assert np.linalg.norm(fd - jv) <= 1e-5 * np.linalg.norm(jv)
