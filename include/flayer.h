@@ -207,6 +207,17 @@ typedef struct {
 
 fl_status fl_plan_info(const fl_plan *plan, fl_plan_info_t *info);
 
+/*
+ * Weights of the frequencies in the least-squares xi of item 3 (Section 5
+ * notes that the single-frequency reconstructions differ in accuracy):
+ * xi = sum_f w_f conj(u_f) v_f / sum_f w_f |u_f|^2; a frequency of weight 0
+ * is not solved at all (frequency selection). w: HOST array of n_omega
+ * finite weights >= 0, not all 0, copied; NULL restores all ones. Applies
+ * to combine = 0 and to fl_invert_vjp / fl_invert_jvp; synchronizes the
+ * plan's stream. Errors: FL_EINVAL, FL_EDEVICE.
+ */
+fl_status fl_set_frequency_weights(fl_plan *plan, const double *w);
+
 /* Copy the active-system and factorization counts of the last fl_invert into
  * the info block (synchronizes the plan's stream). */
 fl_status fl_plan_refresh_info(fl_plan *plan);

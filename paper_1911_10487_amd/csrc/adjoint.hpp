@@ -251,19 +251,20 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
 // (d) reversed: vbar_f = g u_f / den, ubar_f = (conj(g)(v_f - xi u_f) - g conj(xi) u_f) / den
 __global__ __launch_bounds__(256) void k_xi_vjp(const z64* __restrict__ g, const z64* __restrict__ xi,
                                                 const z64* __restrict__ u, const z64* __restrict__ v,
-                                                long nvox, int F, z64* __restrict__ vbar,
-                                                z64* __restrict__ ubar) {
+                                                long nvox, int F, const double* __restrict__ fw,
+                                                z64* __restrict__ vbar, z64* __restrict__ ubar) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvox) return;
   double den = 0.0;
-  for (int f = 0; f < F; ++f) den += nrm2(u[(long)f * nvox + i]);
+  for (int f = 0; f < F; ++f) den += (fw ? fw[f] : 1.0) * nrm2(u[(long)f * nvox + i]);
   const double inv = den > 0.0 ? 1.0 / den : 0.0;
   const z64 gg = g[i], x = xi[i];
   for (int f = 0; f < F; ++f) {
+    const double wi = fw ? fw[f] * inv : inv;
     const z64 uu = u[(long)f * nvox + i], vv = v[(long)f * nvox + i];
-    vbar[(long)f * nvox + i] = inv * (gg * uu);
+    vbar[(long)f * nvox + i] = wi * (gg * uu);
     const z64 t = cj(gg) * (vv - x * uu) - gg * (cj(x) * uu);
-    ubar[(long)f * nvox + i] = inv * t;
+    ubar[(long)f * nvox + i] = wi * t;
   }
 }
 
@@ -271,6 +272,7 @@ __global__ __launch_bounds__(256) void k_xi_vjp(const z64* __restrict__ g, const
 __global__ __launch_bounds__(256) void k_xi_jvp(const z64* __restrict__ xi, const z64* __restrict__ u,
                                                 const z64* __restrict__ v, const z64* __restrict__ vd,
                                                 const z64* __restrict__ ud, long nvox, int F,
+                                                const double* __restrict__ fw,
                                                 z64* __restrict__ out) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvox) return;
@@ -280,8 +282,13 @@ __global__ __launch_bounds__(256) void k_xi_jvp(const z64* __restrict__ xi, cons
   for (int f = 0; f < F; ++f) {
     const long o = (long)f * nvox + i;
     const z64 uu = u[o], vv = v[o], dv = vd[o], du = ud[o];
-    den += nrm2(uu);
-    acc = acc + cmulc(uu, dv) + cmulc(du, vv - x * uu) - x * cmulc(uu, du);
+    if (fw) {
+      den += fw[f] * nrm2(uu);
+      acc = acc + fw[f] * (cmulc(uu, dv) + cmulc(du, vv - x * uu) - x * cmulc(uu, du));
+    } else {
+      den += nrm2(uu);
+      acc = acc + cmulc(uu, dv) + cmulc(du, vv - x * uu) - x * cmulc(uu, du);
+    }
   }
   out[i] = den > 0.0 ? (1.0 / den) * acc : mk(0.0, 0.0);
 }

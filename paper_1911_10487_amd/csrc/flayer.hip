@@ -83,6 +83,10 @@ struct fl_plan {
   z64 *vX = nullptr, *u = nullptr, *u0w = nullptr;
   double *wn2 = nullptr, *partial = nullptr, *thr2 = nullptr, *norm2 = nullptr;
   double* rowsq = nullptr;  // per row of W: sum of squares (stage (a) rows)
+  // weights of the frequencies in the least-squares xi (fl_set_frequency_weights)
+  double* fw = nullptr;
+  std::vector<double> fw_host;
+  bool fw_on = false;
   int *flag = nullptr, *cnt = nullptr, *list = nullptr, *count = nullptr;
   int nb_scan = 0;
   // solver chunk
@@ -442,6 +446,12 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
   return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
 }
 
+// The frequency weights of the least-squares xi, or NULL when they are all
+// one (or xi is per frequency).
+const double* freq_weights(const fl_plan* p) {
+  return (p->fw_on && p->opts.combine == 0) ? p->fw : nullptr;
+}
+
 // Classification (with v^ = 0 written for the systems without a solve) and,
 // unless the systems are grouped by orbit afterwards, their compaction.
 template <typename T>
@@ -450,8 +460,8 @@ fl_status solve_prepare(fl_plan* p, bool compact) {
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
   hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const z64*)p->What,
-                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), p->wn2, p->flag,
-                     p->Vh, (int)(sizeof(T) == 4), p->nz);
+                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), freq_weights(p),
+                     p->wn2, p->flag, p->Vh, (int)(sizeof(T) == 4), p->nz);
   LAUNCHCHK();
   if (!compact) return FL_OK;
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
@@ -875,7 +885,7 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
   // (d) xi, in FP64
   RUN(mark(p, FL_STAGE_XI));
   hipLaunchKernelGGL(k_xi, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->u, p->vX, nvox, F,
-                     p->opts.combine, (z64*)xi_out);
+                     p->opts.combine, freq_weights(p), (z64*)xi_out);
   LAUNCHCHK();
   RUN(mark(p, -1));
   return FL_OK;
@@ -963,7 +973,7 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const Tw<T> tw = twiddles_of<T>(p);
   // (d) reversed
   hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, p->xi_tmp, p->u, p->vX,
-                     nvox, F, p->vbar, p->ubar);
+                     nvox, F, freq_weights(p), p->vbar, p->ubar);
   LAUNCHCHK();
   // (c) reversed: vbar2 = vbar + K^H ubar, then V^bar = FFT2(pad(vbar2)) / N
   {
@@ -1061,7 +1071,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   // v' and u' = K v' (no incident term), then xi'
   RUN(stage_c<T>(p, p->Yb, p->vbar, p->ubar, nullptr));
   hipLaunchKernelGGL(k_xi_jvp, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->xi_tmp, p->u, p->vX,
-                     p->vbar, p->ubar, nvox, F, dxi);
+                     p->vbar, p->ubar, nvox, F, freq_weights(p), dxi);
   LAUNCHCHK();
   return FL_OK;
 }
@@ -1460,6 +1470,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->list, FN);
   PALLOC(p->count, 1);
   PALLOC(p->partial, F * 256);
+  PALLOC(p->fw, F);
   PALLOC(p->rowsq, (long)F * nd * py);
   PALLOC(p->thr2, F);
   PALLOC(p->norm2, F);
@@ -1563,6 +1574,11 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (o.prefactor) {
     s = prefactor(p, reps);
     if (s != FL_OK) return bail(s);
+  }
+  p->fw_host.assign(F, 1.0);
+  {
+    hipError_t e = hipMemcpy(p->fw, p->fw_host.data(), F * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail(FL_EDEVICE, "weights: %s", hipGetErrorString(e)));
   }
   *out = p;
   return FL_OK;
@@ -1737,6 +1753,28 @@ fl_status fl_plan_info(const fl_plan* p, fl_plan_info_t* info) {
   info->device_bytes = p->bytes;
   info->last_active = p->last_active;
   info->last_factorized = p->last_factorized;
+  return FL_OK;
+}
+
+fl_status fl_set_frequency_weights(fl_plan* p, const double* w) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  std::vector<double> v(p->F, 1.0);
+  if (w) {
+    bool any = false;
+    for (int f = 0; f < p->F; ++f) {
+      if (!(w[f] >= 0.0) || !std::isfinite(w[f]))
+        return fail(FL_EINVAL, "weight %d must be finite and >= 0", f);
+      any = any || w[f] > 0.0;
+      v[f] = w[f];
+    }
+    if (!any) return fail(FL_EINVAL, "at least one frequency weight must be positive");
+  }
+  // the previous inversion may still read the weights: wait for it
+  HIPCHK(hipStreamSynchronize(p->st));
+  p->fw_host = v;
+  HIPCHK(hipMemcpy(p->fw, p->fw_host.data(), p->F * sizeof(double), hipMemcpyHostToDevice));
+  p->fw_on = false;
+  for (double x : v) p->fw_on = p->fw_on || x != 1.0;
   return FL_OK;
 }
 

@@ -206,9 +206,12 @@ __global__ __launch_bounds__(256) void k_widen(const cx<TI>* __restrict__ in, z6
 }
 
 // item 3: xi = sum_f conj(u_f) v_f / sum_f |u_f|^2 (0 where the denominator
-// vanishes); per_f != 0 writes one quotient per frequency instead.
+// vanishes), with the frequency weights fw as factors of both sums when fw
+// is given; per_f != 0 writes one quotient per frequency instead.
 __global__ __launch_bounds__(256) void k_xi(const z64* __restrict__ u, const z64* __restrict__ v,
-                                            long nvox, int F, int per_f, z64* __restrict__ xi) {
+                                            long nvox, int F, int per_f,
+                                            const double* __restrict__ fw,
+                                            z64* __restrict__ xi) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvox) return;
   if (per_f) {
@@ -220,12 +223,20 @@ __global__ __launch_bounds__(256) void k_xi(const z64* __restrict__ u, const z64
     }
     return;
   }
+  // weighted least squares when fw is given (weights of the frequencies)
   z64 num = mk(0.0, 0.0);
   double den = 0.0;
   for (int f = 0; f < F; ++f) {
     z64 uu = u[(long)f * nvox + i], vv = v[(long)f * nvox + i];
-    num = cfmac(num, uu, vv);
-    den += nrm2(uu);
+    if (fw) {
+      // w_f conj(u) v = conj(w_f u) v
+      const double w = fw[f];
+      num = cfmac(num, w * uu, vv);
+      den += w * nrm2(uu);
+    } else {
+      num = cfmac(num, uu, vv);
+      den += nrm2(uu);
+    }
   }
   xi[i] = den > 0.0 ? mk(num.x / den, num.y / den) : mk(0.0, 0.0);
 }

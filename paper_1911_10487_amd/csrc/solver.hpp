@@ -30,7 +30,8 @@ namespace fl {
 template <typename T>
 __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What, int nd, long N,
                                                   int F, const double* __restrict__ thr2,
-                                                  int solve_all, double* __restrict__ wn2,
+                                                  int solve_all, const double* __restrict__ fw,
+                                                  double* __restrict__ wn2,
                                                   int* __restrict__ flag, void* __restrict__ Vh,
                                                   int vh_single, int nz) {
   long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,7 +59,8 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   // thr2[f] < 0 marks noise-free data, solve_all the rule with one alpha per
   // frequency: then every nonzero system is solved
   double t = thr2[f];
-  const int act = (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
+  // a frequency of weight 0 in the least-squares xi is not solved
+  const int act = (fw && fw[f] == 0.0) ? 0 : (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
   flag[fm] = act;
   // v^ = 0 for a system without a solve (the solver writes the others)
   if (!act) {

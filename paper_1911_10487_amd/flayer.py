@@ -112,6 +112,8 @@ def lib():
     L.fl_batch_destroy.restype = None
     L.fl_plan_destroy.argtypes = [P]
     L.fl_plan_destroy.restype = None
+    L.fl_set_frequency_weights.argtypes = [P, ctypes.POINTER(D)]
+    L.fl_set_frequency_weights.restype = I
     TP = ctypes.POINTER(FlTuning)
     L.fl_tuning_get.argtypes = [P, TP]
     L.fl_tuning_get.restype = I
@@ -186,6 +188,18 @@ class Plan:
     def active_systems(self) -> int:
         _check(lib().fl_plan_refresh_info(self._h))
         return self.info().last_active
+
+    def set_frequency_weights(self, weights=None):
+        """Weights of the frequencies in the least-squares xi (None: all
+        ones); a weight of 0 drops that frequency's solve."""
+        if weights is None:
+            _check(lib().fl_set_frequency_weights(self._h, None))
+            return
+        w = np.ascontiguousarray(weights, np.float64)
+        if w.shape != (self.n_omega,):
+            raise ValueError(f"need {self.n_omega} weights")
+        _check(lib().fl_set_frequency_weights(
+            self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def factorized_systems(self) -> int:
         """Matrices factorized by the last invert (active symmetry orbits

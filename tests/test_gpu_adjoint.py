@@ -168,3 +168,22 @@ def test_chunked_factorization_matches_resident(case, precision):
     assert n_act > 2 * 37, n_act
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_weighted_derivatives_match_oracle(case):
+    import torch
+    p, W, u0, d = case
+    g = synth.random_field((p.nz, p.ny, p.nx), (47,))
+    dW = synth.random_field(W.shape, (48,))
+    wt = [0.3, 1.7]
+    plan = _plan(p)
+    plan.set_frequency_weights(wt)
+    Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    gW, _ = plan.vjp(Wt, ut, d, torch.from_numpy(g).cuda())
+    jv = plan.jvp(Wt, ut, d, torch.from_numpy(dW).cuda())
+    gW, jv = gW.cpu().numpy(), jv.cpu().numpy()
+    plan.close()
+    rW, _ = adjoint.vjp(p, W, u0, d, g, weights=wt)
+    rj = adjoint.jvp(p, W, u0, d, dW, weights=wt)
+    say("weighted vjp", rel(gW, rW), "jvp", rel(jv, rj))
+    assert rel(gW, rW) <= TOL and rel(jv, rj) <= TOL

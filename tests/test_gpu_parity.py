@@ -493,3 +493,27 @@ def test_odd_square_torus_orbits_match_oracle():
     for x in out:
         assert rel(x, ref) <= TOL
     assert rel(out[0], out[1]) <= TOL
+
+
+def test_frequency_weights_match_oracle():
+    """fl_set_frequency_weights: the weighted least squares of item 3, a
+    weight of 0 dropping that frequency's solve, against the oracle; then
+    back to all ones; invalid weights are refused."""
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import FlError, FL_EINVAL, Plan
+    p, u0, W = _ragged()
+    Wd = synth.add_noise(p, W, 0.02)
+    plan = Plan.from_problem(p)
+    Wt, ut = torch.from_numpy(Wd).cuda(), torch.from_numpy(u0).cuda()
+    for wt in ([1.0, 0.0], [0.3, 1.7], None):
+        plan.set_frequency_weights(wt)
+        xi = plan.invert(Wt, ut, 0.02).cpu().numpy()
+        ref, st = invert.invert(p, Wd, u0, 0.02, weights=wt, stages=True)
+        say("weights", wt, rel(xi, ref))
+        assert rel(xi, ref) <= TOL
+        assert plan.active_systems() == int(np.count_nonzero(st["branch"]))
+    for bad in ([0.0, 0.0], [1.0, -1.0], [1.0, float("nan")]):
+        with pytest.raises(FlError) as e:
+            plan.set_frequency_weights(bad)
+        assert e.value.status == FL_EINVAL
+    plan.close()
