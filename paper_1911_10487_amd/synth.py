@@ -95,6 +95,17 @@ def make_problem(name: str, nx: int, ny: int, nz: int, omegas, n_blobs: int,
     )
 
 
+def thin_problem(name: str, nx: int, ny: int, nz: int, omegas, n_blobs: int, seed: tuple,
+                 deltas=(0.01,), gap: float = 0.5, spacing: float = 0.01, nd: int = 2,
+                 h: float = H, px: int | None = None, py: int | None = None) -> Problem:
+    """Data in a thin layer (the paper's second experiment): nd planes
+    `spacing` apart, the first `gap` above the top of X; the spacing need
+    not be a multiple of h."""
+    p = make_problem(name, nx, ny, nz, omegas, n_blobs, seed, deltas, h=h, nd=nd, px=px, py=py)
+    p.planes = nz * h + gap + spacing * np.arange(nd)
+    return p
+
+
 def workload(name: str) -> list[Problem]:
     """The named workload as a list of instances (one except ``uneven``)."""
     if name == "small":

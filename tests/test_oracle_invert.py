@@ -235,3 +235,32 @@ def test_weighted_derivatives_satisfy_the_dot_product_identity(two_freq):
     xm = invert.invert(p, W - h * dW, u0, 0.02, weights=wt)
     fd = (xp - xm) / (2 * h)
     assert np.linalg.norm(fd - jv) <= 1e-5 * np.linalg.norm(jv)
+
+
+def test_thin_layer_solutions_are_minimum_norm_and_meet_the_discrepancy():
+    # nd = 2 planes, nz = 8: wide systems. Every solved v^_m lies in the row
+    # space of A_m (minimum norm) and a root system's residual is tau delta_m
+    p = synth.thin_problem("thin", 6, 5, 8, [2 * np.pi], 2, (4, 4), gap=0.3, spacing=0.01,
+                           px=12, py=10)
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, _, _, _ = forward.synthesize(p, xi, u0, born=True)
+    Wd = synth.add_noise(p, W, 0.01)
+    x, st = invert.invert(p, Wd, u0, 0.01, stages=True)
+    assert np.isfinite(x).all()
+    N = p.px * p.py
+    tab, idx = model.system_table(p, 0)
+    A = model.system_matrices(p, 0, tab, idx, np.arange(N))
+    V = st["Vhat"][0].reshape(p.nz, N).T
+    w = st["What"][0].reshape(p.nd, N).T
+    dm = invert.system_noise_level_hat(st["What"][0], 0.01, N)
+    br = st["branch"][0]
+    assert (br == 2).any()
+    for m in np.nonzero(br)[0]:
+        # component of v in null(A): v - A^H (A A^H)^-1 A v
+        Am = A[m]
+        proj = Am.conj().T @ np.linalg.solve(Am @ Am.conj().T, Am @ V[m])
+        assert np.linalg.norm(V[m] - proj) <= 1e-8 * np.linalg.norm(V[m])
+        if br[m] == 2:
+            r = np.linalg.norm(Am @ V[m] - w[m])
+            assert abs(r / (1.5 * dm) - 1.0) <= 1e-9

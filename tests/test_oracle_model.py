@@ -220,3 +220,15 @@ def test_table_is_invariant_under_the_torus_symmetries(px, py):
         assert np.abs(tab.transpose(0, 2, 1) - tab).max() <= 1e-13 * scale
     # and the symmetry is not vacuous: G^ does vary across the wavenumbers
     assert np.abs(tab - tab[:, :1, :1]).max() > 0.1 * scale
+
+
+def test_thin_layer_data_operator_matches_direct_sum():
+    # two data planes 0.01 apart, off X's z-lattice: nd * nz distinct heights
+    p = synth.thin_problem("thin", 3, 2, 2, [2 * np.pi], 1, (0, 0), gap=0.3, spacing=0.01,
+                           px=8, py=6)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 3))
+    W = model.data_operator(p, 0, vX)
+    Wb = _brute_data(p, 0, vX)
+    assert np.linalg.norm(W - Wb) <= 1e-13 * np.linalg.norm(Wb)
+    tab, idx = model.system_table(p, 0)
+    assert tab.shape[0] == p.nd * p.nz
