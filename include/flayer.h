@@ -21,10 +21,12 @@
  * ---------------------------------------
  * Geometry: X is the box [0, nx h] x [0, ny h] x [0, nz h] sampled at cell
  *   centres ((i + 1/2) h). The data planes z_j (j < nd) lie outside
- *   [0, nz h] and are spaced exactly h apart (z_j = z_0 + j h), so that
- *   z_j - z'_l depends on j - l only and every A_m is Toeplitz. The
- *   horizontal plane is a px x py torus (default 2 nx x 2 ny); X's window
- *   sits at offset ((px - nx) / 2, (py - ny) / 2) of it.
+ *   [0, nz h], all on one side. Either nd = nz and they are spaced exactly h
+ *   apart (z_j = z_0 + j h: z_j - z'_l depends on j - l only and every A_m
+ *   is Toeplitz), or nd <= 4 planes at any heights form a thin data
+ *   layer (Section 5, second experiment; nd <= nz, every A_m is wide,
+ *   nz <= 128). The horizontal plane is a px x py torus (default
+ *   2 nx x 2 ny); X's window sits at offset ((px - nx) / 2, (py - ny) / 2).
  * Arrays: complex values are interleaved (re, im), C order, contiguous.
  *   W       [n_omega][nd][py][px]   data on the torus of every data plane
  *   u0      [n_omega][nz][ny][nx]   incident field in X
@@ -123,19 +125,21 @@ void fl_opts_default(fl_opts *opts);
 
 /*
  * Build a plan: validate the geometry, build the per-frequency tables
- * (the FFT of G sampled on the torus at every height difference, Section 5:
- * "calculated ... from the known values ... using the FFT"; and the 3D FFT of
- * the in-X volume kernel with the self-cell integral of G over the ball of
- * volume h^3), and allocate workspaces.
- *   nx, ny, nz   X grid (>= 1); nd data planes (must equal nz in this build)
+ * (the FFT of G sampled on the torus at every height difference: Section 5
+ * obtains the discrete transform of G from its sampled values by the FFT;
+ * and the 3D FFT of the in-X volume kernel with the self-cell integral of G
+ * over the ball of volume h^3), and allocate workspaces.
+ *   nx, ny, nz   X grid (>= 1); nd data planes (nd = nz on X's lattice, or
+ *                a thin layer of nd <= min(4, nz) planes at any heights)
  *   h            cell size (> 0); planes: nd heights (host); omegas: n_omega
  *                angular frequencies (host, > 0); c0 > 0 background speed
  *   opts         NULL => defaults
  *   out          receives the plan (library-owned; free with fl_plan_destroy)
- * Errors: FL_EINVAL (sizes, planes inside X or off the h lattice, torus too
- * small, omega or c0 or h not positive), FL_EUNSUPPORTED (nd != nz, torus
- * sizes with prime factors other than 2, 3, 5, or above 1024), FL_ENOMEM,
- * FL_EDEVICE.
+ * Errors: FL_EINVAL (sizes, planes inside X, straddling X, or more than 4
+ * planes off the h lattice, torus too small, omega or c0 or h not positive),
+ * FL_EUNSUPPORTED (nd != nz beyond a thin layer, torus sizes with prime
+ * factors other than 2, 3, 5, or above 1024; a thin layer with alpha_rule 1,
+ * prefactor, derivatives or fl_plan_tune), FL_ENOMEM, FL_EDEVICE.
  */
 fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h,
                          const double *planes, const double *omegas, double c0,

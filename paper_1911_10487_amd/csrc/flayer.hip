@@ -113,6 +113,10 @@ struct fl_plan {
   // offsets), and the left reflectors
   bool orbits = false;
   int n_orb = 0;
+  // thin data layer (nd <= THIN_ND planes at any heights): zt [nd][nz] the
+  // height differences of the table planes
+  bool thin = false;
+  double* zt = nullptr;
   int *orep = nullptr, *omem = nullptr, *oflag = nullptr, *olist = nullptr, *ocount = nullptr,
       *oslot = nullptr, *ocnt = nullptr, *olist_sys = nullptr;
   z64* refl_l = nullptr;
@@ -298,12 +302,12 @@ fl_status build_tables(fl_plan* p) {
     if (p->opts.kernel_mode == 1) {
       // closed-form transform of G at the torus wavenumbers, times omega^2 h
       hipLaunchKernelGGL(k_gclosed, dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt, p->nzeta,
-                         p->px, p->py, p->h, zeta0, k0, p->opts.damping, om * om * p->h);
+                         p->px, p->py, p->h, zeta0, p->zt, k0, p->opts.damping, om * om * p->h);
       LAUNCHCHK();
     } else {
       // sampled omega^2 h^3 G on every height plane, then FFT2 -> A's entries
       hipLaunchKernelGGL((k_gplanes<double>), dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt,
-                         p->nzeta, p->px, p->py, p->h, zeta0, k0, om * om * p->h * p->h * p->h);
+                         p->nzeta, p->px, p->py, p->h, zeta0, p->zt, k0, om * om * p->h * p->h * p->h);
       LAUNCHCHK();
       RUN((run_fft<double, double, double, -1>(
           rows_args(gt, gt, p->tw_x, p->px, (long)p->nzeta * p->py), p->st)));
@@ -683,6 +687,34 @@ fl_status prefactor(fl_plan* p, const std::vector<int>& reps) {
   return FL_OK;
 }
 
+// The thin-layer solves of the compacted systems, one wave each.
+template <typename T>
+fl_status run_thin(fl_plan* p) {
+  ThinArgs a{};
+  a.gsys = p->gsys;
+  a.tpitch = p->TP;
+  a.What = (const z64*)p->What;
+  a.list = p->list;
+  a.count = p->count;
+  a.nd = p->nd;
+  a.nz = p->nz;
+  a.N = p->N;
+  a.thr2 = p->thr2;
+  a.eta = p->opts.eta;
+  a.Vh = p->Vh;
+  a.vh_single = sizeof(T) == 4;
+  a.alpha = p->alpha;
+  a.branch = p->branch;
+  const unsigned g = (unsigned)std::min<long>((long)p->F * p->N, 16384);
+  RUN(mark(p, FL_STAGE_DP));
+  if (p->nz <= 64)
+    hipLaunchKernelGGL(k_thin_solve<64>, dim3(g), dim3(64), 0, p->st, a);
+  else
+    hipLaunchKernelGGL(k_thin_solve<128>, dim3(g), dim3(64), 0, p->st, a);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
 // shared: allow one factorization per orbit (the derivative calls need the
 // per-system factorizations and pass false)
 template <typename T>
@@ -690,6 +722,7 @@ fl_status solve_systems(fl_plan* p, bool shared = true) {
   const long FN = (long)p->F * p->N;
   p->last_shared = p->opts.alpha_rule == 0 && shared && p->orbits;
   RUN(solve_prepare<T>(p, !p->last_shared));
+  if (p->thin) return run_thin<T>(p);
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
   if (p->last_shared && p->prefactored) {
     RUN(group_by_orbit(p));
@@ -915,6 +948,7 @@ fl_status adjoint_preconditions(fl_plan* p) {
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the least-squares xi (combine 0)");
   if (p->opts.alpha_rule != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the per-system alpha (alpha_rule 0)");
+  if (p->thin) return fail(FL_EUNSUPPORTED, "derivatives are not implemented for a thin data layer");
   return ensure_adjoint_buffers(p);
 }
 
@@ -1353,21 +1387,33 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (px < 2 * nx - 1 || py < 2 * ny - 1)
     return fail(FL_EINVAL, "torus %dx%d too small for window %dx%d (need >= 2n-1)", px, py, nx, ny);
   const double top = nz * h;
+  bool lattice = true, above = false, below = false;
   for (int j = 0; j < nd; ++j) {
     if (!std::isfinite(planes[j])) return fail(FL_EINVAL, "planes[%d] not finite", j);
     if (planes[j] >= 0.0 && planes[j] <= top)
       return fail(FL_EINVAL, "data plane %d at z=%g lies inside X = [0, %g]", j, planes[j], top);
-    if (std::fabs(planes[j] - (planes[0] + j * h)) > 1e-9 * h)
-      return fail(FL_EINVAL, "data planes must be spaced h apart (plane %d)", j);
+    lattice = lattice && std::fabs(planes[j] - (planes[0] + j * h)) <= 1e-9 * h;
+    above = above || planes[j] > top;
+    below = below || planes[j] < 0.0;
   }
-  if (planes[0] < 0.0 && planes[nd - 1] > 0.0)
-    return fail(FL_EINVAL, "data planes straddle X");
-  if (nd != nz) return fail(FL_EUNSUPPORTED, "nd (%d) != nz (%d) is not supported", nd, nz);
+  if (above && below) return fail(FL_EINVAL, "data planes straddle X");
+  // a thin data layer: a few planes at any heights (wide systems)
+  const bool thin = nd <= THIN_ND && !(lattice && nd == nz);
+  if (!thin) {
+    if (!lattice) return fail(FL_EINVAL, "data planes must be spaced h apart (nd > %d)", THIN_ND);
+    if (nd != nz)
+      return fail(FL_EUNSUPPORTED, "nd (%d) != nz (%d) needs nd <= %d (thin layer)", nd, nz,
+                  THIN_ND);
+  } else if (nd > nz) {
+    return fail(FL_EUNSUPPORTED, "thin layer: nd (%d) > nz (%d) is not supported", nd, nz);
+  }
   if (!smooth235(px) || !smooth235(py) || !smooth235(2 * nz) || px > 1024 || py > 1024 ||
       2 * nz > 1024)
     return fail(FL_EUNSUPPORTED, "FFT sizes %d, %d, %d need factors 2, 3, 5 only and <= 1024", px,
                 py, 2 * nz);
-  if (!(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
+  if (thin && nz > 128) return fail(FL_EUNSUPPORTED, "thin layer: nz = %d > 128", nz);
+  if (!thin &&
+      !(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
     return fail(FL_EUNSUPPORTED, "nz = %d: this build solves nz in {16,32,48,64,80,96,128}", nz);
   if (o.precision != 0 && o.precision != 1) return fail(FL_EUNSUPPORTED, "precision must be 0 or 1");
   if (o.kernel_mode != 0 && o.kernel_mode != 1) return fail(FL_EINVAL, "kernel_mode must be 0 or 1");
@@ -1399,6 +1445,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (o.prefactor && (o.factor_per_system || o.alpha_rule))
     return fail(FL_EUNSUPPORTED, "prefactor needs shared factorizations (factor_per_system 0, "
                                  "alpha_rule 0)");
+  if (thin && (o.alpha_rule || o.prefactor))
+    return fail(FL_EUNSUPPORTED, "thin layer: alpha_rule 1 and prefactor are not supported");
 
   fl_plan* p = new fl_plan();
   p->nx = nx;
@@ -1417,11 +1465,12 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   p->opts.py = py;
   p->st = (hipStream_t)o.stream;
   p->N = (long)px * py;
-  p->nzeta = nd + nz - 1;
-  p->TP = 2 * nz;
+  p->thin = thin;
+  p->nzeta = thin ? nd * nz : nd + nz - 1;
+  p->TP = thin ? nd * nz : 2 * nz;
   p->ox = (px - nx) / 2;
   p->oy = (py - ny) / 2;
-  p->n = nz;
+  p->n = thin ? nd : nz;
   p->prec = o.precision;
   auto bail = [&](fl_status s) {
     fl_plan_destroy(p);
@@ -1446,6 +1495,15 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     }
   }
   PALLOC(p->gtab, F * p->nzeta * N);
+  if (thin) {
+    // height differences z_j - z'_l, index j nz + l
+    std::vector<double> zt((size_t)nd * nz);
+    for (int j = 0; j < nd; ++j)
+      for (int l = 0; l < nz; ++l) zt[(size_t)j * nz + l] = planes[j] - (l + 0.5) * h;
+    PALLOC(p->zt, nd * nz);
+    hipError_t e = hipMemcpy(p->zt, zt.data(), zt.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(fail(FL_EDEVICE, "heights: %s", hipGetErrorString(e)));
+  }
   PALLOC(p->gsys, FN * p->TP);
   PALLOC(p->ktab, F * 2 * nz * N);
   const long big = F * std::max(nd, nz) * N;
@@ -1478,7 +1536,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   // 128^2 x 64 grids run as one chunk even with five frequencies
   long cap = std::max<long>(1024, (24L << 30) / ((long)nz * nz * (long)sizeof(z64)));
   if (o.max_chunk > 0) cap = std::min<long>(cap, o.max_chunk);
-  p->C = (int)std::min<long>(FN, cap);
+  p->C = thin ? 1 : (int)std::min<long>(FN, cap);  // the thin solver needs no workspace
   const long C = p->C;
   PALLOC(p->dg, C * nz);
   PALLOC(p->sp, C * nz);
@@ -1834,6 +1892,7 @@ fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, 
   if (!p) return fail(FL_EINVAL, "NULL plan");
   if (!W || !u0 || !xi_scratch) return fail(FL_EINVAL, "NULL array argument");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  if (p->thin) return fail(FL_EUNSUPPORTED, "a thin data layer has no solver schedule to tune");
   if (reps < 1) reps = 1;
   fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid, p->dp_spw};
   RUN(fl_invert(p, W, u0, delta, xi_scratch));
@@ -1923,7 +1982,7 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
   RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));
   hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
-                     w1, nd, nz, N, F, w2);
+                     w1, nd, nz, N, F, (int)p->thin, w2);
   LAUNCHCHK();
   FftArgs c = cols_args(w2, w2, p->tw_y, py, px, F * nd);
   RUN((run_fft<double, double, double, 1>(c, st)));

@@ -11,7 +11,8 @@ __device__ __forceinline__ int min_image(int p, int P) { return p <= P / 2 ? p :
 // with minimum-image horizontal offsets. zeta_d = zeta0 + d h.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nzeta, int px, int py,
-                                                 double h, double zeta0, double k0, double wgt) {
+                                                 double h, double zeta0, const double* __restrict__ zt,
+                                                 double k0, double wgt) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long N = (long)px * py;
   if (idx >= N * nzeta) return;
@@ -19,7 +20,8 @@ __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nz
   long p = idx - (long)d * N;
   int iy = (int)(p / px), ix = (int)(p - (long)iy * px);
   double dx = h * min_image(ix, px), dy = h * min_image(iy, py);
-  double z = zeta0 + d * h;
+  // height difference d: zeta0 + d h on X's lattice, else from the list zt
+  double z = zt ? zt[d] : zeta0 + d * h;
   double r = sqrt(dx * dx + dy * dy + z * z);
   double s, c;
   sincos(k0 * r, &s, &c);
@@ -33,8 +35,9 @@ __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nz
 // signed DFT index m (the continuous 2D transform of G at the torus
 // wavenumbers).
 __global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzeta, int px, int py,
-                                                 double h, double zeta0, double k0, double damping,
-                                                 double wgt) {
+                                                 double h, double zeta0,
+                                                 const double* __restrict__ zt, double k0,
+                                                 double damping, double wgt) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long N = (long)px * py;
   if (idx >= N * nzeta) return;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzet
     sr = -sr;
     si = -si;
   }
-  const double z = fabs(zeta0 + d * h);
+  const double z = fabs(zt ? zt[d] : zeta0 + d * h);
   double sn, cs;
   sincos(sr * z, &sn, &cs);
   const double ex = exp(-si * z);
@@ -265,18 +268,21 @@ __global__ __launch_bounds__(256) void k_current(const double* __restrict__ xi,
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_systems(const cx<T>* __restrict__ gtab,
                                                        const cx<T>* __restrict__ Vh, int nd, int nz,
-                                                       long N, int F, cx<T>* __restrict__ Wh) {
+                                                       long N, int F, int thin,
+                                                       cx<T>* __restrict__ Wh) {
   long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (fm >= (long)F * N) return;
   int f = (int)(fm / N);
   long m = fm - (long)f * N;
-  const int nzeta = nd + nz - 1;
+  // table index of (j, l): j - l + nz - 1 on X's lattice, j nz + l otherwise
+  const int nzeta = thin ? nd * nz : nd + nz - 1;
+  const int sj = thin ? nz : 1, sl = thin ? 1 : -1, d0 = thin ? 0 : nz - 1;
   const cx<T>* g = gtab + (long)f * nzeta * N + m;
   const cx<T>* v = Vh + (long)f * nz * N + m;
   for (int j = 0; j < nd; ++j) {
     z64 acc = mk(0.0, 0.0);
     for (int l = 0; l < nz; ++l)
-      acc = cfma(acc, cast<double>(g[(long)(j - l + nz - 1) * N]), cast<double>(v[(long)l * N]));
+      acc = cfma(acc, cast<double>(g[(long)(j * sj + l * sl + d0) * N]), cast<double>(v[(long)l * N]));
     Wh[((long)f * nd + j) * N + m] = cast<T>(acc);
   }
 }

@@ -1372,4 +1372,244 @@ __global__ __launch_bounds__(64) void k_global_update(GState* __restrict__ S,
   if (lane == 0) S[f] = g;
 }
 
+// ------------------------------------------------------- thin data layer
+
+// Data in a thin layer: nd <= THIN_ND planes at any heights, nd <= nz, so
+// every A_m is wide (nd x nz). With the Householder QR A^T = Q [R; 0]
+// (lanes over the nz rows of A^T), A = R^T Q^T restricted to Q's first nd
+// columns, and the minimum-norm Tikhonov solution is v = conj(Q [conj(y); 0])
+// with y the Tikhonov solution of the nd x nd system R^T y = w. y comes from
+// the one-sided Jacobi SVD of R^T, alpha from the discrepancy principle by
+// 64-point multisection on log(alpha) down to a relative bracket of 1e-15
+// (the misfit costs O(nd) per trial). One wave per active system; the small
+// dense steps run redundantly on every lane.
+constexpr int THIN_ND = 4;
+
+struct ThinArgs {
+  const z64* gsys;       // per system, row-major A [nd][nz] (pitch tpitch)
+  int tpitch;
+  const z64* What;       // [F][nd][N]
+  const int* list;
+  const int* count;
+  int nd, nz;
+  long N;
+  const double* thr2;    // [F] (tau delta_m)^2, < 0 for noise-free data
+  double eta;
+  void* Vh;
+  int vh_single;
+  double* alpha;
+  signed char* branch;
+};
+
+__device__ __forceinline__ z64 thin_phase(z64 a) {
+  const double r = sqrt(nrm2(a));
+  return r > 0.0 ? mk(a.x / r, a.y / r) : mk(1.0, 0.0);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_thin_solve(ThinArgs a) {
+  __shared__ z64 sb[THIN_ND][NMAX];  // rows of A (columns of A^T), then reflectors
+  __shared__ double sg[THIN_ND];
+  __shared__ z64 sr[THIN_ND][THIN_ND];
+  __shared__ z64 sw[THIN_ND];
+  const int lane = threadIdx.x, nd = a.nd, nz = a.nz;
+  const int total = *a.count;
+  for (int gs = blockIdx.x; gs < total; gs += gridDim.x) {
+    const int fm = a.list[gs];
+    const int f = (int)(fm / a.N);
+    const long m = fm - (long)f * a.N;
+    const z64* row = a.gsys + (long)fm * a.tpitch;
+    double fr = 0.0;
+    for (int j = 0; j < nd; ++j)
+      for (int l = lane; l < nz; l += 64) {
+        const z64 v = row[j * nz + l];
+        sb[j][l] = v;
+        fr += nrm2(v);
+      }
+    fr = lanes_sum<64>(fr);
+    if (lane < nd) sw[lane] = a.What[((long)f * nd + lane) * a.N + m];
+    __syncthreads();
+    // Householder QR of A^T, column by column
+    for (int j = 0; j < nd; ++j) {
+      double s = 0.0;
+      for (int l = lane; l < nz; l += 64)
+        if (l >= j) s += nrm2(sb[j][l]);
+      s = lanes_sum<64>(s);
+      const z64 piv = sb[j][j];
+      const double xn = sqrt(s), a2 = sqrt(nrm2(piv));
+      const z64 ph = thin_phase(piv);
+      const z64 beta = mk(-ph.x * xn, -ph.y * xn);
+      const double g = xn > 0.0 ? 1.0 / (xn * (xn + a2)) : 0.0;
+      __syncthreads();
+      if (lane == 0) {
+        sb[j][j] = piv - beta;
+        sg[j] = g;
+        sr[j][j] = beta;
+      }
+      __syncthreads();
+      for (int k = j + 1; k < nd; ++k) {
+        z64 t = mk(0.0, 0.0);
+        for (int l = lane; l < nz; l += 64)
+          if (l >= j) t = cfmac(t, sb[j][l], sb[k][l]);
+        t.x = lanes_sum<64>(t.x);
+        t.y = lanes_sum<64>(t.y);
+        t = g * t;
+        for (int l = lane; l < nz; l += 64)
+          if (l >= j) sb[k][l] = cfms(sb[k][l], sb[j][l], t);
+        __syncthreads();
+        if (lane == 0) sr[j][k] = sb[k][j];
+        __syncthreads();
+      }
+    }
+    // L = R^T (lower triangular) and its one-sided Jacobi SVD: M = L V = U S
+    z64 M[THIN_ND][THIN_ND], V[THIN_ND][THIN_ND], w[THIN_ND];
+#pragma unroll
+    for (int i = 0; i < THIN_ND; ++i) {
+      w[i] = i < nd ? sw[i] : mk(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < THIN_ND; ++j) {
+        M[i][j] = (i < nd && j < nd && i >= j) ? sr[j][i] : mk(0.0, 0.0);
+        V[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+      }
+    }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      bool off = false;
+#pragma unroll
+      for (int p = 0; p < THIN_ND; ++p)
+#pragma unroll
+        for (int q = p + 1; q < THIN_ND; ++q) {
+          if (q >= nd) continue;
+          double ap = 0.0, aq = 0.0;
+          z64 c = mk(0.0, 0.0);
+#pragma unroll
+          for (int i = 0; i < THIN_ND; ++i) {
+            ap += nrm2(M[i][p]);
+            aq += nrm2(M[i][q]);
+            c = cfmac(c, M[i][p], M[i][q]);
+          }
+          const double ac = sqrt(nrm2(c));
+          if (!(ac > 1e-15 * sqrt(ap * aq))) continue;
+          off = true;
+          const z64 e = mk(c.x / ac, c.y / ac);
+          const double zeta = (aq - ap) / (2.0 * ac);
+          const double t = zeta != 0.0 ? copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta))
+                                       : 1.0;
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+          for (int i = 0; i < THIN_ND; ++i) {
+            const z64 mp = M[i][p], mq = cmulc(e, M[i][q]);
+            M[i][p] = cs * mp - sn * mq;
+            M[i][q] = sn * mp + cs * mq;
+            const z64 vp = V[i][p], vq = cmulc(e, V[i][q]);
+            V[i][p] = cs * vp - sn * vq;
+            V[i][q] = sn * vp + cs * vq;
+          }
+        }
+      if (!off) break;
+    }
+    double sig[THIN_ND], b2[THIN_ND];
+    z64 b[THIN_ND];
+    double wn = 0.0, bn = 0.0, smax = 0.0;
+    bool defic = false;
+#pragma unroll
+    for (int i = 0; i < THIN_ND; ++i) {
+      double s2 = 0.0;
+      z64 bi = mk(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < THIN_ND; ++r) {
+        s2 += nrm2(M[r][i]);
+        bi = cfmac(bi, M[r][i], w[r]);
+      }
+      sig[i] = sqrt(s2);
+      b[i] = sig[i] > 0.0 ? mk(bi.x / sig[i], bi.y / sig[i]) : mk(0.0, 0.0);
+      defic = defic || (i < nd && !(s2 > 0.0));
+      b2[i] = nrm2(b[i]);
+      wn += nrm2(w[i]);
+      bn += b2[i];
+      smax = fmax(smax, s2);
+    }
+    // the square R^T spans C^nd unless a singular value is zero, so the
+    // part of w outside its range is zero (wn - bn would only be rounding)
+    const double rho2 = defic ? fmax(0.0, wn - bn) : 0.0;
+    // phi(alpha) = sum_i (alpha / (s_i^2 + alpha))^2 |b_i|^2 + rho^2
+    auto phi = [&](double al) {
+      double s = rho2;
+#pragma unroll
+      for (int i = 0; i < THIN_ND; ++i) {
+        const double q = al / (sig[i] * sig[i] + al);
+        s += q * q * b2[i];
+      }
+      return s;
+    };
+    const double T = a.thr2[f];
+    const double amin = a.eta * fr;
+    double al = amin;
+    int br = 1;
+    if (T >= 0.0 && phi(amin) < T) {
+      br = 2;
+      double lo = log(amin), hi = log(smax) + 1.0;
+      for (int round = 0; round < 60 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++round) {
+        const double x = lo + (hi - lo) * (lane + 1) / 64.0;
+        const unsigned long long bal = __ballot(phi(exp(x)) >= T);
+        if (!bal) {
+          // the root lies above: look further up
+          lo = hi;
+          hi = hi + 256.0;
+          continue;
+        }
+        const int l1 = __ffsll((long long)bal) - 1;
+        const double nh = __shfl(x, l1);
+        if (l1 > 0) lo = __shfl(x, l1 - 1);
+        hi = nh;
+      }
+      al = exp(0.5 * (lo + hi));
+    }
+    // y = V diag(s / (s^2 + alpha)) b, then v = conj(H_0 ... H_{nd-1} [conj(y); 0])
+    z64 y[THIN_ND];
+#pragma unroll
+    for (int j = 0; j < THIN_ND; ++j) {
+      y[j] = mk(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < THIN_ND; ++i) {
+        const double c = sig[i] > 0.0 ? sig[i] / (sig[i] * sig[i] + al) : 0.0;
+        y[j] = cfma(y[j], V[j][i], c * b[i]);
+      }
+    }
+    z64 t0 = mk(0.0, 0.0), t1 = mk(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < THIN_ND; ++j) {
+      if (lane == j && j < nd) t0 = cj(y[j]);
+    }
+    for (int j = nd - 1; j >= 0; --j) {
+      const z64 u0 = (lane >= j && lane < nz) ? sb[j][lane] : mk(0.0, 0.0);
+      const z64 u1 = (NMAX > 64 && lane + 64 < nz) ? sb[j][lane + 64] : mk(0.0, 0.0);
+      z64 s = cmulc(u0, t0);
+      if (NMAX > 64) s = cfmac(s, u1, t1);
+      s.x = lanes_sum<64>(s.x);
+      s.y = lanes_sum<64>(s.y);
+      s = sg[j] * s;
+      t0 = t0 - u0 * s;
+      if (NMAX > 64) t1 = t1 - u1 * s;
+    }
+    const long o0 = (long)f * nz * a.N + m;
+    if (lane < nz) {
+      if (a.vh_single)
+        ((z32*)a.Vh)[o0 + (long)lane * a.N] = cast<float>(cj(t0));
+      else
+        ((z64*)a.Vh)[o0 + (long)lane * a.N] = cj(t0);
+    }
+    if (NMAX > 64 && lane + 64 < nz) {
+      if (a.vh_single)
+        ((z32*)a.Vh)[o0 + (long)(lane + 64) * a.N] = cast<float>(cj(t1));
+      else
+        ((z64*)a.Vh)[o0 + (long)(lane + 64) * a.N] = cj(t1);
+    }
+    if (lane == 0) {
+      a.alpha[fm] = al;
+      a.branch[fm] = (signed char)br;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace fl

@@ -120,3 +120,19 @@ def test_prefactor_is_validated():
     assert st == flayer.FL_EUNSUPPORTED and "prefactor" in msg and not out.value
     st, msg, out = _create(prefactor=1, alpha_rule=1)
     assert st == flayer.FL_EUNSUPPORTED and not out.value
+
+
+def test_thin_layer_validation():
+    # two planes 0.01 apart (off the lattice) form a thin layer: the host
+    # checks refuse what it does not support before any device work
+    thin = 3.0 + 0.01 * np.arange(2)
+    st, msg, out = _create(nd=2, planes=thin, alpha_rule=1)
+    assert st == flayer.FL_EUNSUPPORTED and "thin" in msg and not out.value
+    st, msg, out = _create(nd=2, planes=thin, prefactor=1)
+    assert st == flayer.FL_EUNSUPPORTED and not out.value
+    st, msg, out = _create(nz=2, nd=3, planes=3.0 + 0.01 * np.arange(3))
+    assert st == flayer.FL_EUNSUPPORTED and "nd (3) > nz (2)" in msg
+    st, msg, out = _create(nd=2, planes=np.array([-1.0, 3.0]))
+    assert st == flayer.FL_EINVAL and "straddle" in msg
+    st, msg, out = _create(nd=6, planes=3.0 + 0.01 * np.arange(6))
+    assert st == flayer.FL_EINVAL and "spaced h" in msg
