@@ -119,6 +119,13 @@ typedef struct {
                           needs factor_per_system 0 and alpha_rule 0
                           (FL_EUNSUPPORTED otherwise). 0 (default): each
                           fl_invert factorizes the orbits it needs */
+  int regularizer;     /* item 1's regularizing algorithm: 0 = Tikhonov with the
+                          discrepancy-chosen alpha (default); 1 = truncated
+                          SVD (Section 5.2 reports it best): the fewest
+                          leading singular triplets with s_i^2 > eta ||A||_F^2
+                          whose residual is within tau delta_m; the ALPHA tap
+                          then holds that count. Implemented for a thin data
+                          layer (FL_EUNSUPPORTED otherwise) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);

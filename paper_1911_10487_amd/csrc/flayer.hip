@@ -701,6 +701,7 @@ fl_status run_thin(fl_plan* p) {
   a.N = p->N;
   a.thr2 = p->thr2;
   a.eta = p->opts.eta;
+  a.tsvd = p->opts.regularizer == 1;
   a.Vh = p->Vh;
   a.vh_single = sizeof(T) == 4;
   a.alpha = p->alpha;
@@ -1447,6 +1448,9 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
                                  "alpha_rule 0)");
   if (thin && (o.alpha_rule || o.prefactor))
     return fail(FL_EUNSUPPORTED, "thin layer: alpha_rule 1 and prefactor are not supported");
+  if (o.regularizer != 0 && o.regularizer != 1) return fail(FL_EINVAL, "regularizer must be 0 or 1");
+  if (o.regularizer == 1 && !thin)
+    return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) is implemented for a thin data layer only");
 
   fl_plan* p = new fl_plan();
   p->nx = nx;

@@ -1395,6 +1395,7 @@ struct ThinArgs {
   long N;
   const double* thr2;    // [F] (tau delta_m)^2, < 0 for noise-free data
   double eta;
+  int tsvd;              // 1: truncated SVD instead of Tikhonov
   void* Vh;
   int vh_single;
   double* alpha;
@@ -1545,7 +1546,52 @@ __global__ __launch_bounds__(64) void k_thin_solve(ThinArgs a) {
     const double amin = a.eta * fr;
     double al = amin;
     int br = 1;
-    if (T >= 0.0 && phi(amin) < T) {
+    // TSVD: keep the fewest leading triplets (s_i^2 > eta ||A||_F^2) whose
+    // residual rho^2 + sum_{i >= k} |b_i|^2 is within T; alpha receives k
+    double keep[THIN_ND];
+#pragma unroll
+    for (int i = 0; i < THIN_ND; ++i) keep[i] = 1.0;
+    if (a.tsvd) {
+      // rank of each singular value in decreasing order (ties by index)
+      int rank[THIN_ND];
+#pragma unroll
+      for (int i = 0; i < THIN_ND; ++i) {
+        int r = 0;
+#pragma unroll
+        for (int j = 0; j < THIN_ND; ++j)
+          r += (j < nd) && (sig[j] > sig[i] || (sig[j] == sig[i] && j < i));
+        rank[i] = r;
+      }
+      int kmax = 0;
+      double sb2[THIN_ND];
+#pragma unroll
+      for (int k = 0; k < THIN_ND; ++k) {
+        sb2[k] = 0.0;
+#pragma unroll
+        for (int i = 0; i < THIN_ND; ++i)
+          if (i < nd && rank[i] == k) sb2[k] = b2[i];
+        kmax += (k < nd) && (sig[k] * sig[k] > amin);
+      }
+      // tails sum_{i >= k} |b_i|^2 in decreasing-singular-value order,
+      // accumulated from the smallest singular value up
+      double tail[THIN_ND + 1];
+      tail[THIN_ND] = 0.0;
+#pragma unroll
+      for (int k = THIN_ND - 1; k >= 0; --k) tail[k] = k < nd ? tail[k + 1] + sb2[k] : 0.0;
+      int k = nd;
+      bool found = false;
+#pragma unroll
+      for (int kk = 0; kk <= THIN_ND; ++kk)
+        if (!found && kk <= nd && tail[kk] + rho2 <= T) {
+          k = kk;
+          found = true;
+        }
+      k = min(k, kmax);
+#pragma unroll
+      for (int i = 0; i < THIN_ND; ++i) keep[i] = (i < nd && rank[i] < k) ? 1.0 : 0.0;
+      al = (double)k;
+      br = 0;
+    } else if (T >= 0.0 && phi(amin) < T) {
       br = 2;
       double lo = log(amin), hi = log(smax) + 1.0;
       for (int round = 0; round < 60 && hi - lo > 1e-15 * fmax(1.0, fabs(hi)); ++round) {
@@ -1571,7 +1617,10 @@ __global__ __launch_bounds__(64) void k_thin_solve(ThinArgs a) {
       y[j] = mk(0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < THIN_ND; ++i) {
-        const double c = sig[i] > 0.0 ? sig[i] / (sig[i] * sig[i] + al) : 0.0;
+        // Tikhonov filter s / (s^2 + alpha), or 1 / s for a kept TSVD triplet
+        const double c = !(sig[i] > 0.0) ? 0.0
+                         : a.tsvd         ? keep[i] / sig[i]
+                                          : sig[i] / (sig[i] * sig[i] + al);
         y[j] = cfma(y[j], V[j][i], c * b[i]);
       }
     }

@@ -40,6 +40,7 @@ class FlOpts(ctypes.Structure):
         ("kernel_mode", ctypes.c_int), ("damping", ctypes.c_double),
         ("alpha_rule", ctypes.c_int), ("factor_per_system", ctypes.c_int),
         ("forward_method", ctypes.c_int), ("prefactor", ctypes.c_int),
+        ("regularizer", ctypes.c_int),
     ]
 
 
@@ -152,7 +153,7 @@ class Plan:
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
                  tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0,
                  kernel_mode=0, damping=0.0, alpha_rule=0, factor_per_system=0,
-                 forward_method=0, prefactor=0):
+                 forward_method=0, prefactor=0, regularizer=0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
@@ -160,6 +161,7 @@ class Plan:
         o.kernel_mode, o.damping = kernel_mode, damping
         o.alpha_rule, o.factor_per_system = alpha_rule, factor_per_system
         o.forward_method, o.prefactor = forward_method, prefactor
+        o.regularizer = regularizer
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)

@@ -136,3 +136,10 @@ def test_thin_layer_validation():
     assert st == flayer.FL_EINVAL and "straddle" in msg
     st, msg, out = _create(nd=6, planes=3.0 + 0.01 * np.arange(6))
     assert st == flayer.FL_EINVAL and "spaced h" in msg
+
+
+def test_tsvd_needs_a_thin_layer():
+    st, msg, out = _create(regularizer=1)
+    assert st == flayer.FL_EUNSUPPORTED and "TSVD" in msg and not out.value
+    st, msg, out = _create(regularizer=3)
+    assert st == flayer.FL_EINVAL and "regularizer" in msg

@@ -112,3 +112,23 @@ def test_thin_layer_has_no_derivatives(thin):
                  torch.ones((p.nz, p.ny, p.nx), dtype=torch.complex128, device="cuda"))
     assert e.value.status == FL_EUNSUPPORTED
     plan.close()
+
+
+@pytest.mark.parametrize("delta", [0.01, 0.0])
+def test_thin_tsvd_matches_oracle(thin, delta):
+    # regularizer 1: the truncated SVD with the discrepancy-chosen count of
+    # triplets (the paper's best performer), against the oracle's rule "tsvd":
+    # the same count for every solved system and the same solution
+    p, xi, u0, W = thin
+    Wd = synth.add_noise(p, W, delta)
+    ref_xi, ref = invert.invert(p, Wd, u0, delta, rule="tsvd", stages=True)
+    got, st = _run(p, Wd, u0, delta, regularizer=1)
+    k_ref = ref["alpha"].reshape(st["alpha"].shape)
+    act = np.isfinite(st["alpha"])
+    assert np.array_equal(st["alpha"][act], k_ref[act])
+    assert not np.any(k_ref[~act])
+    say("thin tsvd delta", delta, "counts", np.unique(k_ref, return_counts=True), "Vhat",
+        rel(st["Vhat"], ref["Vhat"]), "xi", rel(got, ref_xi))
+    tol = TOL if delta > 0 else 1e3 * 2.0 ** -53 * 1e5
+    assert rel(st["Vhat"], ref["Vhat"]) <= tol
+    assert rel(got, ref_xi) <= tol
