@@ -124,8 +124,12 @@ typedef struct {
                           SVD (Section 5.2 reports it best): the fewest
                           leading singular triplets with s_i^2 > eta ||A||_F^2
                           whose residual is within tau delta_m; the ALPHA tap
-                          then holds that count. Implemented for a thin data
-                          layer (FL_EUNSUPPORTED otherwise) */
+                          then holds that count. For a thin data layer, and
+                          for square systems with nz <= 64 on the per-call
+                          orbit factorizations (factor_per_system 0,
+                          alpha_rule 0, prefactor 0; FL_EUNSUPPORTED
+                          otherwise). No derivatives (fl_invert_vjp / _jvp
+                          return FL_EUNSUPPORTED) */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);

@@ -16,6 +16,7 @@
 #include "fft.hpp"
 #include "pointwise.hpp"
 #include "solver.hpp"
+#include "tsvd.hpp"
 
 using namespace fl;
 
@@ -121,6 +122,10 @@ struct fl_plan {
       *oslot = nullptr, *ocnt = nullptr, *olist_sys = nullptr;
   z64* refl_l = nullptr;
   double* gam_l = nullptr;
+  // truncated SVD of the square systems (regularizer 1): per orbit slot the
+  // SVD of the phase-scaled real bidiagonal
+  bool tsvd_sq = false;
+  TsvdOut tsv{};
   // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
   bool has_adj = false;
   z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;
@@ -718,12 +723,51 @@ fl_status run_thin(fl_plan* p) {
 
 // shared: allow one factorization per orbit (the derivative calls need the
 // per-system factorizations and pass false)
+// Truncated SVD of the square systems on the orbits' factorizations: the
+// bidiagonalization, the SVD of each factorization's real bidiagonal, then
+// every active system's truncated solve.
+template <typename T>
+fl_status solve_tsvd(fl_plan* p) {
+  RUN(group_by_orbit(p));
+  RUN(run_bidiag_orbits<T>(p));
+  const long FO = (long)p->F * p->n_orb;
+  const long FN = (long)p->F * p->N;
+  RUN(mark(p, FL_STAGE_DP));
+  hipLaunchKernelGGL(k_tsvd_svd, dim3((unsigned)std::min<long>(FO, 4096)), dim3(256), 0, p->st,
+                     p->dg, p->sp, p->ocount, (int)FO, p->n, p->tsv);
+  LAUNCHCHK();
+  TsvdArgs a{};
+  a.What = (const z64*)p->What;
+  a.list = p->olist_sys;
+  a.count = p->count;
+  a.oslot = p->oslot;
+  a.orep = p->orep;
+  a.refl_l = p->refl_l;
+  a.gam_l = p->gam_l;
+  a.refl = p->refl;
+  a.gam = p->gam;
+  a.fro = p->fro;
+  a.s = p->tsv;
+  a.thr2 = p->thr2;
+  a.eta = p->opts.eta;
+  a.n = p->n;
+  a.N = p->N;
+  a.Vh = p->Vh;
+  a.vh_single = sizeof(T) == 4;
+  a.alpha = p->alpha;
+  a.branch = p->branch;
+  hipLaunchKernelGGL(k_tsvd_solve, dim3((unsigned)std::min<long>(FN, 16384)), dim3(64), 0, p->st, a);
+  LAUNCHCHK();
+  return FL_OK;
+}
+
 template <typename T>
 fl_status solve_systems(fl_plan* p, bool shared = true) {
   const long FN = (long)p->F * p->N;
-  p->last_shared = p->opts.alpha_rule == 0 && shared && p->orbits;
+  p->last_shared = p->opts.alpha_rule == 0 && (shared || p->tsvd_sq) && p->orbits;
   RUN(solve_prepare<T>(p, !p->last_shared));
   if (p->thin) return run_thin<T>(p);
+  if (p->tsvd_sq) return solve_tsvd<T>(p);
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
   if (p->last_shared && p->prefactored) {
     RUN(group_by_orbit(p));
@@ -950,6 +994,8 @@ fl_status adjoint_preconditions(fl_plan* p) {
   if (p->opts.alpha_rule != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the per-system alpha (alpha_rule 0)");
   if (p->thin) return fail(FL_EUNSUPPORTED, "derivatives are not implemented for a thin data layer");
+  if (p->tsvd_sq)
+    return fail(FL_EUNSUPPORTED, "derivatives are implemented for Tikhonov (regularizer 0)");
   return ensure_adjoint_buffers(p);
 }
 
@@ -1449,8 +1495,14 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (thin && (o.alpha_rule || o.prefactor))
     return fail(FL_EUNSUPPORTED, "thin layer: alpha_rule 1 and prefactor are not supported");
   if (o.regularizer != 0 && o.regularizer != 1) return fail(FL_EINVAL, "regularizer must be 0 or 1");
-  if (o.regularizer == 1 && !thin)
-    return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) is implemented for a thin data layer only");
+  if (o.regularizer == 1 && !thin) {
+    if (nz > TSVD_NMAX)
+      return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) of square systems needs nz <= %d", TSVD_NMAX);
+    if (o.factor_per_system || o.alpha_rule || o.prefactor)
+      return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) of square systems needs shared "
+                                   "factorizations per call (factor_per_system 0, alpha_rule 0, "
+                                   "prefactor 0)");
+  }
 
   fl_plan* p = new fl_plan();
   p->nx = nx;
@@ -1621,6 +1673,18 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
       if (e == hipSuccess)
         e = hipMemcpy(p->omem, omem.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
       if (e != hipSuccess) return bail(fail(FL_EDEVICE, "orbit tables: %s", hipGetErrorString(e)));
+    }
+    if (o.regularizer == 1 && !thin) {
+      if (!p->orbits)
+        return bail(fail(FL_EUNSUPPORTED,
+                         "TSVD (regularizer 1) of square systems needs every orbit of the %ld in "
+                         "one workspace (max_chunk)", FO));
+      p->tsvd_sq = true;
+      PALLOC(p->tsv.sig, FO * nz);
+      PALLOC(p->tsv.P, FO * nz * nz);
+      PALLOC(p->tsv.Qc, FO * nz * nz);
+      PALLOC(p->tsv.cdl, FO * nz);
+      PALLOC(p->tsv.dr, FO * nz);
     }
   }
 #undef PALLOC
@@ -1897,6 +1961,7 @@ fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, 
   if (!W || !u0 || !xi_scratch) return fail(FL_EINVAL, "NULL array argument");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   if (p->thin) return fail(FL_EUNSUPPORTED, "a thin data layer has no solver schedule to tune");
+  if (p->tsvd_sq) return fail(FL_EUNSUPPORTED, "the TSVD solver has no schedule to tune");
   if (reps < 1) reps = 1;
   fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid, p->dp_spw};
   RUN(fl_invert(p, W, u0, delta, xi_scratch));

@@ -138,8 +138,12 @@ def test_thin_layer_validation():
     assert st == flayer.FL_EINVAL and "spaced h" in msg
 
 
-def test_tsvd_needs_a_thin_layer():
-    st, msg, out = _create(regularizer=1)
-    assert st == flayer.FL_EUNSUPPORTED and "TSVD" in msg and not out.value
+def test_tsvd_validation():
+    # square systems: TSVD runs on the per-call orbit factorizations only
+    for kw in (dict(factor_per_system=1), dict(alpha_rule=1), dict(prefactor=1)):
+        st, msg, out = _create(regularizer=1, **kw)
+        assert st == flayer.FL_EUNSUPPORTED and "TSVD" in msg and not out.value, kw
+    st, msg, out = _create(nz=80, nd=80, planes=10.25 + 0.125 * np.arange(80), regularizer=1)
+    assert st == flayer.FL_EUNSUPPORTED and "nz <= 64" in msg and not out.value
     st, msg, out = _create(regularizer=3)
     assert st == flayer.FL_EINVAL and "regularizer" in msg
