@@ -475,7 +475,8 @@ fl_status solve_prepare(fl_plan* p, bool compact) {
   if (!compact) return FL_OK;
   hipLaunchKernelGGL(k_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->count, nullptr,
+                     nullptr);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, FN, p->cnt, p->list);
   LAUNCHCHK();
@@ -624,17 +625,14 @@ fl_status solve_global(fl_plan* p) {
 fl_status group_by_orbit(fl_plan* p) {
   const long FN = (long)p->F * p->N;
   hipStream_t st = p->st;
-  hipLaunchKernelGGL(k_orbit_flag, dim3(nblk(FN, 256)), dim3(256), 0, st, p->flag, p->orep, p->omem,
-                     p->N, p->F, p->oflag);
+  hipLaunchKernelGGL(k_orbit_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->flag, p->orep,
+                     p->omem, p->N, p->oflag, FN, p->cnt, p->ocnt);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_orbit_block_count, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN,
-                     p->cnt, p->ocnt);
-  LAUNCHCHK();
-  if (!p->prefactored) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, p->nb_scan, p->ocount);
-    LAUNCHCHK();
-  }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->ocnt, p->nb_scan, p->count);
+  // member offsets (and, unless the orbits were compacted at plan creation,
+  // orbit offsets) in one launch
+  hipLaunchKernelGGL(k_scan, dim3(p->prefactored ? 1 : 2), dim3(1024), 0, st, p->ocnt, p->nb_scan,
+                     p->count, p->prefactored ? nullptr : p->cnt,
+                     p->prefactored ? nullptr : p->ocount);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_orbit_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->omem,
                      p->flag, p->N, p->cnt, p->ocnt, p->prefactored ? nullptr : p->olist,

@@ -72,29 +72,6 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   }
 }
 
-// Wavenumbers related by the torus's mirror (and, on a square torus, swap)
-// symmetries share A_m: thread per (f, m); for a representative m (orep[m]
-// = m), ocw[f N + m] counts the members of its orbit (omem[m][0..7], -1
-// padded) that need a solve; every other m gets 0.
-__global__ __launch_bounds__(256) void k_orbit_flag(const int* __restrict__ flag,
-                                                    const int* __restrict__ orep,
-                                                    const int* __restrict__ omem, long N, int F,
-                                                    int* __restrict__ ocw) {
-  const long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (fm >= (long)F * N) return;
-  const int f = (int)(fm / N);
-  const long m = fm - (long)f * N;
-  int c = 0;
-  if (orep[m] == m) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int mj = omem[m * 8 + j];
-      if (mj >= 0) c += flag[(long)f * N + mj];
-    }
-  }
-  ocw[fm] = c;
-}
-
 // Inclusive scan of small ints over a 1024-thread block (wave shuffles, then
 // the wave totals in wsum); returns the thread's inclusive sum, and wsum[15]
 // holds the block's sum afterwards.
@@ -120,15 +97,33 @@ __device__ __forceinline__ int block_incl_sum_scan(int v, int* wsum) {
   return v + (wv > 0 ? wsum[wv - 1] : 0);
 }
 
-// Per block of 1024 (f, m): the active orbits (cnt) and their active
-// members (cntw).
-__global__ __launch_bounds__(1024) void k_orbit_block_count(const int* __restrict__ ocw, long n,
+// Wavenumbers related by the torus's mirror (and, on a square torus, swap)
+// symmetries share A_m. Per block of 1024 (f, m): for a representative m
+// (orep[m] = m), ocw[f N + m] counts the members of its orbit (omem[m][0..7],
+// -1 padded) that need a solve, every other m gets 0; and the block's
+// active orbits (cnt) and their active members (cntw).
+__global__ __launch_bounds__(1024) void k_orbit_block_count(const int* __restrict__ flag,
+                                                            const int* __restrict__ orep,
+                                                            const int* __restrict__ omem, long N,
+                                                            int* __restrict__ ocw, long n,
                                                             int* __restrict__ cnt,
                                                             int* __restrict__ cntw) {
   __shared__ int wsum[16];
   __shared__ int wcnt[16];
   const long i = (long)blockIdx.x * 1024 + threadIdx.x;
-  const int c = i < n ? ocw[i] : 0;
+  int c = 0;
+  if (i < n) {
+    const int f = (int)(i / N);
+    const long m = i - (long)f * N;
+    if (orep[m] == m) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int mj = omem[m * 8 + j];
+        if (mj >= 0) c += flag[(long)f * N + mj];
+      }
+    }
+    ocw[i] = c;
+  }
   const unsigned long long bal = __ballot(c > 0);
   if ((threadIdx.x & 63) == 0) wcnt[threadIdx.x >> 6] = __popcll(bal);
   block_incl_sum_scan(c, wsum);
@@ -216,10 +211,14 @@ __global__ __launch_bounds__(1024) void k_block_count(const int* __restrict__ fl
   if (threadIdx.x == 0) cnt[blockIdx.x] = total;
 }
 
-// single block: exclusive scan of nb block counts; writes the total to *count
-__global__ __launch_bounds__(1024) void k_scan(int* __restrict__ cnt, int nb, int* __restrict__ count) {
+// block b: exclusive scan of the nb block counts cnt_b in place, the total to
+// *count_b (block 0: cnt, count; block 1, if launched: cnt2, count2)
+__global__ __launch_bounds__(1024) void k_scan(int* __restrict__ cnt0, int nb, int* __restrict__ count0,
+                                               int* __restrict__ cnt2, int* __restrict__ count2) {
   __shared__ int wsum[16];
   __shared__ int total;
+  int* cnt = blockIdx.x == 0 ? cnt0 : cnt2;
+  int* count = blockIdx.x == 0 ? count0 : count2;
   int carry = 0;
   for (int base = 0; base < nb; base += 1024) {
     int i = base + threadIdx.x;
