@@ -379,13 +379,31 @@ __host__ __device__ constexpr int p2_row() {
   return L + L / 16 + (((1 - (L + L / 16)) % 32) + 32) % 32;
 }
 
+// Element of the LDS exchange rows. FP64 transforms exchange the real and
+// then the imaginary parts through a row of doubles: half the LDS per
+// transform, so twice as many transforms stay resident on a CU (the FP64
+// kernels are HBM-bound and otherwise LDS-limited to 1.5 waves per SIMD).
+// FP32 transforms exchange whole complex values.
+template <typename T>
+struct P2Lds {
+  using type = cx<T>;
+  static constexpr bool split = false;
+};
+template <>
+struct P2Lds<double> {
+  using type = double;
+  static constexpr bool split = true;
+};
+
 // Transforms per workgroup: up to 512 threads and 64 KiB of LDS (twiddles
 // plus one padded row per transform).
 template <int L, typename T>
 __host__ __device__ constexpr int p2_cb() {
   constexpr int TT = L / P2<L>::E;
   int cb = 512 / TT;
-  while (cb > 1 && (size_t)(L + cb * p2_row<L>()) * sizeof(cx<T>) > 65536) cb /= 2;
+  while (cb > 1 && (size_t)L * sizeof(cx<T>) +
+                           (size_t)cb * p2_row<L>() * sizeof(typename P2Lds<T>::type) > 65536)
+    cb /= 2;
   return cb;
 }
 
@@ -514,22 +532,66 @@ __device__ __forceinline__ void p2_gather(cx<T> (&e)[P2<L>::E], const cx<T>* row
   for (int s = 0; s < E; ++s) e[s] = row[p2pad(t + TT * s)];
 }
 
+// The same placement and read for one part (IM: imaginary) through a row of
+// reals. Between the two parts the registers hold the new real parts and
+// the old imaginary ones, which the second scatter still reads in the old
+// order.
+template <typename T, int L, int R, int NS, bool IM>
+__device__ __forceinline__ void p2_scatter_part(const cx<T> (&e)[P2<L>::E], T* row, int t) {
+  constexpr int E = P2<L>::E, TT = L / E, NB = E / R;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int i = t + TT * q;
+    const int base = (i / NS) * NS * R + (i & (NS - 1));
+#pragma unroll
+    for (int r = 0; r < R; ++r) row[p2pad(base + r * NS)] = IM ? e[q + r * NB].y : e[q + r * NB].x;
+  }
+}
+template <typename T, int L, bool IM>
+__device__ __forceinline__ void p2_gather_part(cx<T> (&e)[P2<L>::E], const T* row, int t) {
+  constexpr int E = P2<L>::E, TT = L / E;
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const T v = row[p2pad(t + TT * s)];
+    if (IM)
+      e[s].y = v;
+    else
+      e[s].x = v;
+  }
+}
+
+// One exchange between passes: Stockham placement, barrier, reads.
+template <typename T, int L, int R, int NS>
+__device__ __forceinline__ void p2_exchange(cx<T> (&e)[P2<L>::E], typename P2Lds<T>::type* row,
+                                            int t) {
+  if constexpr (P2Lds<T>::split) {
+    p2_scatter_part<T, L, R, NS, false>(e, row, t);
+    __syncthreads();
+    p2_gather_part<T, L, false>(e, row, t);
+    __syncthreads();
+    p2_scatter_part<T, L, R, NS, true>(e, row, t);
+    __syncthreads();
+    p2_gather_part<T, L, true>(e, row, t);
+  } else {
+    p2_scatter<T, L, R, NS>(e, row, t);
+    __syncthreads();
+    p2_gather<T, L>(e, row, t);
+  }
+}
+
 // The whole transform, registers to registers. SYNC_IN: the LDS row may still
 // be read by other threads (a previous transform's last gather).
 template <typename T, int DIR, int L, bool SYNC_IN>
-__device__ __forceinline__ void p2_fft(cx<T> (&e)[P2<L>::E], cx<T>* row, const cx<T>* tws, int t) {
+__device__ __forceinline__ void p2_fft(cx<T> (&e)[P2<L>::E], typename P2Lds<T>::type* row,
+                                       const cx<T>* tws, int t) {
   using P = P2<L>;
   p2_butterflies<T, DIR, L, P::R0, 1>(e, tws, t);
   if constexpr (SYNC_IN) __syncthreads();
-  p2_scatter<T, L, P::R0, 1>(e, row, t);
-  __syncthreads();
-  p2_gather<T, L>(e, row, t);
+  p2_exchange<T, L, P::R0, 1>(e, row, t);
   p2_butterflies<T, DIR, L, P::R1, P::R0>(e, tws, t);
   if constexpr (P::NP == 3) {
     __syncthreads();
-    p2_scatter<T, L, P::R1, P::R0>(e, row, t);
-    __syncthreads();
-    p2_gather<T, L>(e, row, t);
+    p2_exchange<T, L, P::R1, P::R0>(e, row, t);
     p2_butterflies<T, DIR, L, P::R2, P::R0 * P::R1>(e, tws, t);
   }
 }
@@ -595,7 +657,7 @@ template <typename TI, typename T, typename TO, int DIR, int L>
 __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_p2(FftArgs g) {
   constexpr int CB = p2_cb<L, T>(), NT = CB * (L / P2<L>::E);
   __shared__ cx<T> tws[L];
-  __shared__ cx<T> lds[CB * p2_row<L>()];
+  __shared__ typename P2Lds<T>::type lds[CB * p2_row<L>()];
   int t, bl;
   p2_map<L, CB>(g.in_kfast, t, bl);
   const int b = blockIdx.x * CB + bl, plane = blockIdx.y;
@@ -625,14 +687,14 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_conv_p
                                                                               int conj_mul) {
   constexpr int CB = p2_cb<L, T>(), E = P2<L>::E, TT = L / E, NT = CB * TT;
   __shared__ cx<T> tws[L];
-  __shared__ cx<T> lds[CB * p2_row<L>()];
+  __shared__ typename P2Lds<T>::type lds[CB * p2_row<L>()];
   int t, bl;
   p2_map<L, CB>(0, t, bl);
   const int b = blockIdx.x * CB + bl, plane = blockIdx.y;
   p2_stage_twiddles<T, L>((const cx<T>*)g.tw, tws, NT);
   cx<T> e[E];
   p2_load<T, T, L>(g, e, b, plane, t);
-  cx<T>* row = lds + bl * p2_row<L>();
+  typename P2Lds<T>::type* row = lds + bl * p2_row<L>();
   p2_fft<T, -1, L, false>(e, row, tws, t);
   if (b < g.B) {
     const cx<T>* K = (const cx<T>*)mul + (long)plane * mul_sp + b;
@@ -656,7 +718,7 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_rows_crop_
     const cx<T>* __restrict__ tw, int nwin, int win_off, int rows, double scale) {
   constexpr int CB = p2_cb<L, T>(), E = P2<L>::E, TT = L / E, NT = CB * TT;
   __shared__ cx<T> tws[L];
-  __shared__ cx<T> lds[CB * p2_row<L>()];
+  __shared__ typename P2Lds<T>::type lds[CB * p2_row<L>()];
   int t, bl;
   p2_map<L, CB>(1, t, bl);
   const long row_i = (long)blockIdx.x * CB + bl;
@@ -665,23 +727,55 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_rows_crop_
   cx<T> e[E];
 #pragma unroll
   for (int s = 0; s < E; ++s) e[s] = ok ? in[row_i * L + t + TT * s] : mk((T)0, (T)0);
-  cx<T>* row = lds + bl * p2_row<L>();
+  typename P2Lds<T>::type* row = lds + bl * p2_row<L>();
   p2_fft<T, 1, L, false>(e, row, tws, t);
   const T sc = (T)scale;
   __syncthreads();
+  if constexpr (P2Lds<T>::split) {
+    // the scaled window, then its real and imaginary parts in turn through
+    // the row of reals (the window at the start, zeros after it)
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int k = t + TT * s;
-    const int kk = k - win_off;
-    if (kk >= 0 && kk < nwin) {
-      const cx<T> v = sc * e[s];
-      if (ok) out_v[row_i * nwin + kk] = cast<double>(v);
-      row[p2pad(kk)] = v;
+    for (int s = 0; s < E; ++s) {
+      const int kk = t + TT * s - win_off;
+      if (kk >= 0 && kk < nwin) {
+        e[s] = sc * e[s];
+        if (ok) out_v[row_i * nwin + kk] = cast<double>(e[s]);
+      }
     }
-    if (k >= nwin) row[p2pad(k)] = mk((T)0, (T)0);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int k = t + TT * s;
+      const int kk = k - win_off;
+      if (kk >= 0 && kk < nwin) row[p2pad(kk)] = e[s].x;
+      if (k >= nwin) row[p2pad(k)] = (T)0;
+    }
+    __syncthreads();
+    p2_gather_part<T, L, false>(e, row, t);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int k = t + TT * s;
+      const int kk = k - win_off;
+      if (kk >= 0 && kk < nwin) row[p2pad(kk)] = e[s].y;
+      if (k >= nwin) row[p2pad(k)] = (T)0;
+    }
+    __syncthreads();
+    p2_gather_part<T, L, true>(e, row, t);
+  } else {
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const int k = t + TT * s;
+      const int kk = k - win_off;
+      if (kk >= 0 && kk < nwin) {
+        const cx<T> v = sc * e[s];
+        if (ok) out_v[row_i * nwin + kk] = cast<double>(v);
+        row[p2pad(kk)] = v;
+      }
+      if (k >= nwin) row[p2pad(k)] = mk((T)0, (T)0);
+    }
+    __syncthreads();
+    p2_gather<T, L>(e, row, t);
   }
-  __syncthreads();
-  p2_gather<T, L>(e, row, t);
   p2_fft<T, -1, L, true>(e, row, tws, t);
   if (ok) {
 #pragma unroll
