@@ -95,3 +95,22 @@ def test_square_tsvd_full_size_sampled():
     say("full size sampled", len(ms), "systems, counts",
         np.unique(k_ref, return_counts=True), "Vhat", e)
     assert e <= tol_for(delta)
+
+
+def test_square_tsvd_closed_form_rank_one():
+    # kernel_mode 1: every A_m has rank one, so B' is singular to rounding
+    # and all but one singular value sit far below the eta floor: the count
+    # is at most one and the rest of w^ is residual
+    p, W, u0 = _global_case("small")
+    delta = 0.01
+    Wd = synth.add_noise(p, W, delta)
+    kw = dict(kernel_mode=1, damping=0.02, eta=1e-4)
+    ref_xi, ref = invert.invert(p, Wd, u0, delta, rule="tsvd", stages=True, **kw)
+    xi, st = gpu_run(p, Wd, u0, delta, regularizer=1, **kw)
+    k_ref = ref["alpha"].reshape(st["alpha"].shape)
+    act = np.isfinite(st["alpha"])
+    assert np.array_equal(st["alpha"][act], k_ref[act])
+    assert k_ref.max() <= 1
+    e = {"Vhat": rel(st["Vhat"], ref["Vhat"]), "xi": rel(xi, ref_xi)}
+    say("closed form", np.unique(k_ref[act], return_counts=True), e)
+    assert all(v <= tol_for(delta) for v in e.values()), e
