@@ -965,10 +965,10 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
   // with its rho and off), q' (sq), the complex superdiagonal and then the
   // Elden right-hand side (srr), the complex diagonal and then y (sy), the
   // right phases (sdr)
+  // (nothing else: at SPW = 4 and NMAX = 64 these are 20 KiB, so that eight
+  // one-wave workgroups fit in a CU's 160 KiB)
   __shared__ double sd[SPW][NMAX], se[SPW][NMAX];
   __shared__ z64 sq[SPW][NMAX], srr[SPW][NMAX], sy[SPW][NMAX], sdr[SPW][NMAX];
-  __shared__ double sal[SPW];
-  __shared__ int sbr[SPW];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int n = a.n;
   const int total = *a.count;
@@ -1027,7 +1027,10 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       }
     }
     __syncthreads();
-    // phase scaling and alpha, one system at a time over the whole wave
+    // phase scaling and alpha, one system at a time over the whole wave; the
+    // group of system s keeps its alpha and branch (the same on every lane)
+    double gal = 0.0;
+    int gbr = 0;
     for (int s = 0; s < SPW; ++s) {
       const int sls = sl0 + s, gss = a.chunk0 + sls;
       if (sls >= a.C || gss >= total) break;
@@ -1053,15 +1056,15 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       } else {
         br = dp_choose_alpha(n, lane, sd[s], se[s], sq[s], a.thr2[fsf], a.fro[fss], a.eta, &al);
       }
-      if (lane == 0) {
-        sal[s] = al;
-        sbr[s] = br;
+      if (grp == s) {
+        gal = al;
+        gbr = br;
       }
       __syncthreads();
     }
     // Elden solve of each group's system by the group's first lane
-    const int br = live ? sbr[grp] : 0;
-    const double al = live ? sal[grp] : 0.0;
+    const int br = live ? gbr : 0;
+    const double al = live ? gal : 0.0;
     if (br != 0 && gl == 0)
       elden_solve(sd[grp], se[grp], sq[grp], n, al, sd[grp], se[grp], srr[grp], sy[grp]);
     __syncthreads();
