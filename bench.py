@@ -107,6 +107,54 @@ def cpu_baseline(p, Wd, u0, delta, vf):
                        f"{dt:.1f} s; LAPACK SVDs on {threads} threads, FFTs single-threaded"}, xi)
 
 
+def _event_ms(torch, fn, reps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def time_variants(p, Wd, u0, delta, args, torch, dev):
+    """Secondary figures on the same data, none of them the headline: the
+    derivatives of W -> xi (one VJP, one JVP, one power-iteration step =
+    JVP + VJP; per-system factorizations, as the derivative path needs), and
+    the inversion with the truncated-SVD regularizer."""
+    from paper_1911_10487_amd.autograd import power_iteration
+    from paper_1911_10487_amd.flayer import Plan
+    out = {}
+    vf = p.voxel_frequencies
+    for label, prec in (("fp64", 0), ("mixed", 1)):
+        plan = Plan.from_problem(p, precision=prec)
+        g = torch.randn((p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        dW = torch.randn(Wd.shape, dtype=Wd.dtype, device=dev)
+        t_vjp = _event_ms(torch, lambda: plan.vjp(Wd, u0, delta, g), args.steps)
+        t_jvp = _event_ms(torch, lambda: plan.jvp(Wd, u0, delta, dW), args.steps)
+        power_iteration(plan, Wd, u0, delta, iters=1)  # warm-up (library set-up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est, _ = power_iteration(plan, Wd, u0, delta, iters=5)
+        torch.cuda.synchronize()
+        t_pi = (time.perf_counter() - t0) * 1e3 / 5
+        plan.close()
+        tplan = Plan.from_problem(p, precision=prec, regularizer=1)
+        xi = torch.empty((p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
+        t_tsvd = _event_ms(torch, lambda: tplan.invert(Wd, u0, delta, xi), args.steps)
+        tplan.close()
+        out[label] = {"vjp_ms": t_vjp, "jvp_ms": t_jvp, "power_iteration_ms_per_step": t_pi,
+                      "power_iteration_sigma_after_5": est[-1],
+                      "tsvd_ms_per_step": t_tsvd, "tsvd_value": vf / (t_tsvd * 1e-3)}
+        print(f"[bench] {label}: vjp {t_vjp:.3f} ms, jvp {t_jvp:.3f} ms, power step "
+              f"{t_pi:.3f} ms, tsvd inversion {t_tsvd:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +171,9 @@ def main():
     ap.add_argument("--no-prefactor", action="store_true",
                     help="skip the secondary timing of plans that factorize every matrix at "
                          "plan creation")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the secondary timings of the derivatives and of the TSVD "
+                         "regularizer")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing "
                          "(a known-size kernel for scaling HBM counters)")
@@ -196,6 +247,9 @@ def main():
                "stages_ms_per_step": r["stages"]}
         print(f"[bench] mixed, plan-time factorization: {r['ms']:.3f} ms/step", file=sys.stderr,
               flush=True)
+    variants = None
+    if not args.no_variants:
+        variants = time_variants(p, Wd, u0, delta, args, torch, dev)
     xi64 = runs["fp64"]["xi"]
     ximx = runs["mixed"]["xi"]
     mixed_vs_fp64 = float(np.linalg.norm(ximx - xi64) / np.linalg.norm(xi64))
@@ -246,6 +300,8 @@ def main():
     }
     if pre is not None:
         out["prefactored_plan"] = pre
+    if variants is not None:
+        out["variants"] = variants
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
