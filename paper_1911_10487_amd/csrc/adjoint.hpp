@@ -10,9 +10,14 @@
 // (Householder reflectors V, phases D_R, real bidiagonal B'), so
 // M^-1 x = V D_R (B'^T B' + alpha I)^-1 D_R^H V^H x, and the tridiagonal
 // solve uses R^T R = B'^T B' + alpha I from the Givens QR of [B'; sqrt(alpha) I].
-// A and A^H are applied directly from the system's Toeplitz table row.
+// A and A^H are applied directly from the system's Toeplitz table row. With
+// shared factorizations (one per symmetry orbit of the wavenumbers) the
+// system's factorization is its orbit's: the reflectors of the orbit slot,
+// and B', D_R from the slot's complex bidiagonal by the same phase scaling
+// as the forward solve.
 #pragma once
 #include "common.hpp"
+#include "solver.hpp"
 
 namespace fl {
 
@@ -39,6 +44,12 @@ struct AdjArgs {
   const double* Tdot;   // JVP: per frequency T'
   void* Y;              // VJP: w^bar [F][n][N] complex128; JVP: v^' (type of Vh)
   double* cm;           // VJP: [F*N] implicit-alpha coefficients s / phi_a
+  // shared factorizations (NULL: one per system): system (f, m) uses slot
+  // oslot[f N + orep[m]] of refl, gam and of the complex bidiagonal dg, sp
+  const int* oslot;
+  const int* orep;
+  const z64* dg;
+  const z64* sp;
 };
 
 template <typename T>
@@ -65,6 +76,7 @@ struct AdjShared {
   z64 vec[NMAX];
   double d[NMAX], e[NMAX], irho[NMAX], off[NMAX];
   z64 dr[NMAX];
+  z64 cy[NMAX], cs[NMAX], cq[NMAX];  // a shared slot's complex bidiagonal, scratch
 };
 
 // y = M^-1 x for the wave-distributed x (entries lane, lane + 64)
@@ -161,10 +173,22 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     const bool root = a.branch[fm] == 2;
     const z64* trow = a.gsys + ((long)f * a.N + m) * a.tpitch;
     for (int i = lane; i < 2 * n - 1; i += 64) S.t[i] = trow[i];
-    for (int i = lane; i < n; i += 64) {
-      S.d[i] = a.bd_d[(long)sl * n + i];
-      S.e[i] = a.bd_e[(long)sl * n + i];
-      S.dr[i] = a.bd_dr[(long)sl * n + i];
+    // factorization slot: the system's own, or its orbit's
+    const int fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
+    if (a.oslot) {
+      for (int i = lane; i < n; i += 64) {
+        S.cy[i] = a.dg[(long)fs * n + i];
+        S.cs[i] = a.sp[(long)fs * n + i];
+        S.cq[i] = mk(0.0, 0.0);
+      }
+      __syncthreads();
+      dp_phase_scale<NMAX>(n, lane, S.d, S.e, S.cq, S.cs, S.cy, S.dr);
+    } else {
+      for (int i = lane; i < n; i += 64) {
+        S.d[i] = a.bd_d[(long)sl * n + i];
+        S.e[i] = a.bd_e[(long)sl * n + i];
+        S.dr[i] = a.bd_dr[(long)sl * n + i];
+      }
     }
     __syncthreads();
     if (lane == 0) {
@@ -199,7 +223,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     double phia = 1.0, sx2 = 0.0;
     if (root) {
       z64 m0 = vh0, m1 = vh1;
-      minv<NMAX>(a, S, sl, m0, m1);                   // x2 = M^-1 v^
+      minv<NMAX>(a, S, fs, m0, m1);                   // x2 = M^-1 v^
       phia = 2.0 * al * wdot(vh0, vh1, m0, m1).x;
       if (MODE == 0) sx2 = -wdot(x0i, x1i, m0, m1).x; // s = -Re(v^bar^H x2)
       z64 a0 = m0, a1 = m1;
@@ -213,7 +237,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     }
     if (MODE == 0) {
       z64 y0 = x0i, y1 = x1i;
-      minv<NMAX>(a, S, sl, y0, y1);
+      minv<NMAX>(a, S, fs, y0, y1);
       toeplitz<NMAX, false>(S, n, y0, y1);            // A M^-1 v^bar
       double c = 0.0;
       if (root) {
@@ -233,7 +257,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
         b0 = b0 - ad * vh0;
         b1 = b1 - ad * vh1;
       }
-      minv<NMAX>(a, S, sl, b0, b1);
+      minv<NMAX>(a, S, fs, b0, b1);
       if (a.single) {
         z32* out = (z32*)a.Y + base;
         if (lane < n) out[(long)lane * a.N] = cast<float>(b0);

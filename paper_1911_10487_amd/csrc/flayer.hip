@@ -1020,13 +1020,32 @@ AdjArgs adj_args(fl_plan* p) {
   return a;
 }
 
-// Per-system derivative pass over every compacted system. The forward left
-// the factorization of the last chunk in the workspace; when the systems span
-// several chunks, each chunk is factorized again (same kernels, same
-// results) right before its derivative pass.
+// Per-system derivative pass over every solved system. With shared
+// factorizations (the forward factorized one matrix per active orbit) one
+// launch takes the orbit-grouped systems and their orbits' slots. Otherwise
+// the forward left the factorization of the last chunk in the workspace;
+// when the systems span several chunks, each chunk is factorized again
+// (same kernels, same results) right before its derivative pass.
 template <int MODE, typename T>
 fl_status launch_sys_adjoint(fl_plan* p, AdjArgs& a) {
   const long FN = (long)p->F * p->N;
+  if (p->last_shared) {
+    a.list = p->olist_sys;
+    a.count = p->count;
+    a.C = (int)FN;
+    a.chunk0 = 0;
+    a.oslot = p->oslot;
+    a.orep = p->orep;
+    a.dg = p->dg;
+    a.sp = p->sp;
+    const unsigned gs = (unsigned)std::min<long>(FN, 16384);
+    if (p->n <= 64)
+      hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(gs), dim3(64), 0, p->st, a);
+    else
+      hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(gs), dim3(64), 0, p->st, a);
+    LAUNCHCHK();
+    return FL_OK;
+  }
   const unsigned g = (unsigned)std::min<long>(p->C, 8192);
   const bool resident = (long)p->C >= FN;
   for (long c0 = 0; c0 < FN; c0 += p->C) {
@@ -1048,7 +1067,7 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp, false));
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
   const Tw<T> tw = twiddles_of<T>(p);
   // (d) reversed
   hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, p->xi_tmp, p->u, p->vX,
@@ -1113,7 +1132,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp, false));
+  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
   // T'_f = 2 tau^2 delta^2 Re <W_f, W'_f>
   {
     dim3 g(256, F);
