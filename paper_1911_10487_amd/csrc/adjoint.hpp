@@ -82,18 +82,18 @@ struct AdjShared {
 // y = M^-1 x for the wave-distributed x (entries lane, lane + 64)
 template <int NMAX>
 __device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64& x1) {
+  constexpr int E = NMAX / 64;  // elements per lane: lane, lane + 64
+  constexpr int RG = E == 1 ? 8 : 4;  // reflector rows loaded ahead
   const int n = a.n, lane = threadIdx.x;
   const z64* R = a.refl + (long)sl * n * n;
   const double* G = a.gam + (long)sl * n;
-  // z = V^H x = P_{n-3} ... P_0 x
-  for (int k = 0; k <= n - 3; ++k) {
-    const double g = G[k];
-    const z64 v0 = (lane > k && lane < n) ? R[(long)k * n + lane] : mk(0.0, 0.0);
-    const z64 v1 = (lane + 64 > k && lane + 64 < n) ? R[(long)k * n + lane + 64] : mk(0.0, 0.0);
-    const z64 s = g * wdot(v0, v1, x0, x1);
-    x0 = x0 - v0 * s;
-    x1 = x1 - v1 * s;
-  }
+  z64 x[E];
+  // z = V^H x = P_{n-3} ... P_0 x (reflector k has entries k + 1 .. n - 1)
+  x[0] = x0;
+  if constexpr (E > 1) x[1] = x1;
+  group_reflect<64, E, RG>(x, R, G, n, lane, 0, n - 2, 1, 1);
+  x0 = x[0];
+  if constexpr (E > 1) x1 = x[1];
   // D_R^H, then (R^T R)^-1 sequentially on lane 0
   if (lane < n) S.vec[lane] = cmulc(S.dr[lane], x0);
   if (lane + 64 < n) S.vec[lane + 64] = cmulc(S.dr[lane + 64], x1);
@@ -117,18 +117,13 @@ __device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64&
     }
   }
   __syncthreads();
-  x0 = lane < n ? S.dr[lane] * S.vec[lane] : mk(0.0, 0.0);
-  x1 = lane + 64 < n ? S.dr[lane + 64] * S.vec[lane + 64] : mk(0.0, 0.0);
+  x[0] = lane < n ? S.dr[lane] * S.vec[lane] : mk(0.0, 0.0);
+  if constexpr (E > 1) x[1] = lane + 64 < n ? S.dr[lane + 64] * S.vec[lane + 64] : mk(0.0, 0.0);
   __syncthreads();
   // V y = P_0 (P_1 (... P_{n-3} y))
-  for (int k = n - 3; k >= 0; --k) {
-    const double g = G[k];
-    const z64 v0 = (lane > k && lane < n) ? R[(long)k * n + lane] : mk(0.0, 0.0);
-    const z64 v1 = (lane + 64 > k && lane + 64 < n) ? R[(long)k * n + lane + 64] : mk(0.0, 0.0);
-    const z64 s = g * wdot(v0, v1, x0, x1);
-    x0 = x0 - v0 * s;
-    x1 = x1 - v1 * s;
-  }
+  group_reflect<64, E, RG>(x, R, G, n, lane, n - 3, -1, -1, 1);
+  x0 = x[0];
+  x1 = E > 1 ? x[E - 1] : mk(0.0, 0.0);
 }
 
 // (A x)_j = sum_l t[j - l + n - 1] x_l, or (A^H x)_l = sum_j conj(t[j - l + n - 1]) x_j
@@ -318,16 +313,29 @@ __global__ __launch_bounds__(256) void k_xi_jvp(const z64* __restrict__ xi, cons
 }
 
 // Tbar[f] = sum_m cm[f * N + m] (fixed order), one block per frequency
-__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ x, long N,
-                                                  double* __restrict__ out) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(1024) void k_sum_rows(const double* __restrict__ x, long N,
+                                                   double* __restrict__ out) {
+  // 1024 threads, four independent partial sums each (four loads in flight),
+  // then the waves' totals in a fixed order
+  __shared__ double red[16];
   const int f = blockIdx.x;
-  double s = 0.0;
-  for (long i = threadIdx.x; i < N; i += blockDim.x) s += x[(long)f * N + i];
+  const double* xf = x + (long)f * N;
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  long i = threadIdx.x;
+  for (; i + 3 * 1024 < N; i += 4 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s4[u] += xf[i + u * 1024];
+  }
+  for (; i < N; i += 1024) s4[0] += xf[i];
+  double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   s = lanes_sum<64>(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[f] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    out[f] = t;
+  }
 }
 
 // gW[f] += c * Tbar[f] * W[f]
@@ -347,11 +355,25 @@ __global__ __launch_bounds__(256) void k_dotre(const cx<TI>* __restrict__ a, con
                                                long per_f, double* __restrict__ partial) {
   __shared__ double red[4];
   const int f = blockIdx.y, nb = gridDim.x;
-  double s = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < per_f; i += (long)nb * blockDim.x) {
-    const cx<TI> x = a[(long)f * per_f + i], y = b[(long)f * per_f + i];
-    s += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+  // four independent partial sums per thread (four loads of each operand in
+  // flight)
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  const long step = (long)nb * blockDim.x;
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const cx<TI>* af = a + (long)f * per_f;
+  const cx<TI>* bf = b + (long)f * per_f;
+  for (; i + 3 * step < per_f; i += 4 * step) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const cx<TI> x = af[i + u * step], y = bf[i + u * step];
+      s4[u] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+    }
   }
+  for (; i < per_f; i += step) {
+    const cx<TI> x = af[i], y = bf[i];
+    s4[0] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+  }
+  double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   s = lanes_sum<64>(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();

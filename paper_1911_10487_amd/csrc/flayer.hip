@@ -1103,7 +1103,7 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   a.Y = p->Yb;
   a.cm = p->cm;
   RUN((launch_sys_adjoint<0, T>(p, a)));
-  hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(256), 0, st, p->cm, N, p->Tb);
+  hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(1024), 0, st, p->cm, N, p->Tb);
   LAUNCHCHK();
   // (a) reversed: Wbar = N IFFT2(W^bar) + 2 tau^2 delta^2 Tbar_f W_f (FP64)
   {
