@@ -104,9 +104,10 @@ typedef struct {
                           (kx -> -kx, ky -> -ky, and kx <-> ky when px = py):
                           fl_invert factorizes each such orbit once (about N/8
                           systems on a square torus) and applies the orbit's
-                          left reflectors to every member's data; 1 = one
-                          factorization per system (always so for alpha_rule 1
-                          and the derivative calls) */
+                          left reflectors to every member's data (the
+                          derivative calls use the orbit factorizations too);
+                          1 = one factorization per system (always so for
+                          alpha_rule 1) */
   int forward_method;  /* fl_forward with maxit > 0: 0 = BiCGSTAB (default);
                           1 = Algorithm 1's fixed point u <- u0 + omega^2 K(xi u)
                           from u0, stopped per frequency when the change is
