@@ -719,8 +719,6 @@ fl_status run_thin(fl_plan* p) {
   return FL_OK;
 }
 
-// shared: allow one factorization per orbit (the derivative calls need the
-// per-system factorizations and pass false)
 // Truncated SVD of the square systems on the orbits' factorizations: the
 // bidiagonalization, the SVD of each factorization's real bidiagonal, then
 // every active system's truncated solve.
@@ -759,10 +757,13 @@ fl_status solve_tsvd(fl_plan* p) {
   return FL_OK;
 }
 
+// Item 1 for every active system: one factorization per active orbit when
+// the plan has them (alpha_rule 0, factor_per_system 0), else per system in
+// chunks; the regularizer and alpha rule pick the solver.
 template <typename T>
-fl_status solve_systems(fl_plan* p, bool shared = true) {
+fl_status solve_systems(fl_plan* p) {
   const long FN = (long)p->F * p->N;
-  p->last_shared = p->opts.alpha_rule == 0 && (shared || p->tsvd_sq) && p->orbits;
+  p->last_shared = p->opts.alpha_rule == 0 && p->orbits;
   RUN(solve_prepare<T>(p, !p->last_shared));
   if (p->thin) return run_thin<T>(p);
   if (p->tsvd_sq) return solve_tsvd<T>(p);
@@ -904,8 +905,7 @@ fl_status stage_c(fl_plan* p, const void* Vin, z64* vout, z64* uout, const z64* 
 
 // The inversion launch sequence; T is the FFT / storage precision.
 template <typename T>
-fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out,
-                      bool shared = true) {
+fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, void* xi_out) {
   hipStream_t st = p->st;
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
@@ -955,7 +955,7 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
     RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->What, p->tw_y, py, px, F * nd), st)));
   }
   // (b) regularized solves of the active systems -> v^ plane-major
-  RUN(solve_systems<T>(p, shared));
+  RUN(solve_systems<T>(p));
   // (c) v = crop(IFFT2(v^)) / N, then u = u0 + omega^2 K v (zero-padded 3D FFT)
   RUN(stage_c<T>(p, p->Vh, p->vX, p->u, u0d));
   // (d) xi, in FP64
