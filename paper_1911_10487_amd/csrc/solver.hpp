@@ -791,25 +791,38 @@ __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, doub
   }
 }
 
-// Discrepancy choice of alpha for one system (the whole wave): round 0
-// tests the floor alpha_min = eta ||A||_F^2 (lane 0) and spreads lanes 1..63
+// Discrepancy choice of alpha for one system per group of W lanes (W = 64:
+// the whole wave; W = 32: each half-wave searches its own system, every lane
+// passing its half's arrays and constants): round 0 tests the floor
+// alpha_min = eta ||A||_F^2 (the group's lane 0) and spreads lanes 1..W-1
 // over (log alpha_min, log ||A||_F^2 + 1]; then a multisection on the
-// bracket. T < 0 (noise-free data) keeps the floor. Returns the branch
-// (1 floor, 2 root) and writes alpha.
-__device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd, const double* se,
+// bracket with W points per round. T < 0 (noise-free data) keeps the floor.
+// Returns the branch (1 floor, 2 root) and writes alpha, the same on every
+// lane of the group. The groups' control flow may diverge; the evaluations
+// are per lane, and ballots and shuffles stay inside the group.
+template <int W>
+__device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* sd, const double* se,
                                                const z64* sq, double T, double fro, double eta,
                                                double* alpha_out) {
+  static_assert(W == 32 || W == 64, "a group is a half-wave or the wave");
+  const int lane = lane_w & (W - 1);  // lane within the group
+  const int hb = lane_w & (64 - W);   // the group's first lane in the wave
+  auto gballot = [&](bool pr) -> unsigned long long {
+    const unsigned long long b = __ballot(pr);
+    return W == 64 ? b : (b >> hb) & 0xffffffffull;
+  };
+  auto gshfl = [&](double v, int src) -> double { return __shfl(v, hb + src); };
   const double amin = eta * fro;
   double al = amin;
   int br = 1;
   if (T >= 0.0) {
-    // round 0: lane 0 tests the floor alpha_min; lanes 1..63 spread over
+    // round 0: lane 0 tests the floor alpha_min; lanes 1..W-1 spread over
     // (log alpha_min, log ||A||_F^2 + 1], where the root almost always is
     const double h0 = log(fro) + 1.0;
     double lo = log(amin);
-    const double st0 = (h0 - lo) / 63.0;
+    const double st0 = (h0 - lo) / (double)(W - 1);
     double ph = phi_fwd(sd, se, sq, n, exp(lane == 0 ? lo : lo + st0 * lane));
-    unsigned long long bal = __ballot(ph >= T);
+    unsigned long long bal = gballot(ph >= T);
     if (!(bal & 1ull)) {
       br = 2;
       // bracket [lo, hi] on x = log(alpha) with phi(lo) < T <= phi(hi);
@@ -819,29 +832,29 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd
       if (bal) {
         const int l1 = __ffsll((long long)bal) - 1;
         hi = lo + st0 * l1;
-        fhi = __shfl(ph, l1);
+        fhi = gshfl(ph, l1);
         lo = lo + st0 * (l1 - 1);
-        flo = __shfl(ph, l1 - 1);
+        flo = gshfl(ph, l1 - 1);
       } else {
         // the root lies above: probe upward in steps of 4
         lo = h0;
-        flo = __shfl(ph, 63);
+        flo = gshfl(ph, W - 1);
         const double pu = phi_fwd(sd, se, sq, n, exp(h0 + 4.0 * (lane + 1)));
-        const unsigned long long bu = __ballot(pu >= T);
+        const unsigned long long bu = gballot(pu >= T);
         if (bu) {
           const int l1 = __ffsll((long long)bu) - 1;
           hi = h0 + 4.0 * (l1 + 1);
-          fhi = __shfl(pu, l1);
+          fhi = gshfl(pu, l1);
           if (l1 > 0) {
             lo = h0 + 4.0 * l1;
-            flo = __shfl(pu, l1 - 1);
+            flo = gshfl(pu, l1 - 1);
           }
         } else {
-          hi = h0 + 4.0 * 64;
+          hi = h0 + 4.0 * W;
           lo = hi;
         }
       }
-      // Multisection with 64 points per round. Once phi is known at both
+      // Multisection with W points per round. Once phi is known at both
       // ends, the points are packed around the secant estimate of the
       // root (phi is smooth in log alpha, so the secant error shrinks like
       // the square of the bracket). A window that misses the root still
@@ -859,10 +872,10 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd
           a0 = fmax(lo, xs - hw);
           a1 = fmin(hi, xs + hw);
         }
-        // 64 points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
-        const double step = (a1 - a0) / (a1 < hi ? 64.0 : 65.0);
+        // W points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
+        const double step = (a1 - a0) / (a1 < hi ? (double)W : (double)(W + 1));
         const double pl = phi_fwd(sd, se, sq, n, exp(a0 + step * (lane + 1)));
-        const unsigned long long b2 = __ballot(pl >= T);
+        const unsigned long long b2 = gballot(pl >= T);
         if (b2) {
           const int l1 = __ffsll((long long)b2) - 1;
           if (l1 >= 1 && step <= 2e-3) {
@@ -872,12 +885,12 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd
             // (below 1e-12 in log alpha), so no further round is needed.
             // Newton on the cubic in t (grid index from j0), from the secant
             // point, kept inside the bracketing grid interval.
-            const int j0 = min(max(l1 - 2, 0), 60);
-            const double p0 = __shfl(pl, j0), p1 = __shfl(pl, j0 + 1);
-            const double p2 = __shfl(pl, j0 + 2), p3 = __shfl(pl, j0 + 3);
+            const int j0 = min(max(l1 - 2, 0), W - 4);
+            const double p0 = gshfl(pl, j0), p1 = gshfl(pl, j0 + 1);
+            const double p2 = gshfl(pl, j0 + 2), p3 = gshfl(pl, j0 + 3);
             const double d1 = p1 - p0, d2 = p2 - 2.0 * p1 + p0;
             const double d3 = p3 - 3.0 * p2 + 3.0 * p1 - p0;
-            const double pa = __shfl(pl, l1 - 1), pb = __shfl(pl, l1);
+            const double pa = gshfl(pl, l1 - 1), pb = gshfl(pl, l1);
             const double ta = (double)(l1 - 1 - j0), tb = ta + 1.0;
             double t = ta + (pb > pa ? (T - pa) / (pb - pa) : 0.5);
 #pragma unroll
@@ -893,15 +906,15 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane, const double* sd
           }
           miss = l1 == 0 && a0 > lo;  // the root may lie left of the window
           hi = a0 + step * (l1 + 1);
-          fhi = __shfl(pl, l1);
+          fhi = gshfl(pl, l1);
           if (l1 > 0) {
             lo = a0 + step * l1;
-            flo = __shfl(pl, l1 - 1);
+            flo = gshfl(pl, l1 - 1);
           }
         } else {
           miss = a1 < hi;             // the root lies right of the window
-          lo = a0 + step * 64;
-          flo = __shfl(pl, 63);
+          lo = a0 + step * W;
+          flo = gshfl(pl, W - 1);
         }
       }
       double xr = 0.5 * (lo + hi);
@@ -957,7 +970,7 @@ __device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict
 // back-transform v^ = V (D_R y) run for the SPW systems at once, each in a
 // group of G = 64 / SPW lanes, so their reductions span G lanes only.
 template <int NMAX, int SPW>
-__global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
+__global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   constexpr int G = 64 / SPW;
   constexpr int E = (NMAX + G - 1) / G;
   constexpr int RG = E >= 4 ? 2 : (E == 2 ? 4 : 8);
@@ -1027,8 +1040,12 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
       }
     }
     __syncthreads();
-    // phase scaling and alpha, one system at a time over the whole wave; the
-    // group of system s keeps its alpha and branch (the same on every lane)
+    // phase scaling one system at a time over the whole wave; alpha the same
+    // way, or with two systems per wave for both at once, each half-wave (the
+    // system's own group) searching its system with 32 points per round (three
+    // rounds for the pair instead of two for each in turn). The group of
+    // system s keeps its alpha and branch (the same on every lane).
+    constexpr bool PAIRED = SPW == 2;
     double gal = 0.0;
     int gbr = 0;
     for (int s = 0; s < SPW; ++s) {
@@ -1048,17 +1065,32 @@ __global__ __launch_bounds__(64) void k_dp_solve(DpArgs a) {
           a.bd_dr[(long)sls * n + i] = sdr[s][i];
         }
       }
-      double al;
-      int br;
-      if (a.alpha_fixed) {
-        al = a.alpha_fixed[fsf];
-        br = a.branch_fixed[fsf];
-      } else {
-        br = dp_choose_alpha(n, lane, sd[s], se[s], sq[s], a.thr2[fsf], a.fro[fss], a.eta, &al);
+      if constexpr (!PAIRED) {
+        double al;
+        int br;
+        if (a.alpha_fixed) {
+          al = a.alpha_fixed[fsf];
+          br = a.branch_fixed[fsf];
+        } else {
+          br = dp_choose_alpha<64>(n, lane, sd[s], se[s], sq[s], a.thr2[fsf], a.fro[fss], a.eta,
+                                   &al);
+        }
+        if (grp == s) {
+          gal = al;
+          gbr = br;
+        }
       }
-      if (grp == s) {
-        gal = al;
-        gbr = br;
+      __syncthreads();
+    }
+    if constexpr (PAIRED) {
+      if (live) {
+        if (a.alpha_fixed) {
+          gal = a.alpha_fixed[f];
+          gbr = a.branch_fixed[f];
+        } else {
+          gbr = dp_choose_alpha<32>(n, lane, sd[grp], se[grp], sq[grp], a.thr2[f], a.fro[fs],
+                                    a.eta, &gal);
+        }
       }
       __syncthreads();
     }
