@@ -59,10 +59,11 @@ def stage_units(p, active, factorized, n, b=16):
         "xi": ("GB/s", 2 * F * nvox * 16 + nvox * 16),
         # complex Householder bidiagonalization of an n x n matrix: 4 x (8/3) n^3
         "bidiag": ("TFLOP/s", factorized * 32.0 / 3.0 * n ** 3),
-        # per system: 2 search rounds x 64 trial alphas x 20 flops per row of
-        # the discrepancy recurrence, q = U^H w and v^ = V y (8 n^2 flops
-        # each), the bidiagonal Tikhonov solve (about 40 n)
-        "dp": ("TFLOP/s", active * (2 * 64 * 20.0 * n + 16.0 * n * n + 40.0 * n)),
+        # per system: 3 search rounds x 32 trial alphas (two systems share a
+        # wave, one per half) x 20 flops per row of the discrepancy
+        # recurrence, q = U^H w and v^ = V y (8 n^2 flops each), the
+        # bidiagonal Tikhonov solve (about 40 n)
+        "dp": ("TFLOP/s", active * (3 * 32 * 20.0 * n + 16.0 * n * n + 40.0 * n)),
         "backtransform": ("GB/s", 0),
     }
     return u
