@@ -59,11 +59,11 @@ def stage_units(p, active, factorized, n, b=16):
         "xi": ("GB/s", 2 * F * nvox * 16 + nvox * 16),
         # complex Householder bidiagonalization of an n x n matrix: 4 x (8/3) n^3
         "bidiag": ("TFLOP/s", factorized * 32.0 / 3.0 * n ** 3),
-        # per system: 3 search rounds x 32 trial alphas (two systems share a
-        # wave, one per half) x 20 flops per row of the discrepancy
-        # recurrence, q = U^H w and v^ = V y (8 n^2 flops each), the
-        # bidiagonal Tikhonov solve (about 40 n)
-        "dp": ("TFLOP/s", active * (3 * 32 * 20.0 * n + 16.0 * n * n + 40.0 * n)),
+        # per system: 3 search rounds x 16 trial alphas (four systems share
+        # a wave, one per 16-lane group) x 20 flops per row of the
+        # discrepancy recurrence, q = U^H w and v^ = V y (8 n^2 flops each),
+        # the bidiagonal Tikhonov solve (about 40 n)
+        "dp": ("TFLOP/s", active * (3 * 16 * 20.0 * n + 16.0 * n * n + 40.0 * n)),
         "backtransform": ("GB/s", 0),
     }
     return u
@@ -366,7 +366,8 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev, prefactor=0):
         tr, tc, wpe = tuning["schedule"]
         kname = (f"k_bidiag<{tr}, {tc}, {p.nz // tr}, {p.nz // tc}, double, {wpe}>")
     elif dom == "dp":
-        kname = f"k_dp_solve<{64 if p.nz <= 64 else 128}, {tuning['dp_systems_per_wave'] or 2}>"
+        spw = tuning['dp_systems_per_wave'] or (4 if p.nz <= 64 else 2)
+        kname = f"k_dp_solve<{64 if p.nz <= 64 else 128}, {spw}>"
     tr_ = profiled_traffic(args.workload, prec, kname)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": tr_["bytes"] if tr_ else None,

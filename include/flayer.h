@@ -327,10 +327,12 @@ void fl_batch_destroy(fl_batch *batch);
  *   bidiag_grid     workgroups of the persistent bidiagonalization launch
  *                   (0 = 8192 for n <= 64, else 2048)
  *   dp_grid         one-wave workgroups of the discrepancy launch (0 = 16384)
- *   dp_systems_per_wave  systems one discrepancy wave takes: the alpha search
- *                   runs over the whole wave per system, the reflector passes
- *                   and the Elden solve for all of them at once in groups of
- *                   64 / w lanes; 1, 2, 4 (4 for nz <= 64 only), 0 = 2
+ *   dp_systems_per_wave  systems w one discrepancy wave takes, each in a
+ *                   group of 64 / w lanes for the reflector passes and the
+ *                   Elden solve; with w = 2 or 4 the groups also search their
+ *                   systems' alpha at once (64 / w points per round), with
+ *                   w = 1 the whole wave searches; 1, 2, 4 (4 for nz <= 64
+ *                   only), 0 = 4 for nz <= 64, else 2
  * Schedules sum in different orders, so their results agree to rounding, not
  * bitwise; a plan starts with schedule {0, 0, 0, 0}.
  */

@@ -495,8 +495,8 @@ fl_status run_bidiag(fl_plan* p, long c0) {
 }
 
 // Systems per wave of the discrepancy kernel (fl_tuning.dp_systems_per_wave;
-// 0 = 2).
-int dp_spw_of(const fl_plan* p) { return p->dp_spw > 0 ? p->dp_spw : 2; }
+// 0 = 4 for n <= 64, else 2).
+int dp_spw_of(const fl_plan* p) { return p->dp_spw > 0 ? p->dp_spw : (p->n <= 64 ? 4 : 2); }
 
 // Discrepancy root, Tikhonov solve and back-transform of the same chunk;
 // fixed: take alpha and the branch per frequency from the global search.

@@ -804,12 +804,15 @@ template <int W>
 __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* sd, const double* se,
                                                const z64* sq, double T, double fro, double eta,
                                                double* alpha_out) {
-  static_assert(W == 32 || W == 64, "a group is a half-wave or the wave");
+  static_assert(W == 16 || W == 32 || W == 64, "a group is 16 or 32 lanes or the wave");
   const int lane = lane_w & (W - 1);  // lane within the group
   const int hb = lane_w & (64 - W);   // the group's first lane in the wave
   auto gballot = [&](bool pr) -> unsigned long long {
     const unsigned long long b = __ballot(pr);
-    return W == 64 ? b : (b >> hb) & 0xffffffffull;
+    if constexpr (W == 64)
+      return b;
+    else
+      return (b >> hb) & ((1ull << W) - 1ull);
   };
   auto gshfl = [&](double v, int src) -> double { return __shfl(v, hb + src); };
   const double amin = eta * fro;
@@ -1045,7 +1048,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
     // system's own group) searching its system with 32 points per round (three
     // rounds for the pair instead of two for each in turn). The group of
     // system s keeps its alpha and branch (the same on every lane).
-    constexpr bool PAIRED = SPW == 2;
+    constexpr bool PAIRED = SPW == 2 || (SPW == 4 && NMAX <= 64);
     double gal = 0.0;
     int gbr = 0;
     for (int s = 0; s < SPW; ++s) {
@@ -1088,8 +1091,8 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
           gal = a.alpha_fixed[f];
           gbr = a.branch_fixed[f];
         } else {
-          gbr = dp_choose_alpha<32>(n, lane, sd[grp], se[grp], sq[grp], a.thr2[f], a.fro[fs],
-                                    a.eta, &gal);
+          gbr = dp_choose_alpha<64 / SPW>(n, lane, sd[grp], se[grp], sq[grp], a.thr2[f],
+                                          a.fro[fs], a.eta, &gal);
         }
       }
       __syncthreads();

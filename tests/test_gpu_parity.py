@@ -337,6 +337,15 @@ def test_every_solver_schedule_matches_oracle():
                 err = rel(got, rq)
                 say("schedule", nz, v, g, err)
                 assert err <= TOL
+        # systems per discrepancy wave: 1 (whole-wave search), 2 and 4 (each
+        # 32- or 16-lane group searching its own system)
+        for w in (1, 2, 4):
+            plan.set_tuning(0, 0, 0, w)
+            got = plan.invert(torch.from_numpy(Wq).cuda(), torch.from_numpy(uq).cuda(),
+                              0.02).cpu().numpy()
+            err = rel(got, rq)
+            say("systems per wave", nz, w, err)
+            assert err <= TOL
         plan.close()
     plan = Plan.from_problem(p)
     Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
