@@ -976,7 +976,7 @@ template <int NMAX, int SPW>
 __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   constexpr int G = 64 / SPW;
   constexpr int E = (NMAX + G - 1) / G;
-  constexpr int RG = E >= 4 ? 2 : (E == 2 ? 4 : 8);
+  constexpr int RG = E >= 8 ? 2 : (E == 2 ? 4 : (E == 4 ? 4 : 8));
   // per system: real bidiagonal (sd, se; the Elden solve overwrites them
   // with its rho and off), q' (sq), the complex superdiagonal and then the
   // Elden right-hand side (srr), the complex diagonal and then y (sy), the
