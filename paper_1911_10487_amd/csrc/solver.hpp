@@ -13,12 +13,12 @@
 //       applied to w on the fly (q = U^H w); the right ones are written out
 //       for the back-transform.
 //   k_dp_solve
-//       one wave per system: phase-scale B to a real bidiagonal, pick alpha by
-//       the discrepancy principle with a 64-way multisection on log(alpha)
-//       (each lane evaluates the discrepancy at its own alpha in one O(n)
-//       pass), solve at the chosen alpha by Elden's Givens QR of
-//       [B; sqrt(alpha) I], and back-transform v^ = V y into the plane-major
-//       array.
+//       one wave per 1, 2 or 4 systems, each in its own group of lanes:
+//       phase-scale B to a real bidiagonal, pick alpha by the discrepancy
+//       principle with a multisection on log(alpha) (each lane evaluates the
+//       discrepancy at its own alpha in one O(n) pass), solve at the chosen
+//       alpha by Elden's Givens QR of [B; sqrt(alpha) I], and back-transform
+//       v^ = V y into the plane-major array.
 #pragma once
 #include "common.hpp"
 
@@ -967,16 +967,18 @@ __device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict
   }
 }
 
-// SPW systems per single-wave workgroup. The phase scaling and the alpha
-// search use the whole wave for one system at a time (64 trial alphas per
-// round); q = U^H w (shared factorizations), the Elden solve and the
-// back-transform v^ = V (D_R y) run for the SPW systems at once, each in a
-// group of G = 64 / SPW lanes, so their reductions span G lanes only.
+// SPW systems per single-wave workgroup, each in a group of G = 64 / SPW
+// lanes. The phase scaling uses the whole wave for one system at a time; the
+// alpha searches (G trial alphas per round), q = U^H w (shared
+// factorizations), the Elden solve and the back-transform v^ = V (D_R y) run
+// for the SPW systems at once, each in its group, so their reductions span G
+// lanes only.
 template <int NMAX, int SPW>
 __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   constexpr int G = 64 / SPW;
   constexpr int E = (NMAX + G - 1) / G;
-  constexpr int RG = E >= 8 ? 2 : (E == 2 ? 4 : (E == 4 ? 4 : 8));
+  // reflector rows loaded ahead in the passes
+  constexpr int RG = E >= 8 ? 2 : (E == 1 ? 8 : 4);
   // per system: real bidiagonal (sd, se; the Elden solve overwrites them
   // with its rho and off), q' (sq), the complex superdiagonal and then the
   // Elden right-hand side (srr), the complex diagonal and then y (sy), the
@@ -1043,12 +1045,13 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       }
     }
     __syncthreads();
-    // phase scaling one system at a time over the whole wave; alpha the same
-    // way, or with two systems per wave for both at once, each half-wave (the
-    // system's own group) searching its system with 32 points per round (three
-    // rounds for the pair instead of two for each in turn). The group of
-    // system s keeps its alpha and branch (the same on every lane).
-    constexpr bool PAIRED = SPW == 2 || (SPW == 4 && NMAX <= 64);
+    // phase scaling one system at a time over the whole wave; then the alpha
+    // of every system at once, each group searching its own system with G
+    // points per round (three rounds for all of them, against two for each
+    // in turn with 64 points); with one system per wave the whole wave
+    // searches. The group of system s keeps its alpha and branch (the same
+    // on every lane).
+    constexpr bool GROUPED = SPW == 2 || (SPW == 4 && NMAX <= 64);
     double gal = 0.0;
     int gbr = 0;
     for (int s = 0; s < SPW; ++s) {
@@ -1068,7 +1071,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
           a.bd_dr[(long)sls * n + i] = sdr[s][i];
         }
       }
-      if constexpr (!PAIRED) {
+      if constexpr (!GROUPED) {
         double al;
         int br;
         if (a.alpha_fixed) {
@@ -1085,7 +1088,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       }
       __syncthreads();
     }
-    if constexpr (PAIRED) {
+    if constexpr (GROUPED) {
       if (live) {
         if (a.alpha_fixed) {
           gal = a.alpha_fixed[f];
