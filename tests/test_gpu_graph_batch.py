@@ -28,13 +28,14 @@ def _data(p, delta, born=True):
     return synth.add_noise(p, W, delta), u0
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replays_match_eager(precision):
+@pytest.mark.parametrize("precision,regularizer", [(0, 0), (1, 0), (0, 1)])
+def test_graph_replays_match_eager(precision, regularizer):
+    # regularizer 1: the truncated SVD's kernels captured as well
     import torch
     from paper_1911_10487_amd.flayer import Graph, Plan
     p = synth.make_problem("graph", 24, 20, 32, [2 * np.pi, 3 * np.pi], 3, (24, 0), (0.01,),
                            px=48, py=40)
-    plan = Plan.from_problem(p, precision=precision)
+    plan = Plan.from_problem(p, precision=precision, regularizer=regularizer)
     W1, u0 = _data(p, 0.01)
     W2 = synth.add_noise(p, W1, 0.02)
     ut = torch.from_numpy(u0).cuda()
@@ -42,7 +43,7 @@ def test_graph_replays_match_eager(precision):
     xi_g = torch.zeros((p.nz, p.ny, p.nx), dtype=torch.complex128, device="cuda")
     eager1 = plan.invert(torch.from_numpy(W1).cuda(), ut, 0.01).cpu().numpy()
     eager2 = plan.invert(torch.from_numpy(W2).cuda(), ut, 0.01).cpu().numpy()
-    say("capture", precision)
+    say("capture", precision, regularizer)
     g = Graph(plan, Wb, ut, 0.01, xi_g)
     for rep in range(3):
         for Wn, ref in ((W1, eager1), (W2, eager2)):
