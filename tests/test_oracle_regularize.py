@@ -144,3 +144,21 @@ def test_tsvd_keeps_the_fewest_triplets_meeting_the_discrepancy():
         assert resid(k[i]) <= rg.TAU * dm * (1 + 1e-12)
         if k[i] > 0:
             assert resid(k[i] - 1) > rg.TAU * dm
+
+
+def test_tsvd_without_noise_is_the_floored_pseudo_inverse():
+    # delta = 0: no residual is within a zero threshold, so every triplet above
+    # the floor s^2 > eta ||A||_F^2 is kept: the pseudo-inverse whose cut-off
+    # relative to s_max is sqrt(eta) ||A||_F / s_max (numpy's pinv)
+    A = _graded(6, 9, 9, 0.05, (21,))
+    w = synth.random_field((6, 9), (22,))
+    v, k = rg.tsvd_dp(A, w, 0.0)
+    for i in range(6):
+        s = np.linalg.svd(A[i], compute_uv=False)
+        fro = np.linalg.norm(A[i])
+        floor = np.sqrt(rg.ETA) * fro
+        # the graded spectrum keeps no singular value near the cut-off
+        assert np.min(np.abs(s - floor)) > 0.1 * floor
+        assert k[i] == np.count_nonzero(s > floor) < 9
+        ref = np.linalg.pinv(A[i], rcond=floor / s[0]) @ w[i]
+        assert np.linalg.norm(v[i] - ref) <= 1e-10 * np.linalg.norm(ref)
