@@ -180,8 +180,8 @@ def main():
                          "(a known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the inversion runs on a single GPU; --gpus {args.gpus} is not "
+              "supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum {
   FL_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed */
   FL_ENOCONV = 4,      /* an iterative solve did not reach its tolerance */
   FL_ENUMERIC = 5,     /* non-finite value met where a finite one is needed */
-  FL_EUNSUPPORTED = 6  /* a valid request this build does not implement */
+  FL_EUNSUPPORTED = 6  /* a valid request the library does not implement */
 } fl_status;
 
 /* Options. Zero-initialize and call fl_opts_default, then override. */

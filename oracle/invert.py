@@ -3,7 +3,7 @@
 Algorithm 2 (Section 4):
   item 1  for every frequency and horizontal wavenumber, solve the first-kind
           system of eq. (8) by a regularizing algorithm  -> V^(z', omega, Omega)
-  item 2  V = F^-1[V^] on X, and U from eq. (9); this build evaluates eq. (9)
+  item 2  V = F^-1[V^] on X, and U from eq. (9); the oracle evaluates eq. (9)
           in X as the linear convolution of v with the volume kernel (the
           in-X form of eq. 4), zero-padded in all three directions
   item 3  xi from u xi = V: v/u for one frequency, least squares over the

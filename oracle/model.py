@@ -2,7 +2,7 @@
 
 Follows the paper's Section 1 (eq. 1-4), Section 2 (eq. 5) and Section 5
 (discretization on uniform grids; G~ and U~0 from the FFT of sampled
-functions). Conventions of this build, each a reading of a passage the paper
+functions). Conventions taken here, each a reading of a passage the paper
 leaves open:
 
 * X cells are centred: x_i = (i + 1/2) h, z'_l = (l + 1/2) h, quadrature

@@ -3,7 +3,7 @@
 Algorithm 2, item 1 asks for a regularizing algorithm that yields the normal
 (minimum-norm) solution (Section 4, comment b; Section 5.2 names Tikhonov
 regularization and TSVD). The paper does not say how the parameter is chosen;
-this build's reading:
+the reading taken here:
 
 * Tikhonov: v(alpha) = (A^H A + alpha I)^{-1} A^H w.
 * Discrepancy principle per system: alpha solves

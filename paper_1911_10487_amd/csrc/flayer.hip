@@ -70,7 +70,7 @@ struct fl_plan {
   hipStream_t st;
   long N;
   int nzeta, TP, ox, oy, n;
-  // tables (FP64 in this build)
+  // tables (always FP64)
   z64 *tw_x = nullptr, *tw_y = nullptr, *tw_z = nullptr;
   z64* gtab = nullptr;  // [F][nzeta][N]
   z64* gsys = nullptr;  // [F][N][TP]
@@ -1478,7 +1478,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   if (thin && nz > 128) return fail(FL_EUNSUPPORTED, "thin layer: nz = %d > 128", nz);
   if (!thin &&
       !(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
-    return fail(FL_EUNSUPPORTED, "nz = %d: this build solves nz in {16,32,48,64,80,96,128}", nz);
+    return fail(FL_EUNSUPPORTED, "nz = %d: the library solves nz in {16,32,48,64,80,96,128}", nz);
   if (o.precision != 0 && o.precision != 1) return fail(FL_EUNSUPPORTED, "precision must be 0 or 1");
   if (o.kernel_mode != 0 && o.kernel_mode != 1) return fail(FL_EINVAL, "kernel_mode must be 0 or 1");
   if (!(o.damping >= 0) || !std::isfinite(o.damping)) return fail(FL_EINVAL, "damping must be >= 0");

@@ -38,7 +38,7 @@ def test_item_1_sees_the_data_operator(small):
 
 
 def test_flipping_the_transform_sign_leaves_xi_unchanged(small, monkeypatch):
-    # Section 2 prints exp(+i ...); this build uses exp(-i ...). G is radial,
+    # Section 2 prints exp(+i ...); the oracle and the kernels use exp(-i ...). G is radial,
     # so the two conventions give the same xi.
     p, xi, u0, W, U, V = small
     Wd = synth.add_noise(p, W, 0.01)
