@@ -730,7 +730,7 @@ fl_status solve_tsvd(fl_plan* p) {
   const long FN = (long)p->F * p->N;
   RUN(mark(p, FL_STAGE_DP));
   hipLaunchKernelGGL(k_tsvd_svd, dim3((unsigned)std::min<long>(FO, 4096)), dim3(256), 0, p->st,
-                     p->dg, p->sp, p->ocount, (int)FO, p->n, p->tsv);
+                     p->dg, p->sp, p->ocount, (int)FO, p->n, p->opts.eta, p->tsv);
   LAUNCHCHK();
   TsvdArgs a{};
   a.What = (const z64*)p->What;

@@ -6,7 +6,8 @@
 //   k_tsvd_svd
 //       one workgroup per factorization: phase-scale the complex bidiagonal
 //       B = D_L B' D_R^H to a real one, then one-sided (Hestenes) Jacobi on
-//       the dense B': its columns converge to P Sigma, B' = P Sigma Q^T, and
+//       the dense B' (pairs of columns both far below the truncation floor
+//       left unrotated): its columns converge to P Sigma, B' = P Sigma Q^T, and
 //       Q = B'^T P Sigma^{-1} (relative error u sigma_1 / sigma_j in column
 //       j, which matters only for the triplets that are kept). So
 //       A = (U D_L P) Sigma (V D_R Q)^H.
@@ -56,10 +57,11 @@ __device__ __forceinline__ void rr_pair(int m2, int r, int p, int& i, int& j) {
 __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
                                                   const z64* __restrict__ sp,
                                                   const int* __restrict__ count, int C, int n,
-                                                  TsvdOut o) {
+                                                  double eta, TsvdOut o) {
   __shared__ double M[TSVD_NMAX * TSVD_PITCH];  // column c at M[c * PITCH + r]
   __shared__ double sd[TSVD_NMAX], se[TSVD_NMAX];
   __shared__ z64 sq[TSVD_NMAX], srr[TSVD_NMAX], sy[TSVD_NMAX], sdr[TSVD_NMAX];
+  __shared__ double sth;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int total = min(*count, C);
   const int m2 = n + (n & 1);  // a zero column pads an odd n
@@ -76,6 +78,12 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
     // sq becomes conj(D_L), sdr D_R
     if (wv == 0) dp_phase_scale<TSVD_NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
     __syncthreads();
+    if (wv == 0) {
+      double f = 0.0;
+      for (int i = lane; i < n; i += 64) f += sd[i] * sd[i] + (i + 1 < n ? se[i] * se[i] : 0.0);
+      f = lanes_sum<64>(f);
+      if (lane == 0) sth = eta * f / n;
+    }
     for (int t = tid; t < m2 * TSVD_PITCH; t += 256) {
       const int c = t / TSVD_PITCH, r = t - c * TSVD_PITCH;
       double b = 0.0;
@@ -83,6 +91,13 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
       M[t] = b;
     }
     __syncthreads();
+    // Pairs of columns whose squared norms are both below th = eta ||B'||_F^2 / n
+    // are not rotated: at convergence every other pair is orthogonal, so the
+    // columns below th span a subspace whose largest singular value squared
+    // is below their summed squared norms, < n th, the floor under which no
+    // triplet is kept; the kept triplets are unchanged and their sweeps end
+    // in about half the count
+    const double th = sth;
     const int p = tid >> 3, h = tid & 7;
     // rows h + 8 s of both columns: the rows past n are zero in M, so
     // every thread handles its eight rows with no bound test and all loads of
@@ -118,7 +133,7 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
           a += __shfl_xor(a, 4);
           b += __shfl_xor(b, 4);
           c += __shfl_xor(c, 4);
-          if (a > 0.0 && b > 0.0 && c * c > tol * tol * (a * b)) {
+          if (a > 0.0 && b > 0.0 && c * c > tol * tol * (a * b) && (a >= th || b >= th)) {
             rot = 1;
             // the smaller root t of t^2 + 2 z t - 1 = 0, cos = 1 / sqrt(1 + t^2)
             const double z = (b - a) * rcp_nr(2.0 * c);
@@ -228,18 +243,24 @@ __global__ __launch_bounds__(64) void k_tsvd_solve(TsvdArgs a) {
       }
     if (on) sb2[rank] = b2;
     const double wn = lanes_sum<64>(nrm2(qp));
-    const double bn = lanes_sum<64>(b2);
-    const bool defic = __ballot(on && !(sg > 0.0)) != 0ull;
     const double fro = a.fro[fs];
     const int kmax = __popcll(__ballot(on && sg * sg > a.eta * fro));
+    // the nb columns with sigma^2 >= 2 eta ||A||_F^2 / n (at least the
+    // factorization's threshold for rotating a pair) are orthonormal to
+    // every other column; the rest, zero columns included, may not be
+    // orthogonal among themselves, so their share of ||q'||^2 (with the part
+    // outside the range) is taken as a whole: ||q'||^2 minus the leading share
+    const int nb = __popcll(__ballot(on && sg * sg >= 2.0 * a.eta * fro / n));
+    const double bh = lanes_sum<64>((on && rank < nb) ? b2 : 0.0);
+    const double gs = nb < n ? fmax(0.0, wn - bh) : 0.0;
     __syncthreads();
-    // residual after keeping the k = lane leading triplets: the |beta|^2
-    // of the rest summed from the smallest singular value up, plus the part
-    // of q' outside the range (nonzero only for an exactly singular B')
-    const double rho2 = defic ? fmax(0.0, wn - bn) : 0.0;
+    // residual after keeping the k = lane leading triplets: the |beta|^2 of
+    // the rest of the leading nb summed from the smallest singular value up,
+    // plus that share (kmax <= nb, so every count that can be chosen sees
+    // the leading terms one by one)
     double acc = 0.0;
-    for (int t = n - 1; t >= lane; --t) acc += sb2[t];
-    const double tail = acc + rho2;
+    for (int t = nb - 1; t >= lane; --t) acc += sb2[t];
+    const double tail = acc + gs;
     // noise-free data: the residual must vanish
     const double T = fmax(a.thr2[f], 0.0);
     const unsigned long long okb = __ballot(on && tail <= T);
