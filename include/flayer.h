@@ -185,6 +185,7 @@ fl_status fl_invert(fl_plan *plan, const void *W, const void *u0, double delta,
 fl_status fl_invert_vjp(fl_plan *plan, const void *W, const void *u0, double delta,
                         const void *grad_xi, void *grad_W, void *grad_u0);
 
+
 /*
  * Tangent (Jacobian-vector product): dxi ([nz][ny][nx] complex128) for the
  * data tangent dW (same layout and element type as W), u0 held fixed.
@@ -230,7 +231,9 @@ fl_status fl_plan_info(const fl_plan *plan, fl_plan_info_t *info);
  * is not solved at all (frequency selection). w: HOST array of n_omega
  * finite weights >= 0, not all 0, copied; NULL restores all ones. Applies
  * to combine = 0 and to fl_invert_vjp / fl_invert_jvp; synchronizes the
- * plan's stream. Errors: FL_EINVAL, FL_EDEVICE.
+ * plan's stream. The kernels read the weights from device memory at run
+ * time, so a graph captured earlier (fl_graph_create) replays with the
+ * weights set last. Errors: FL_EINVAL, FL_EDEVICE.
  */
 fl_status fl_set_frequency_weights(fl_plan *plan, const double *w);
 

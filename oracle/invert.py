@@ -122,6 +122,20 @@ def _solve_global(p, f, tab, idx, wsys, dm, tau, eta, chunk, bisect_steps=240):
     return V, alpha, branch
 
 
+def solve_sampled(p, f, W_f, delta, ms, tau=TAU, eta=ETA):
+    """Algorithm 2 item 1 for the sampled wavenumbers ms of frequency f only:
+    w_m by the 2D DFT at ms, delta_m from the whole data array of the
+    frequency, A_m from the sampled table; then the same regularized solve
+    as solve_systems. For checking full-size grids where the full tables
+    and transforms are too costly. Returns (Vhat (len(ms), nz), alpha, branch)."""
+    W_f = np.asarray(W_f, np.complex128)
+    wsys = model.dft2_at(W_f, ms, p.px, p.py).T                   # (S, nd)
+    dm = system_noise_level(W_f, delta)
+    tab, idx = model.system_table_at(p, f, ms)
+    A = model.system_matrices(p, f, tab, idx, None)
+    return tikhonov_dp(A, wsys, dm, tau, eta)
+
+
 def system_noise_level_hat(What_f, delta, N):
     """The same delta_m computed from the transformed data via Parseval:
     ||W||^2 = ||W^||^2 / N."""

@@ -69,6 +69,32 @@ def plane_kernel_hat(p, k0: float, zeta: float) -> np.ndarray:
     return p.h * p.h * np.fft.fft2(g)
 
 
+def dft2_at(arr: np.ndarray, ms, px: int, py: int) -> np.ndarray:
+    """The unnormalized 2D DFT of arr (..., py, px) at the flat wavenumber
+    indices ms (m = my*px + mx) only, by the definition
+    sum_p arr[p] exp(-2 pi i (px mx / Px + py my / Py)) (the sum over x as a
+    matrix product with the Fourier vectors, then over y): the transform of
+    Section 2 for a sample of wavenumbers, without a full FFT."""
+    ms = np.asarray(ms)
+    mx, my = ms % px, ms // px
+    ex = np.exp(-2j * np.pi * np.outer(np.arange(px), mx) / px)       # (px, S)
+    ey = np.exp(-2j * np.pi * np.outer(np.arange(py), my) / py)       # (py, S)
+    t = np.asarray(arr, np.complex128) @ ex                            # (..., py, S)
+    return np.einsum("...ys,ys->...s", t, ey)
+
+
+def system_table_at(p, f: int, ms):
+    """Ĝ for every distinct zeta at frequency f and the sampled wavenumbers
+    ms only: (n_zeta, len(ms)), plus the (nd, nz) index map (the FFT of
+    sampled G of Section 5, evaluated by dft2_at)."""
+    k0 = k0_of(p, f)
+    zetas, idx = zeta_index(p)
+    rho2 = horizontal_rho2(p)
+    tab = np.stack([p.h * p.h * dft2_at(green(np.sqrt(rho2 + z * z), k0), ms, p.px, p.py)
+                    for z in zetas])
+    return tab, idx
+
+
 def zeta_index(p):
     """Distinct height differences z_j - z'_l and the map (j, l) -> index.
 
@@ -109,10 +135,13 @@ def system_table(p, f: int, kernel_mode: int = 0, damping: float = 0.0):
 def system_matrices(p, f: int, tab, idx, ms) -> np.ndarray:
     """A_m for the flat system indices ms (m = my*px + mx): (len(ms), nd, nz).
 
-    A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = h)."""
+    A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = h).
+    With ms = None, tab holds the sampled columns already (system_table_at)."""
     om = float(p.omegas[f])
-    ms = np.asarray(ms)
-    flat = tab.reshape(tab.shape[0], -1)[:, ms]   # (n_zeta, len(ms))
+    if ms is None:
+        flat = tab
+    else:
+        flat = tab.reshape(tab.shape[0], -1)[:, np.asarray(ms)]   # (n_zeta, len(ms))
     return (om * om * p.h) * flat[idx].transpose(2, 0, 1)
 
 

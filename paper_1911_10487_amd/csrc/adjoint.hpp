@@ -34,7 +34,7 @@ struct AdjArgs {
   const double* bd_d;   // [C][n] real bidiagonal and phases from the forward
   const double* bd_e;
   const z64* bd_dr;
-  const z64* refl;      // [C][n][n]
+  const z64* refl;      // [C][tri_size(n, 1)] packed right reflectors
   const double* gam;    // [C][n]
   const void* What;     // [F][n][N] forward W^ (complex128)
   const void* Vh;       // [F][n][N] forward v^
@@ -50,6 +50,12 @@ struct AdjArgs {
   const int* orep;
   const z64* dg;
   const z64* sp;
+  // orbit chunks (NULL: every active orbit has a slot): the systems of
+  // compacted orbits [slot0, slot0 + OC), factorizations in slots
+  // oslot - slot0
+  const int* osys0;
+  const int* ocount;
+  int slot0, OC;
 };
 
 template <typename T>
@@ -85,7 +91,7 @@ __device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64&
   constexpr int E = NMAX / 64;  // elements per lane: lane, lane + 64
   constexpr int RG = E == 1 ? 8 : 4;  // reflector rows loaded ahead
   const int n = a.n, lane = threadIdx.x;
-  const z64* R = a.refl + (long)sl * n * n;
+  const z64* R = a.refl + (long)sl * tri_size(n, 1);
   const double* G = a.gam + (long)sl * n;
   z64 x[E];
   // z = V^H x = P_{n-3} ... P_0 x (reflector k has entries k + 1 .. n - 1)
@@ -160,8 +166,10 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
   const int lane = threadIdx.x;
   const int n = a.n;
   const int total = *a.count;
-  for (int sl = blockIdx.x; sl < a.C && a.chunk0 + sl < total; sl += gridDim.x) {
-    const int fm = a.list[a.chunk0 + sl];
+  int c0;
+  const int nsys = launch_range(a.osys0, a.ocount, a.slot0, a.OC, a.chunk0, a.C, total, &c0);
+  for (int sl = blockIdx.x; sl < nsys; sl += gridDim.x) {
+    const int fm = a.list[c0 + sl];
     const int f = (int)(fm / a.N);
     const long m = fm - (long)f * a.N;
     const double al = a.alpha[fm];
@@ -169,7 +177,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     const z64* trow = a.gsys + ((long)f * a.N + m) * a.tpitch;
     for (int i = lane; i < 2 * n - 1; i += 64) S.t[i] = trow[i];
     // factorization slot: the system's own, or its orbit's
-    const int fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
+    const int fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] - a.slot0 : sl;
     if (a.oslot) {
       for (int i = lane; i < n; i += 64) {
         S.cy[i] = a.dg[(long)fs * n + i];

@@ -75,6 +75,15 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
   return mk(-a.y, a.x);
 }
 
+// Householder reflectors of one n x n factorization, packed row after row:
+// reflector k holds entries k + off .. n - 1 (off = 0: left reflectors,
+// which start on the diagonal; off = 1: right reflectors) and starts at
+// tri_start(k, n, off); one factorization's set takes tri_size(n, off).
+__host__ __device__ __forceinline__ long tri_start(int k, int n, int off) {
+  return (long)k * (n - off) - (long)k * (k - 1) / 2;
+}
+__host__ __device__ __forceinline__ long tri_size(int n, int off) { return tri_start(n, n, off); }
+
 template <typename A, typename B>
 __device__ __forceinline__ cx<A> cast(cx<B> v) {
   return mk((A)v.x, (A)v.y);

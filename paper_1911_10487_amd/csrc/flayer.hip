@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,7 +63,16 @@ unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+// Workspaces of the derivative calls (allocated by the plan's first
+// derivative call), in one block laid out by adj_layout.
+struct AdjBufs {
+  z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;  // [F][nvox]
+  void *Xb = nullptr, *Yb = nullptr;  // [F][max(nd, nz)][N] complex128
+  double *cm = nullptr, *Tb = nullptr;  // [F N], [F]
+};
+
 struct fl_plan {
+  int dev = 0;  // the device current at creation (the plan's memory lives there)
   int nx, ny, nz, nd, px, py, F;
   double h, c0;
   std::vector<double> planes, omegas;
@@ -87,7 +97,6 @@ struct fl_plan {
   // weights of the frequencies in the least-squares xi (fl_set_frequency_weights)
   double* fw = nullptr;
   std::vector<double> fw_host;
-  bool fw_on = false;
   int *flag = nullptr, *cnt = nullptr, *list = nullptr, *count = nullptr;
   int nb_scan = 0;
   // solver chunk
@@ -120,6 +129,13 @@ struct fl_plan {
   double* zt = nullptr;
   int *orep = nullptr, *omem = nullptr, *oflag = nullptr, *olist = nullptr, *ocount = nullptr,
       *oslot = nullptr, *ocnt = nullptr, *olist_sys = nullptr;
+  // member ranges of the compacted orbits [F n_orb + 1]; the active orbits
+  // are factorized C at a time (orbit chunks) when they may exceed C
+  int* osys0 = nullptr;
+  // first compacted orbit of the chunk whose factorizations the workspace
+  // holds (-1: none known), so that the derivative pass after a forward
+  // solve re-factorizes only the chunks it no longer holds
+  int* oresident = nullptr;
   z64* refl_l = nullptr;
   double* gam_l = nullptr;
   // truncated SVD of the square systems (regularizer 1): per orbit slot the
@@ -128,9 +144,7 @@ struct fl_plan {
   TsvdOut tsv{};
   // derivative workspaces (allocated by the first fl_invert_vjp / _jvp)
   bool has_adj = false;
-  z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;
-  void *Xb = nullptr, *Yb = nullptr;
-  double *cm = nullptr, *Tb = nullptr;
+  AdjBufs adj;
   double* alpha = nullptr;
   signed char* branch = nullptr;
   // Lippmann-Schwinger solve (allocated by the first fl_forward with maxit > 0)
@@ -398,7 +412,7 @@ const std::vector<BdVariant>& bd_variants(int n) {
 
 template <typename T>
 fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk0, int C,
-                        unsigned grid, BidiagOut& o) {
+                        unsigned grid, BidiagOut& o, const int* resident = nullptr) {
   const int n = p->n;
   const z64* What = (const z64*)p->What;
   const auto& vs = bd_variants(n);
@@ -408,7 +422,7 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
 #define BD(TR, TC, WPE)                                                                     \
   if (v.tr == TR && v.tc == TC && v.wpe == WPE) {                                           \
     hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, double, WPE>), dim3(grid), dim3(TR * TC), 0, \
-                       p->st, p->gsys, p->TP, What, p->N, list, count, chunk0, C, o); \
+                       p->st, p->gsys, p->TP, What, p->N, list, count, chunk0, C, o, resident); \
     LAUNCHCHK();                                                                            \
     return FL_OK;                                                                           \
   }
@@ -455,10 +469,13 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
   return fail(FL_EUNSUPPORTED, "nz = %d has no solver instance", n);
 }
 
-// The frequency weights of the least-squares xi, or NULL when they are all
-// one (or xi is per frequency).
+// The frequency weights of the least-squares xi (NULL when xi is per
+// frequency).
 const double* freq_weights(const fl_plan* p) {
-  return (p->fw_on && p->opts.combine == 0) ? p->fw : nullptr;
+  // always the device array (all ones by default; multiplying by 1 is
+  // exact, so the unweighted results are unchanged), so that a captured
+  // graph reads the weights set after its capture
+  return p->opts.combine == 0 ? p->fw : nullptr;
 }
 
 // Classification (with v^ = 0 written for the systems without a solve) and,
@@ -527,15 +544,24 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
   a.alpha_fixed = fixed ? p->galpha : nullptr;
   a.branch_fixed = fixed ? p->gbranch : nullptr;
   if (shared) {
-    // every active system in one launch, grouped by orbit, factorizations by
-    // orbit slot
+    // the active systems grouped by orbit, factorizations by orbit slot: the
+    // members of the orbits whose factorizations the workspace holds
+    // (orbits [c0, c0 + C) of the compacted list; every orbit when they
+    // were factorized at plan creation)
     a.list = p->olist_sys;
     a.C = (int)((long)p->F * p->N);
+    a.chunk0 = 0;
     a.oslot = p->oslot;
     a.orep = p->orep;
     a.What = (const z64*)p->What;
     a.refl_l = p->refl_l;
     a.gam_l = p->gam_l;
+    if (!p->prefactored) {
+      a.osys0 = p->osys0;
+      a.ocount = p->ocount;
+      a.slot0 = (int)c0;
+      a.OC = p->C;
+    }
   }
   const int spw = dp_spw_of(p);
   const long ngr = ((long)a.C + spw - 1) / spw;
@@ -636,32 +662,52 @@ fl_status group_by_orbit(fl_plan* p) {
   LAUNCHCHK();
   hipLaunchKernelGGL(k_orbit_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->omem,
                      p->flag, p->N, p->cnt, p->ocnt, p->prefactored ? nullptr : p->olist,
-                     p->prefactored ? nullptr : p->oslot, p->olist_sys);
+                     p->prefactored ? nullptr : p->oslot, p->olist_sys,
+                     p->prefactored ? nullptr : p->osys0);
   LAUNCHCHK();
   return FL_OK;
 }
 
-// Bidiagonalization of the compacted orbit representatives, keeping their
-// left reflectors.
+// Active orbits of the compacted list that may need a slot (every orbit of
+// every frequency), and the orbit chunks that cover them.
+long orbit_bound(const fl_plan* p) { return (long)p->F * p->n_orb; }
+long orbit_chunks(const fl_plan* p) { return (orbit_bound(p) + p->C - 1) / p->C; }
+
+// Bidiagonalization of the compacted orbit representatives [o0, o0 + C)
+// into slots 0.. of the workspace, keeping their left reflectors.
+// reuse: skip a chunk that the workspace still holds from the forward solve.
 template <typename T>
-fl_status run_bidiag_orbits(fl_plan* p) {
-  const long FO = (long)p->F * p->n_orb;
+fl_status run_bidiag_orbits(fl_plan* p, long o0 = 0, bool reuse = false) {
+  const long FO = orbit_bound(p);
+  const int C = (int)std::min<long>(p->C, FO - o0);
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, p->refl_l, p->gam_l};
   const long gdef = p->n <= 64 ? 8192 : 2048;
-  const unsigned gb = (unsigned)std::min<long>(FO, p->bd_grid > 0 ? p->bd_grid : gdef);
+  const unsigned gb = (unsigned)std::min<long>(C, p->bd_grid > 0 ? p->bd_grid : gdef);
   RUN(mark(p, FL_STAGE_BIDIAG));
-  return launch_bidiag<T>(p, p->olist, p->ocount, 0, (int)FO, gb, o);
+  RUN(launch_bidiag<T>(p, p->olist, p->ocount, (int)o0, C, gb, o,
+                       reuse ? p->oresident : nullptr));
+  if (p->prefactored) return FL_OK;
+  hipLaunchKernelGGL(k_mark_resident, dim3(1), dim3(1), 0, p->st, p->oresident, p->ocount, (int)o0);
+  LAUNCHCHK();
+  return FL_OK;
 }
 
 // One factorization per active orbit: flag the orbits with an active
 // member, compact them, factorize each representative's A keeping its left
 // reflectors, then solve every active system against its orbit's
-// factorization (q = U^H w from the left reflectors).
+// factorization (q = U^H w from the left reflectors). When the active
+// orbits may exceed the workspace, they are taken C at a time (launches
+// past the last active orbit find no work and end at once).
 template <typename T>
 fl_status solve_orbits(fl_plan* p) {
   RUN(group_by_orbit(p));
-  RUN(run_bidiag_orbits<T>(p));
-  return run_dp<T>(p, 0, false, true);
+  hipLaunchKernelGGL(k_mark_resident, dim3(1), dim3(1), 0, p->st, p->oresident, p->ocount, -1);
+  LAUNCHCHK();
+  for (long o0 = 0; o0 < orbit_bound(p); o0 += p->C) {
+    RUN(run_bidiag_orbits<T>(p, o0));
+    RUN(run_dp<T>(p, o0, false, true));
+  }
+  return FL_OK;
 }
 
 // Plan-time factorization of every orbit representative of every frequency
@@ -969,24 +1015,37 @@ fl_status invert_impl(fl_plan* p, const void* W, const void* u0, double delta, v
 
 // ------------------------------------------------------------ derivatives
 
+// Layout of the derivative workspaces in one block of bytes: fills b's
+// pointers from base (when base is not NULL) and returns the block's size,
+// each part aligned to 256 bytes.
+size_t adj_layout(const fl_plan* p, char* base, AdjBufs* b) {
+  const size_t F = p->F, N = p->N;
+  const size_t nvox = (size_t)p->nx * p->ny * p->nz;
+  const size_t big = F * std::max(p->nd, p->nz) * N * sizeof(z64);
+  const size_t sizes[8] = {F * nvox * sizeof(z64), F * nvox * sizeof(z64), F * nvox * sizeof(z64),
+                           F * nvox * sizeof(z64), big, big, F * N * sizeof(double),
+                           F * sizeof(double)};
+  void** ptrs[8] = {(void**)&b->xi_tmp, (void**)&b->vbar, (void**)&b->ubar, (void**)&b->vbar2,
+                    &b->Xb, &b->Yb, (void**)&b->cm, (void**)&b->Tb};
+  size_t off = 0;
+  for (int i = 0; i < 8; ++i) {
+    if (base) *ptrs[i] = base + off;
+    off += (sizes[i] + 255) / 256 * 256;
+  }
+  return off;
+}
+
 fl_status ensure_adjoint_buffers(fl_plan* p) {
   if (p->has_adj) return FL_OK;
-  const long N = p->N, F = p->F;
-  const long nvox = (long)p->nx * p->ny * p->nz;
-  const size_t big = (size_t)(F * std::max(p->nd, p->nz) * N) * sizeof(z64);
-  ALLOC(p->xi_tmp, F * nvox);
-  ALLOC(p->vbar, F * nvox);
-  ALLOC(p->ubar, F * nvox);
-  ALLOC(p->vbar2, F * nvox);
-  RUN(dalloc_bytes(p, &p->Xb, big));
-  RUN(dalloc_bytes(p, &p->Yb, big));
-  ALLOC(p->cm, F * N);
-  ALLOC(p->Tb, F);
+  void* base = nullptr;
+  RUN(dalloc_bytes(p, &base, adj_layout(p, nullptr, &p->adj)));
+  adj_layout(p, (char*)base, &p->adj);
   p->has_adj = true;
   return FL_OK;
 }
 
-fl_status adjoint_preconditions(fl_plan* p) {
+// The derivative calls' own conditions (regularizer, alpha rule, layer).
+fl_status adjoint_supported(fl_plan* p) {
   if (p->opts.combine != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the least-squares xi (combine 0)");
   if (p->opts.alpha_rule != 0)
@@ -994,6 +1053,11 @@ fl_status adjoint_preconditions(fl_plan* p) {
   if (p->thin) return fail(FL_EUNSUPPORTED, "derivatives are not implemented for a thin data layer");
   if (p->tsvd_sq)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for Tikhonov (regularizer 0)");
+  return FL_OK;
+}
+
+fl_status adjoint_preconditions(fl_plan* p) {
+  RUN(adjoint_supported(p));
   return ensure_adjoint_buffers(p);
 }
 
@@ -1039,11 +1103,24 @@ fl_status launch_sys_adjoint(fl_plan* p, AdjArgs& a) {
     a.dg = p->dg;
     a.sp = p->sp;
     const unsigned gs = (unsigned)std::min<long>(FN, 16384);
-    if (p->n <= 64)
-      hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(gs), dim3(64), 0, p->st, a);
-    else
-      hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(gs), dim3(64), 0, p->st, a);
-    LAUNCHCHK();
+    // with several orbit chunks the forward left the last active one in the
+    // workspace: factorize each other chunk again (same kernel, same
+    // results) right before its derivative pass
+    const long nch = p->prefactored ? 1 : orbit_chunks(p);
+    for (long o0 = 0, c = 0; c < nch; o0 += p->C, ++c) {
+      if (nch > 1) RUN(run_bidiag_orbits<T>(p, o0, true));
+      if (!p->prefactored) {
+        a.osys0 = p->osys0;
+        a.ocount = p->ocount;
+        a.slot0 = (int)o0;
+        a.OC = p->C;
+      }
+      if (p->n <= 64)
+        hipLaunchKernelGGL((k_sys_adjoint<64, MODE>), dim3(gs), dim3(64), 0, p->st, a);
+      else
+        hipLaunchKernelGGL((k_sys_adjoint<128, MODE>), dim3(gs), dim3(64), 0, p->st, a);
+      LAUNCHCHK();
+    }
     return FL_OK;
   }
   const unsigned g = (unsigned)std::min<long>(p->C, 8192);
@@ -1061,31 +1138,31 @@ fl_status launch_sys_adjoint(fl_plan* p, AdjArgs& a) {
 }
 
 template <typename T>
-fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, const z64* gxi,
-                   z64* gW, z64* gu0) {
+fl_status vjp_impl(fl_plan* p, const AdjBufs& b, const void* W, const void* u0, double delta,
+                   const z64* gxi, z64* gW, z64* gu0) {
   hipStream_t st = p->st;
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  RUN(invert_impl<T>(p, W, u0, delta, b.xi_tmp));
   const Tw<T> tw = twiddles_of<T>(p);
   // (d) reversed
-  hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, p->xi_tmp, p->u, p->vX,
-                     nvox, F, freq_weights(p), p->vbar, p->ubar);
+  hipLaunchKernelGGL(k_xi_vjp, dim3(nblk(nvox, 256)), dim3(256), 0, st, gxi, b.xi_tmp, p->u, p->vX,
+                     nvox, F, freq_weights(p), b.vbar, b.ubar);
   LAUNCHCHK();
   // (c) reversed: vbar2 = vbar + K^H ubar, then V^bar = FFT2(pad(vbar2)) / N
   {
-    FftArgs r = rows_args(p->ubar, p->w2, tw.x, px, (long)F * nz * ny);
+    FftArgs r = rows_args(b.ubar, p->w2, tw.x, px, (long)F * nz * ny);
     r.lin = nx;
     r.in_sb = nx;
     RUN((run_fft<double, T, T, -1>(r, st)));
-    RUN(conv_tail<T>(p, p->vbar2, p->vbar, 1));
-    FftArgs a = rows_args(p->vbar2, p->w1, tw.x, px, (long)F * nz * ny);
+    RUN(conv_tail<T>(p, b.vbar2, b.vbar, 1));
+    FftArgs a = rows_args(b.vbar2, p->w1, tw.x, px, (long)F * nz * ny);
     a.lin = nx;
     a.in_sb = nx;
     a.in_off = p->ox;
     RUN((run_fft<double, T, T, -1>(a, st)));
-    FftArgs c = cols_args(p->w1, p->Xb, tw.y, py, px, F * nz);
+    FftArgs c = cols_args(p->w1, b.Xb, tw.y, py, px, F * nz);
     c.lin = ny;
     c.in_off = p->oy;
     c.in_sp = (long)ny * px;
@@ -1094,20 +1171,20 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   }
   // (b) reversed, per solved system
   const long FN = (long)F * N;
-  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(FN * nd, 256)), dim3(256), 0, st, (z64*)p->Yb, FN * nd);
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(FN * nd, 256)), dim3(256), 0, st, (z64*)b.Yb, FN * nd);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_zero_real, dim3(nblk(FN, 256)), dim3(256), 0, st, p->cm, FN);
+  hipLaunchKernelGGL(k_zero_real, dim3(nblk(FN, 256)), dim3(256), 0, st, b.cm, FN);
   LAUNCHCHK();
   AdjArgs a = adj_args(p);
-  a.X = p->Xb;
-  a.Y = p->Yb;
-  a.cm = p->cm;
+  a.X = b.Xb;
+  a.Y = b.Yb;
+  a.cm = b.cm;
   RUN((launch_sys_adjoint<0, T>(p, a)));
-  hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(1024), 0, st, p->cm, N, p->Tb);
+  hipLaunchKernelGGL(k_sum_rows, dim3(F), dim3(1024), 0, st, b.cm, N, b.Tb);
   LAUNCHCHK();
   // (a) reversed: Wbar = N IFFT2(W^bar) + 2 tau^2 delta^2 Tbar_f W_f (FP64)
   {
-    FftArgs c = cols_args(p->Yb, p->w1, p->tw_y, py, px, F * nd);
+    FftArgs c = cols_args(b.Yb, p->w1, p->tw_y, py, px, F * nd);
     RUN((run_fft<double, double, double, 1>(c, st)));
     FftArgs r = rows_args(p->w1, gW, p->tw_x, px, (long)F * nd * py);
     RUN((run_fft<double, double, double, 1>(r, st)));
@@ -1115,13 +1192,13 @@ fl_status vjp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
     const long per_f = (long)nd * N;
     if (p->opts.input_dtype == 0)
       hipLaunchKernelGGL(k_add_noise_term<double>, dim3(nblk(per_f * F, 256)), dim3(256), 0, st, gW,
-                         (const z64*)W, p->Tb, cc, per_f, F);
+                         (const z64*)W, b.Tb, cc, per_f, F);
     else
       hipLaunchKernelGGL(k_add_noise_term<float>, dim3(nblk(per_f * F, 256)), dim3(256), 0, st, gW,
-                         (const z32*)W, p->Tb, cc, per_f, F);
+                         (const z32*)W, b.Tb, cc, per_f, F);
     LAUNCHCHK();
   }
-  if (gu0) HIPCHK(hipMemcpyAsync(gu0, p->ubar, (size_t)F * nvox * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  if (gu0) HIPCHK(hipMemcpyAsync(gu0, b.ubar, (size_t)F * nvox * sizeof(z64), hipMemcpyDeviceToDevice, st));
   return FL_OK;
 }
 
@@ -1132,7 +1209,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
   const long N = p->N;
   const int F = p->F, nd = p->nd, nz = p->nz, nx = p->nx, ny = p->ny, px = p->px, py = p->py;
   const long nvox = (long)nx * ny * nz;
-  RUN(invert_impl<T>(p, W, u0, delta, p->xi_tmp));
+  RUN(invert_impl<T>(p, W, u0, delta, p->adj.xi_tmp));
   // T'_f = 2 tau^2 delta^2 Re <W_f, W'_f>
   {
     dim3 g(256, F);
@@ -1144,7 +1221,7 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
                          (long)nd * N, p->partial);
     LAUNCHCHK();
     const double cc = 2.0 * p->opts.tau * p->opts.tau * delta * delta;
-    hipLaunchKernelGGL(k_finish_dot, dim3(1), dim3(64), 0, st, p->partial, 256, F, cc, p->Tb);
+    hipLaunchKernelGGL(k_finish_dot, dim3(1), dim3(64), 0, st, p->partial, 256, F, cc, p->adj.Tb);
     LAUNCHCHK();
   }
   // W^' = FFT2(W')
@@ -1155,21 +1232,21 @@ fl_status jvp_impl(fl_plan* p, const void* W, const void* u0, double delta, cons
       RUN((run_fft<double, double, double, -1>(g, st)));
     else
       RUN((run_fft<float, double, double, -1>(g, st)));
-    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->Xb, p->tw_y, py, px, F * nd), st)));
+    RUN((run_fft<double, double, double, -1>(cols_args(p->w1, p->adj.Xb, p->tw_y, py, px, F * nd), st)));
   }
   const long FN = (long)F * N;
-  hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * nz, 256)), dim3(256), 0, st, (cx<T>*)p->Yb, FN * nz);
+  hipLaunchKernelGGL(k_zero<T>, dim3(nblk(FN * nz, 256)), dim3(256), 0, st, (cx<T>*)p->adj.Yb, FN * nz);
   LAUNCHCHK();
   AdjArgs a = adj_args(p);
-  a.X = p->Xb;
+  a.X = p->adj.Xb;
   a.x_single = 0;
-  a.Y = p->Yb;
-  a.Tdot = p->Tb;
+  a.Y = p->adj.Yb;
+  a.Tdot = p->adj.Tb;
   RUN((launch_sys_adjoint<1, T>(p, a)));
   // v' and u' = K v' (no incident term), then xi'
-  RUN(stage_c<T>(p, p->Yb, p->vbar, p->ubar, nullptr));
-  hipLaunchKernelGGL(k_xi_jvp, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->xi_tmp, p->u, p->vX,
-                     p->vbar, p->ubar, nvox, F, freq_weights(p), dxi);
+  RUN(stage_c<T>(p, p->adj.Yb, p->adj.vbar, p->adj.ubar, nullptr));
+  hipLaunchKernelGGL(k_xi_jvp, dim3(nblk(nvox, 256)), dim3(256), 0, st, p->adj.xi_tmp, p->u, p->vX,
+                     p->adj.vbar, p->adj.ubar, nvox, F, freq_weights(p), dxi);
   LAUNCHCHK();
   return FL_OK;
 }
@@ -1522,6 +1599,10 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   }
 
   fl_plan* p = new fl_plan();
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    delete p;
+    return fail(FL_EDEVICE, "no HIP device");
+  }
   p->nx = nx;
   p->ny = ny;
   p->nz = nz;
@@ -1605,43 +1686,12 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->rowsq, (long)F * nd * py);
   PALLOC(p->thr2, F);
   PALLOC(p->norm2, F);
-  // reflector workspace C * nz^2 complex; up to 24 GiB, so that the
-  // 128^2 x 64 grids run as one chunk even with five frequencies
-  long cap = std::max<long>(1024, (24L << 30) / ((long)nz * nz * (long)sizeof(z64)));
-  if (o.max_chunk > 0) cap = std::min<long>(cap, o.max_chunk);
-  p->C = thin ? 1 : (int)std::min<long>(FN, cap);  // the thin solver needs no workspace
-  const long C = p->C;
-  PALLOC(p->dg, C * nz);
-  PALLOC(p->sp, C * nz);
-  PALLOC(p->q, C * nz);
-  PALLOC(p->fro, C);
-  PALLOC(p->wnc, C);
-  PALLOC(p->refl, C * nz * nz);
-  PALLOC(p->gam, C * nz);
-  PALLOC(p->bd_d, C * nz);
-  PALLOC(p->bd_e, C * nz);
-  PALLOC(p->bd_dr, C * nz);
-  PALLOC(p->alpha, FN);
-  PALLOC(p->branch, FN);
-  if (o.alpha_rule == 1) {
-    p->gB = (int)std::min<long>(2048, N);
-    PALLOC(p->gd, FN * nz);
-    PALLOC(p->ge, FN * nz);
-    PALLOC(p->gq, FN * nz);
-    PALLOC(p->gfro, FN);
-    PALLOC(p->gf, FN);
-    PALLOC(p->gstart, F + 1);
-    PALLOC(p->gst, F);
-    PALLOC(p->galpha, F);
-    PALLOC(p->gbranch, F);
-    PALLOC(p->gpart, (long)F * p->gB * 64);
-  }
   std::vector<int> reps;  // orbit representatives, increasing
+  std::vector<int> orep_h(N), omem_h(N * 8, -1);
   {
     // symmetry orbits of the wavenumber lattice: mx -> -mx, my -> -my, and
     // mx <-> my on a square torus; the sampled kernel is radial, so Ghat and
     // every A_m are invariant under them
-    std::vector<int> orep(N), omem(N * 8, -1);
     int n_orb = 0;
     for (int my = 0; my < py; ++my)
       for (int mx = 0; mx < px; ++mx) {
@@ -1661,20 +1711,63 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
           }
         int r = m;
         for (int j = 0; j < ni; ++j) r = std::min(r, img[j]);
-        orep[m] = r;
+        orep_h[m] = r;
         if (r == m) {
           ++n_orb;
           reps.push_back(m);
-          for (int j = 0; j < ni; ++j) omem[(long)m * 8 + j] = img[j];
+          for (int j = 0; j < ni; ++j) omem_h[(long)m * 8 + j] = img[j];
         }
       }
     p->n_orb = n_orb;
-    const long FO = (long)F * n_orb;
-    p->orbits = o.factor_per_system == 0 && o.alpha_rule == 0 && FO <= C;
-    if (o.prefactor && !p->orbits)
+  }
+  const long FO = F * p->n_orb;
+  // Reflector workspace of C systems (per-system factorizations: the packed
+  // right reflectors) or C orbit slots (shared factorizations, which also
+  // keep the left reflectors: n^2 complex per slot): up to 80 GiB and 40 %
+  // of the free device memory, so that every orbit of the 256^2 x 128 grid
+  // with seven frequencies (61 GB) has a slot and one launch factorizes them.
+  const bool shared = o.factor_per_system == 0 && o.alpha_rule == 0 && !thin;
+  {
+    size_t fr = 0, tot = 0;
+    long budget = 80L << 30;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min<long>(budget, (long)(fr / 5 * 2));
+    const long slot = (long)sizeof(z64) * (tri_size(nz, 1) + (shared ? tri_size(nz, 0) : 0));
+    long cap = std::max<long>(1024, budget / slot);
+    if (o.max_chunk > 0) cap = std::min<long>(cap, o.max_chunk);
+    // the thin solver needs no workspace
+    p->C = thin ? 1 : (int)std::min<long>(shared ? FO : FN, cap);
+  }
+  const long C = p->C;
+  PALLOC(p->dg, C * nz);
+  PALLOC(p->sp, C * nz);
+  PALLOC(p->q, C * nz);
+  PALLOC(p->fro, C);
+  PALLOC(p->wnc, C);
+  PALLOC(p->refl, C * tri_size(nz, 1));
+  PALLOC(p->gam, C * nz);
+  PALLOC(p->bd_d, C * nz);
+  PALLOC(p->bd_e, C * nz);
+  PALLOC(p->bd_dr, C * nz);
+  PALLOC(p->alpha, FN);
+  PALLOC(p->branch, FN);
+  if (o.alpha_rule == 1) {
+    p->gB = (int)std::min<long>(2048, N);
+    PALLOC(p->gd, FN * nz);
+    PALLOC(p->ge, FN * nz);
+    PALLOC(p->gq, FN * nz);
+    PALLOC(p->gfro, FN);
+    PALLOC(p->gf, FN);
+    PALLOC(p->gstart, F + 1);
+    PALLOC(p->gst, F);
+    PALLOC(p->galpha, F);
+    PALLOC(p->gbranch, F);
+    PALLOC(p->gpart, (long)F * p->gB * 64);
+  }
+  {
+    p->orbits = shared;
+    if (o.prefactor && FO > C)
       return bail(fail(FL_EUNSUPPORTED,
-                       "prefactor needs shared factorizations (factor_per_system 0, alpha_rule 0) "
-                       "and a workspace of %ld systems (max_chunk)", FO));
+                       "prefactor needs a workspace of all %ld orbits (max_chunk)", FO));
     if (p->orbits) {
       PALLOC(p->orep, N);
       PALLOC(p->omem, N * 8);
@@ -1684,15 +1777,17 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
       PALLOC(p->oslot, FN);
       PALLOC(p->ocnt, p->nb_scan);
       PALLOC(p->olist_sys, FN);
-      PALLOC(p->refl_l, FO * nz * nz);
-      PALLOC(p->gam_l, FO * nz);
-      hipError_t e = hipMemcpy(p->orep, orep.data(), N * sizeof(int), hipMemcpyHostToDevice);
+      PALLOC(p->osys0, FO + 1);
+      PALLOC(p->oresident, 1);
+      PALLOC(p->refl_l, C * tri_size(nz, 0));
+      PALLOC(p->gam_l, C * nz);
+      hipError_t e = hipMemcpy(p->orep, orep_h.data(), N * sizeof(int), hipMemcpyHostToDevice);
       if (e == hipSuccess)
-        e = hipMemcpy(p->omem, omem.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
+        e = hipMemcpy(p->omem, omem_h.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
       if (e != hipSuccess) return bail(fail(FL_EDEVICE, "orbit tables: %s", hipGetErrorString(e)));
     }
     if (o.regularizer == 1 && !thin) {
-      if (!p->orbits)
+      if (!p->orbits || FO > C)
         return bail(fail(FL_EUNSUPPORTED,
                          "TSVD (regularizer 1) of square systems needs every orbit of the %ld in "
                          "one workspace (max_chunk)", FO));
@@ -1916,8 +2011,6 @@ fl_status fl_set_frequency_weights(fl_plan* p, const double* w) {
   HIPCHK(hipStreamSynchronize(p->st));
   p->fw_host = v;
   HIPCHK(hipMemcpy(p->fw, p->fw_host.data(), p->F * sizeof(double), hipMemcpyHostToDevice));
-  p->fw_on = false;
-  for (double x : v) p->fw_on = p->fw_on || x != 1.0;
   return FL_OK;
 }
 
@@ -2015,8 +2108,10 @@ fl_status fl_invert_vjp(fl_plan* p, const void* W, const void* u0, double delta,
   if (!W || !u0 || !grad_xi || !grad_W) return fail(FL_EINVAL, "NULL array argument");
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   RUN(adjoint_preconditions(p));
-  return p->prec ? vjp_impl<float>(p, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W, (z64*)grad_u0)
-                 : vjp_impl<double>(p, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W, (z64*)grad_u0);
+  return p->prec ? vjp_impl<float>(p, p->adj, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W,
+                                   (z64*)grad_u0)
+                 : vjp_impl<double>(p, p->adj, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W,
+                                    (z64*)grad_u0);
 }
 
 fl_status fl_invert_jvp(fl_plan* p, const void* W, const void* u0, double delta, const void* dW,

@@ -138,7 +138,9 @@ __global__ __launch_bounds__(1024) void k_orbit_block_count(const int* __restric
 // Compaction of the active orbits in increasing f N + m (olist, oslot; NULL
 // keeps them, for factorizations made at plan creation) and of the active
 // systems grouped by orbit (members in omem order) into list, from the
-// exclusive block offsets cnt / cntw (k_scan of the block counts).
+// exclusive block offsets cnt / cntw (k_scan of the block counts). osys0
+// (with olist): the members of compacted orbit o are list[osys0[o] ..
+// osys0[o + 1]), so that a range of orbits maps to a range of systems.
 __global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ ocw, long n,
                                                         const int* __restrict__ omem,
                                                         const int* __restrict__ flag, long N,
@@ -146,7 +148,8 @@ __global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ 
                                                         const int* __restrict__ cntw,
                                                         int* __restrict__ olist,
                                                         int* __restrict__ oslot,
-                                                        int* __restrict__ list) {
+                                                        int* __restrict__ list,
+                                                        int* __restrict__ osys0) {
   __shared__ int wsum[16];
   __shared__ int wpre[16];
   const long i = (long)blockIdx.x * 1024 + threadIdx.x;
@@ -164,15 +167,24 @@ __global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ 
     }
   }
   __syncthreads();
+  // no active orbit at all still leaves an empty first range
+  if (osys0 && blockIdx.x == 0 && threadIdx.x == 0) osys0[0] = 0;
   if (c > 0) {
+    const int pos0 = cntw[blockIdx.x] + incl - c;
     if (olist) {
       const int o = cnt[blockIdx.x] + wpre[wv] + __popcll(bal & ((1ull << lane) - 1ull));
       olist[o] = (int)i;
       oslot[i] = o;
+      // orbit o's start and end (the next orbit writes the same end value
+      // as its start)
+      if (osys0) {
+        osys0[o] = pos0;
+        osys0[o + 1] = pos0 + c;
+      }
     }
     const int f = (int)(i / N);
     const long m = i - (long)f * N;
-    int pos = cntw[blockIdx.x] + incl - c;
+    int pos = pos0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int mj = omem[m * 8 + j];
@@ -269,9 +281,9 @@ struct BidiagOut {
   z64* q;       // [C][n] U^H w
   double* fro;  // [C] ||A||_F^2
   double* wn2;  // [C] ||w||^2
-  z64* refl;    // [C][n][n] right reflector k in row k, entries k+1..n-1
+  z64* refl;    // [C][tri_size(n, 1)] right reflector k: entries k+1..n-1, packed
   double* gam;  // [C][n]
-  z64* refl_l;  // [C][n][n] left reflector k in row k, entries k..n-1; NULL: not kept
+  z64* refl_l;  // [C][tri_size(n, 0)] left reflector k: entries k..n-1, packed; NULL: not kept
   double* gam_l;
 };
 
@@ -493,7 +505,7 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
                                                    const cx<TW>* __restrict__ What, long N,
                                                    const int* __restrict__ list,
                                                    const int* __restrict__ count, int chunk0, int C,
-                                                   BidiagOut o) {
+                                                   BidiagOut o, const int* __restrict__ resident) {
   constexpr int n = TR * NA;
   static_assert(TR * NA == TC * NB, "square system");
   static_assert(TR == 16 || TR == 32 || TR == 64, "row classes form aligned lane groups");
@@ -506,6 +518,9 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
   const int lane = tid & 63, wv = tid >> 6;
   const int total = *count;
   const bool doq = o.refl_l == nullptr;
+  // the workspace already holds this chunk's factorizations (the forward
+  // solve made them from the same tables)
+  if (resident && *resident == chunk0) return;
 
   for (int sl = blockIdx.x; sl < C; sl += gridDim.x) {
     const int gs = chunk0 + sl;
@@ -558,15 +573,15 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
     bd_blocks<TR, TC, NA, NB, 0>(A, S, r, c, tid, lane, wv, doq);
 
     __syncthreads();
-    z64* refl = o.refl + (long)sl * n * n;
+    z64* refl = o.refl + (long)sl * tri_size(n, 1);
     double* gam = o.gam + (long)sl * n;
-    // right reflector k occupies row k, columns k+1..n-1
+    // right reflector k: row k, columns k+1..n-1
 #pragma unroll
     for (int a = 0; a < NA; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int i = r + TR * a, j = c + TC * b;
-        if (j > i && i + 2 < n) refl[(long)i * n + j] = A[a][b];
+        if (j > i && i + 2 < n) refl[tri_start(i, n, 1) + (j - i - 1)] = A[a][b];
       }
     for (int t = tid; t < n; t += NT) {
       gam[t] = S.gm[t];
@@ -580,18 +595,31 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
     if (o.refl_l) {
       // left reflector j: column j from the diagonal down (the pivot minus
       // beta on the diagonal), as it was when step j formed it
-      z64* rl = o.refl_l + (long)sl * n * n;
+      z64* rl = o.refl_l + (long)sl * tri_size(n, 0);
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int i = r + TR * a, j = c + TC * b;
-          if (i >= j && j + 1 < n) rl[(long)j * n + i] = (i == j) ? A[a][b] - S.dg[j] : A[a][b];
+          if (i >= j && j + 1 < n)
+            rl[tri_start(j, n, 0) + (i - j)] = (i == j) ? A[a][b] - S.dg[j] : A[a][b];
         }
       for (int t = tid; t < n; t += NT) o.gam_l[(long)sl * n + t] = (t + 1 < n) ? S.gl[t] : 0.0;
     }
     __syncthreads();
   }
+}
+
+// After the factorization of orbit chunk [chunk0, chunk0 + C): the
+// workspace holds it if the chunk had an active orbit (a chunk past the
+// last active orbit factorizes nothing and leaves the previous one).
+// chunk0 < 0 clears the mark.
+__global__ void k_mark_resident(int* __restrict__ resident, const int* __restrict__ ocount,
+                                int chunk0) {
+  if (chunk0 < 0)
+    *resident = -1;
+  else if (chunk0 < *ocount)
+    *resident = chunk0;
 }
 
 // ---------------------------------------------------------------- dp
@@ -607,7 +635,7 @@ struct DpArgs {
   long N;
   const double* thr2;  // per frequency: (tau delta_m)^2, < 0 for noise-free data
   double eta;
-  const z64* refl;     // [C][n][n] right reflectors
+  const z64* refl;     // [C][tri_size(n, 1)] right reflectors
   const double* gam;   // [C][n]
   void* Vh;            // [F][n][N] output, plane-major (complex64 or complex128)
   int vh_single;       // 1: Vh holds complex64
@@ -626,7 +654,29 @@ struct DpArgs {
   const z64* What;
   const z64* refl_l;
   const double* gam_l;
+  // orbit chunks (NULL: every active orbit has a slot): this launch solves
+  // the systems of compacted orbits [slot0, slot0 + OC), whose
+  // factorizations sit in slots oslot - slot0 of the workspace
+  const int* osys0;
+  const int* ocount;
+  int slot0, OC;
 };
+
+// The compacted systems [*first, *first + return value) that one solver
+// launch takes: the chunk [chunk0, chunk0 + C) of a list of total systems,
+// or, with orbit chunks, the members of compacted orbits
+// [slot0, slot0 + OC).
+__device__ __forceinline__ int launch_range(const int* osys0, const int* ocount, int slot0, int OC,
+                                            int chunk0, int C, int total, int* first) {
+  if (osys0) {
+    const int oc = *ocount;
+    const int b = osys0[min(slot0, oc)];
+    *first = b;
+    return osys0[min(slot0 + OC, oc)] - b;
+  }
+  *first = chunk0;
+  return min(C, total - chunk0);
+}
 
 // phi(alpha) = ||B y - q||^2 of the Tikhonov solution for the real upper
 // bidiagonal B (d, e; e[n-1] = 0), evaluated in one forward pass without storage:
@@ -932,8 +982,9 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* 
 
 // Householder reflectors applied to one vector by a group of G lanes
 // (element i held by lane i % G in slot i / G): x <- H_k x for k = k0, k0 + dk,
-// ..., with H_k = I - g_k h_k h_k^H and h_k in row k of R (entries from
-// first(k) on). Rows are loaded RG at a time so that their latency overlaps.
+// ..., with H_k = I - g_k h_k h_k^H and h_k the packed reflector k of R
+// (entries k + off .. n - 1). Reflectors are loaded RG at a time so that
+// their latency overlaps.
 template <int G, int E, int RG>
 __device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict__ R,
                                               const double* __restrict__ gam, int n, int gl,
@@ -950,7 +1001,8 @@ __device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int i = gl + G * e;
-        v[g][e] = (ok && i >= k + off && i < n) ? R[(long)k * n + i] : mk(0.0, 0.0);
+        v[g][e] = (ok && i >= k + off && i < n) ? R[tri_start(k, n, off) + (i - k - off)]
+                                                 : mk(0.0, 0.0);
       }
     }
 #pragma unroll
@@ -978,7 +1030,9 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   constexpr int G = 64 / SPW;
   constexpr int E = (NMAX + G - 1) / G;
   // reflector rows loaded ahead in the passes
-  constexpr int RG = E >= 8 ? 2 : (E == 1 ? 8 : 4);
+  // (two at four elements per lane for n > 64: four would take the kernel
+  // past 256 registers, one wave per SIMD)
+  constexpr int RG = (E >= 8 || (E >= 4 && NMAX > 64)) ? 2 : (E == 1 ? 8 : 4);
   // per system: real bidiagonal (sd, se; the Elden solve overwrites them
   // with its rho and off), q' (sq), the complex superdiagonal and then the
   // Elden right-hand side (srr), the complex diagonal and then y (sy), the
@@ -991,7 +1045,8 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   const int n = a.n;
   const int total = *a.count;
   // groups of SPW systems that hold work in this launch
-  const int nsys = min(a.C, total - a.chunk0);
+  int c0;
+  const int nsys = launch_range(a.osys0, a.ocount, a.slot0, a.OC, a.chunk0, a.C, total, &c0);
   const int nact = nsys > 0 ? (nsys + SPW - 1) / SPW : 0;
   // Workgroups go to the eight XCDs in turn: XCD x (of V = min(8, grid))
   // takes the contiguous group range [x per, (x + 1) per), so that systems
@@ -1004,8 +1059,8 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
     if (sg >= nact) break;
     const int sl0 = sg * SPW;
     // this lane's group system
-    const int sl = sl0 + grp, gs = a.chunk0 + sl;
-    const bool live = sl < a.C && gs < total;
+    const int sl = sl0 + grp, gs = c0 + sl;
+    const bool live = sl < nsys;
     int f = 0;
     long m = 0, fs = 0;
     if (live) {
@@ -1013,7 +1068,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       f = (int)(fm / a.N);
       m = fm - (long)f * a.N;
       // factorization slot: the system's own, or its orbit's
-      fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] : sl;
+      fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] - a.slot0 : sl;
       for (int e = 0; e < E; ++e) {
         const int i = gl + G * e;
         if (i < n) {
@@ -1030,7 +1085,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
           const int i = gl + G * e;
           x[e] = i < n ? w[(long)i * a.N] : mk(0.0, 0.0);
         }
-        group_reflect<G, E, RG>(x, a.refl_l + fs * n * n, a.gam_l + fs * n, n, gl, 0, n - 1, 1,
+        group_reflect<G, E, RG>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, gl, 0, n - 1, 1,
                                 0);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1055,12 +1110,12 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
     double gal = 0.0;
     int gbr = 0;
     for (int s = 0; s < SPW; ++s) {
-      const int sls = sl0 + s, gss = a.chunk0 + sls;
-      if (sls >= a.C || gss >= total) break;
+      const int sls = sl0 + s, gss = c0 + sls;
+      if (sls >= nsys) break;
       const int fms = a.list[gss];
       const int fsf = (int)(fms / a.N);
       const long ms = fms - (long)fsf * a.N;
-      const long fss = a.oslot ? a.oslot[(long)fsf * a.N + a.orep[ms]] : sls;
+      const long fss = a.oslot ? a.oslot[(long)fsf * a.N + a.orep[ms]] - a.slot0 : sls;
       dp_phase_scale<NMAX>(n, lane, sd[s], se[s], sq[s], srr[s], sy[s], sdr[s]);
       __syncthreads();
       if (!a.oslot) {
@@ -1132,7 +1187,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
           const int i = gl + G * e;
           y[e] = i < n ? sdr[grp][i] * sy[grp][i] : mk(0.0, 0.0);
         }
-        group_reflect<G, E, RG>(y, a.refl + fs * n * n, a.gam + fs * n, n, gl, n - 3, -1, -1, 1);
+        group_reflect<G, E, RG>(y, a.refl + fs * tri_size(n, 1), a.gam + fs * n, n, gl, n - 3, -1, -1, 1);
         const long o0 = (long)f * n * a.N + m;
 #pragma unroll
         for (int e = 0; e < E; ++e) {

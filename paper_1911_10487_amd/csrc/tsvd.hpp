@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64) void k_tsvd_solve(TsvdArgs a) {
     // q = U^H w
     z64 x[1];
     x[0] = on ? a.What[((long)f * n + lane) * a.N + m] : mk(0.0, 0.0);
-    group_reflect<64, 1, 4>(x, a.refl_l + fs * n * n, a.gam_l + fs * n, n, lane, 0, n - 1, 1, 0);
+    group_reflect<64, 1, 4>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, lane, 0, n - 1, 1, 0);
     const z64 qp = on ? a.s.cdl[fs * n + lane] * x[0] : mk(0.0, 0.0);
     const double sg = on ? a.s.sig[fs * n + lane] : 0.0;
     sqp[lane] = qp;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64) void k_tsvd_solve(TsvdArgs a) {
       }
       y[0] = a.s.dr[fs * n + lane] * y[0];
     }
-    group_reflect<64, 1, 4>(y, a.refl + fs * n * n, a.gam + fs * n, n, lane, n - 3, -1, -1, 1);
+    group_reflect<64, 1, 4>(y, a.refl + fs * tri_size(n, 1), a.gam + fs * n, n, lane, n - 3, -1, -1, 1);
     if (on) {
       const long o = ((long)f * n + lane) * a.N + m;
       if (a.vh_single)

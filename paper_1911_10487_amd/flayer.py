@@ -147,6 +147,22 @@ def _stream_handle():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _need(name, t, shape, dtypes):
+    """Refuse an array that does not match what the kernels will index: a
+    wrong shape or dtype would make them read or write past the tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, the plan needs {tuple(shape)}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, the plan needs one of {dtypes}")
+
+
 class Plan:
     """A flayer plan for one geometry and frequency set (owns device tables)."""
 
@@ -175,8 +191,31 @@ class Plan:
         self.nx, self.ny, self.nz, self.nd = nx, ny, nz, nd
         self.n_omega = len(omegas)
         self.combine = combine
+        self.input_dtype = input_dtype
         info = self.info()
         self.px, self.py = info.px, info.py
+
+    # ---- shapes and dtypes the kernels assume
+
+    def _in_dtypes(self):
+        import torch
+        return (torch.complex64,) if self.input_dtype == 1 else (torch.complex128,)
+
+    def _w_shape(self):
+        return (self.n_omega, self.nd, self.py, self.px)
+
+    def _u_shape(self):
+        return (self.n_omega, self.nz, self.ny, self.nx)
+
+    def _xi_shape(self):
+        s = (self.nz, self.ny, self.nx)
+        return (self.n_omega,) + s if self.combine == 1 else s
+
+    def _check_inputs(self, W, u0):
+        _need("W", W, self._w_shape(), self._in_dtypes())
+        _need("u0", u0, self._u_shape(), self._in_dtypes())
+        if u0.device != W.device:
+            raise ValueError("W and u0 must be on the same device")
 
     @classmethod
     def from_problem(cls, p, **kw):
@@ -213,26 +252,35 @@ class Plan:
         """W (n_omega, nd, py, px) and u0 (n_omega, nz, ny, nx): complex
         tensors on the GPU. Returns xi (nz, ny, nx) complex128 on the GPU."""
         import torch
+        self._check_inputs(W, u0)
         if xi_out is None:
-            shape = (self.nz, self.ny, self.nx)
-            if self.combine == 1:
-                shape = (self.n_omega,) + shape
-            xi_out = torch.empty(shape, dtype=torch.complex128, device=W.device)
-        for t in (W, u0, xi_out):
-            if not t.is_cuda or not t.is_contiguous():
-                raise ValueError("arrays must be contiguous GPU tensors")
+            xi_out = torch.empty(self._xi_shape(), dtype=torch.complex128, device=W.device)
+        _need("xi_out", xi_out, self._xi_shape(), (torch.complex128,))
         _check(lib().fl_invert(self._h, ctypes.c_void_p(W.data_ptr()),
                                ctypes.c_void_p(u0.data_ptr()), float(delta),
                                ctypes.c_void_p(xi_out.data_ptr())))
         return xi_out
 
-    def vjp(self, W, u0, delta, grad_xi, want_u0=False):
-        """Cotangents of W (and u0) for the xi cotangent grad_xi (complex128)."""
+    def vjp(self, W, u0, delta, grad_xi, want_u0=False, out=None):
+        """Cotangents of W (and u0) for the xi cotangent grad_xi (complex128);
+        into `out` = (gW, gu0 or None) when given."""
         import torch
-        gW = torch.empty(W.shape, dtype=torch.complex128, device=W.device)
-        gu = (torch.empty((self.n_omega, self.nz, self.ny, self.nx), dtype=torch.complex128,
-                          device=W.device) if want_u0 else None)
-        g = grad_xi.to(torch.complex128).contiguous()
+        self._check_inputs(W, u0)
+        if out is not None:
+            gW, gu = out
+            _need("gW", gW, self._w_shape(), (torch.complex128,))
+            if gu is not None:
+                _need("gu0", gu, self._u_shape(), (torch.complex128,))
+        else:
+            gW = torch.empty(W.shape, dtype=torch.complex128, device=W.device)
+            gu = (torch.empty(self._u_shape(), dtype=torch.complex128,
+                              device=W.device) if want_u0 else None)
+        if tuple(grad_xi.shape) != self._xi_shape():
+            raise ValueError(f"grad_xi has shape {tuple(grad_xi.shape)}, the plan needs "
+                             f"{self._xi_shape()}")
+        g = grad_xi
+        if not (g.is_cuda and g.dtype == torch.complex128 and g.is_contiguous()):
+            g = grad_xi.to(W.device, torch.complex128).contiguous()
         _check(lib().fl_invert_vjp(self._h, ctypes.c_void_p(W.data_ptr()),
                                    ctypes.c_void_p(u0.data_ptr()), float(delta),
                                    ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(gW.data_ptr()),
@@ -242,8 +290,11 @@ class Plan:
     def jvp(self, W, u0, delta, dW):
         """Tangent of xi for the data tangent dW (same dtype as W)."""
         import torch
-        out = torch.empty((self.nz, self.ny, self.nx), dtype=torch.complex128, device=W.device)
-        d = dW.to(W.dtype).contiguous()
+        self._check_inputs(W, u0)
+        if tuple(dW.shape) != self._w_shape():
+            raise ValueError(f"dW has shape {tuple(dW.shape)}, the plan needs {self._w_shape()}")
+        out = torch.empty(self._xi_shape(), dtype=torch.complex128, device=W.device)
+        d = dW.to(W.device, W.dtype).contiguous()
         _check(lib().fl_invert_jvp(self._h, ctypes.c_void_p(W.data_ptr()),
                                    ctypes.c_void_p(u0.data_ptr()), float(delta),
                                    ctypes.c_void_p(d.data_ptr()), ctypes.c_void_p(out.data_ptr())))
@@ -254,9 +305,11 @@ class Plan:
         (u = u0) for maxit = 0, else u from the BiCGSTAB solve of
         u - omega^2 K(xi u) = u0 (relative residual tol)."""
         import torch
+        _need("xi", xi, (self.nz, self.ny, self.nx), (torch.float64,))
+        _need("u0", u0, self._u_shape(), self._in_dtypes())
         if W_out is None:
-            W_out = torch.empty((self.n_omega, self.nd, self.py, self.px), dtype=torch.complex128,
-                                device=u0.device)
+            W_out = torch.empty(self._w_shape(), dtype=torch.complex128, device=u0.device)
+        _need("W_out", W_out, self._w_shape(), (torch.complex128,))
         _check(lib().fl_forward(self._h, ctypes.c_void_p(xi.data_ptr()),
                                 ctypes.c_void_p(u0.data_ptr()), float(tol), int(maxit),
                                 ctypes.c_void_p(W_out.data_ptr())))
@@ -304,10 +357,8 @@ class Plan:
             if key in cache:
                 self.set_tuning(**cache[key])
                 return self.tuning()
-        shape = (self.nz, self.ny, self.nx)
-        if self.combine == 1:
-            shape = (self.n_omega,) + shape
-        xi = torch.empty(shape, dtype=torch.complex128, device=W.device)
+        self._check_inputs(W, u0)
+        xi = torch.empty(self._xi_shape(), dtype=torch.complex128, device=W.device)
         t = FlTuning()
         _check(lib().fl_plan_tune(self._h, ctypes.c_void_p(W.data_ptr()),
                                   ctypes.c_void_p(u0.data_ptr()), float(delta), int(reps),
@@ -357,6 +408,9 @@ class Graph:
     plan's stream."""
 
     def __init__(self, plan, W, u0, delta, xi_out):
+        import torch
+        plan._check_inputs(W, u0)
+        _need("xi_out", xi_out, plan._xi_shape(), (torch.complex128,))
         self._keep = (plan, W, u0, xi_out)
         h = ctypes.c_void_p()
         _check(lib().fl_graph_create(plan._h, ctypes.c_void_p(W.data_ptr()),
@@ -391,7 +445,13 @@ class Batch:
         self._h = h
 
     def invert(self, Ws, u0s, deltas, xis):
+        import torch
         n = len(self.plans)
+        if not (len(Ws) == len(u0s) == len(deltas) == len(xis) == n):
+            raise ValueError(f"need {n} of each of W, u0, delta and xi")
+        for p, W, u0, xi in zip(self.plans, Ws, u0s, xis):
+            p._check_inputs(W, u0)
+            _need("xi", xi, p._xi_shape(), (torch.complex128,))
         P = ctypes.c_void_p
         W = (P * n)(*[w.data_ptr() for w in Ws])
         U = (P * n)(*[u.data_ptr() for u in u0s])

@@ -147,3 +147,13 @@ def test_tsvd_validation():
     assert st == flayer.FL_EUNSUPPORTED and "nz <= 64" in msg and not out.value
     st, msg, out = _create(regularizer=3)
     assert st == flayer.FL_EINVAL and "regularizer" in msg
+
+
+def test_binding_refuses_host_and_misshaped_tensors():
+    # the argument checks run before any library call (no GPU needed)
+    import torch
+    t = torch.zeros((2, 3), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="GPU"):
+        flayer._need("W", t, (2, 3), (torch.complex128,))
+    with pytest.raises(TypeError):
+        flayer._need("W", np.zeros((2, 3)), (2, 3), (torch.complex128,))

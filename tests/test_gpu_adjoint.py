@@ -170,6 +170,41 @@ def test_chunked_factorization_matches_resident(case, precision):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_orbit_chunks_match_resident(case, precision):
+    """Shared (per-orbit) factorizations taken a few dozen orbits at a time
+    (max_chunk: the forward factorizes chunk after chunk, the derivative
+    passes re-factorize every chunk but the one still in the workspace) give
+    bitwise the xi, VJP and JVP of a plan holding every active orbit at
+    once, and the oracle's xi."""
+    import torch
+    from oracle import invert
+    p, W, u0, d = case
+    g = synth.random_field((p.nz, p.ny, p.nx), (49,))
+    dW = synth.random_field(W.shape, (50,))
+    Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    gt, dWt = torch.from_numpy(g).cuda(), torch.from_numpy(dW).cuda()
+    outs = []
+    for mc in (0, 23):
+        say("orbit chunk", mc, "precision", precision)
+        plan = _plan(p, precision=precision, max_chunk=mc)
+        xi = plan.invert(Wt, ut, d).cpu().numpy()
+        n_orb = plan.factorized_systems()
+        gW, gu = plan.vjp(Wt, ut, d, gt, want_u0=True)
+        jv = plan.jvp(Wt, ut, d, dWt)
+        xi2 = plan.invert(Wt, ut, d).cpu().numpy()
+        torch.cuda.synchronize()
+        outs.append((xi, gW.cpu().numpy(), gu.cpu().numpy(), jv.cpu().numpy(), xi2))
+        plan.close()
+    assert n_orb > 3 * 23, n_orb
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    if precision == 0:
+        ref = invert.invert(p, W, u0, d)
+        say("orbit chunks vs oracle", rel(outs[1][0], ref))
+        assert rel(outs[1][0], ref) <= TOL
+
+
 def test_weighted_derivatives_match_oracle(case):
     import torch
     p, W, u0, d = case

@@ -60,6 +60,32 @@ def test_graph_replays_match_eager(precision, regularizer):
     plan.close()
 
 
+def test_graph_replays_see_later_frequency_weights():
+    """Weights set after the capture apply on replay (the kernels read them
+    from device memory): a weight-0 frequency drops out of the replayed xi
+    exactly as in an eager inversion with those weights."""
+    import torch
+    from paper_1911_10487_amd.flayer import Graph, Plan
+    p = synth.make_problem("graphw", 24, 20, 32, [2 * np.pi, 3 * np.pi], 3, (25, 0), (0.01,),
+                           px=48, py=40)
+    plan = Plan.from_problem(p)
+    W, u0 = _data(p, 0.01)
+    Wb, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    xi_g = torch.zeros((p.nz, p.ny, p.nx), dtype=torch.complex128, device="cuda")
+    g = Graph(plan, Wb, ut, 0.01, xi_g)
+    for wt in ([1.0, 0.0], [0.3, 1.7], None):
+        plan.set_frequency_weights(wt)
+        eager = plan.invert(Wb, ut, 0.01).cpu().numpy()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(xi_g.cpu().numpy(), eager), wt
+        ref = invert.invert(p, W, u0, 0.01, weights=wt)
+        say("graph weights", wt, np.linalg.norm(eager - ref) / np.linalg.norm(ref))
+        assert np.linalg.norm(eager - ref) <= 1e-10 * np.linalg.norm(ref)
+    g.close()
+    plan.close()
+
+
 def test_uneven_batch_matches_eager_and_oracle():
     import torch
     from paper_1911_10487_amd.flayer import Batch, Plan

@@ -264,3 +264,24 @@ def test_thin_layer_solutions_are_minimum_norm_and_meet_the_discrepancy():
         if br[m] == 2:
             r = np.linalg.norm(Am @ V[m] - w[m])
             assert abs(r / (1.5 * dm) - 1.0) <= 1e-9
+
+
+def test_sampled_solve_matches_the_full_solve():
+    # the sampled route (DFT and table at a few wavenumbers) reproduces the
+    # full inversion's per-system outputs at those wavenumbers
+    from oracle import invert as inv
+    p = synth.make_problem("samp", 12, 10, 8, [2 * np.pi, 3 * np.pi], 2, (71, 0), (0.02,),
+                           px=24, py=20)
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, _, _, _ = forward.synthesize(p, xi, u0, born=True)
+    Wd = synth.add_noise(p, W, 0.02)
+    _, st = inv.invert(p, Wd, u0, 0.02, stages=True)
+    ms = np.array([0, 1, 13, 100, 241, 479])
+    for f in range(p.n_omega):
+        V, al, br = inv.solve_sampled(p, f, Wd[f], 0.02, ms)
+        Vref = st["Vhat"][f].reshape(p.nz, -1)[:, ms].T
+        assert np.array_equal(br, st["branch"][f][ms])
+        assert np.linalg.norm(V - Vref) <= 1e-12 * np.linalg.norm(Vref)
+        fin = np.isfinite(al)
+        assert np.allclose(al[fin], st["alpha"][f][ms][fin], rtol=1e-12, atol=0)
