@@ -185,6 +185,25 @@ fl_status fl_invert(fl_plan *plan, const void *W, const void *u0, double delta,
 fl_status fl_invert_vjp(fl_plan *plan, const void *W, const void *u0, double delta,
                         const void *grad_xi, void *grad_W, void *grad_u0);
 
+/*
+ * fl_invert_vjp for callers that cannot allocate device memory at call time
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, but the derivative
+ * workspaces come from a static device array of the library
+ * (FL_NOALLOC_SCRATCH_MB MiB on every GPU the library runs on, held until the
+ * process ends) instead of buffers the plan allocates at its first derivative
+ * call. Nothing is allocated or freed. The plan's workspace must fit:
+ * (4 F nx ny nz + 2 F max(nd, nz) px py) complex128 + F px py doubles, else
+ * FL_EINVAL (e.g. 32x32x16 with one frequency needs 3 MiB). The plan's device
+ * must be current, and stage timing off (FL_EINVAL otherwise). Every call on
+ * one GPU shares that GPU's array and leaves its contents behind (they are
+ * rewritten before use): calls that overlap on one GPU, from any plan or
+ * stream, race. Other errors as fl_invert_vjp.
+ */
+#define FL_NOALLOC_SCRATCH_MB 64
+fl_status fl_invert_vjp_noalloc(fl_plan *plan, const void *W, const void *u0, double delta,
+                                const void *grad_xi, void *grad_W, void *grad_u0);
+
 
 /*
  * Tangent (Jacobian-vector product): dxi ([nz][ny][nx] complex128) for the

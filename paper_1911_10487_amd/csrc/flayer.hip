@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,8 +64,9 @@ unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
-// Workspaces of the derivative calls (allocated by the plan's first
-// derivative call), in one block laid out by adj_layout.
+// Workspaces of the derivative calls: the plan's own (allocated by its
+// first derivative call), or carved from the library's static scratch array
+// by fl_invert_vjp_noalloc.
 struct AdjBufs {
   z64 *xi_tmp = nullptr, *vbar = nullptr, *ubar = nullptr, *vbar2 = nullptr;  // [F][nvox]
   void *Xb = nullptr, *Yb = nullptr;  // [F][max(nd, nz)][N] complex128
@@ -2100,6 +2102,70 @@ fl_status fl_invert(fl_plan* p, const void* W, const void* u0, double delta, voi
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   return p->prec ? invert_impl<float>(p, W, u0, delta, xi_out)
                  : invert_impl<double>(p, W, u0, delta, xi_out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device memory of fl_invert_vjp_noalloc: one array per GPU, which holds it
+// until the process ends. In host code `scratch` names a host-side stand-in,
+// not device memory: kernels get the device address from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = size_t(FL_NOALLOC_SCRATCH_MB) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device.
+fl_status scratch_of_current_device(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FL_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FL_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fl_status fl_invert_vjp_noalloc(fl_plan* p, const void* W, const void* u0, double delta,
+                                const void* grad_xi, void* grad_W, void* grad_u0) {
+  if (!p) return fail(FL_EINVAL, "NULL plan");
+  if (!W || !u0 || !grad_xi || !grad_W) return fail(FL_EINVAL, "NULL array argument");
+  if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
+  RUN(adjoint_supported(p));
+  // stage timing would create events
+  if (p->prof) return fail(FL_EINVAL, "stage timing is on (fl_profile_enable): it creates events");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != p->dev)
+    return fail(FL_EINVAL, "the plan lives on device %d; make it current (device %d is)", p->dev,
+                dev);
+  AdjBufs b;
+  const size_t need = adj_layout(p, nullptr, &b);
+  if (need > kScratchBytes)
+    return fail(FL_EINVAL,
+                "the plan's derivative workspace needs %zu bytes; the allocation-free call has "
+                "%zu (FL_NOALLOC_SCRATCH_MB)", need, kScratchBytes);
+  void* base = nullptr;
+  RUN(scratch_of_current_device(&base));
+  adj_layout(p, (char*)base, &b);
+  return p->prec ? vjp_impl<float>(p, b, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W,
+                                   (z64*)grad_u0)
+                 : vjp_impl<double>(p, b, W, u0, delta, (const z64*)grad_xi, (z64*)grad_W,
+                                    (z64*)grad_u0);
 }
 
 fl_status fl_invert_vjp(fl_plan* p, const void* W, const void* u0, double delta,

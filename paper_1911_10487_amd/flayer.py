@@ -84,6 +84,8 @@ def lib():
     L.fl_invert.restype = I
     L.fl_invert_vjp.argtypes = [P, P, P, D, P, P, P]
     L.fl_invert_vjp.restype = I
+    L.fl_invert_vjp_noalloc.argtypes = [P, P, P, D, P, P, P]
+    L.fl_invert_vjp_noalloc.restype = I
     L.fl_invert_jvp.argtypes = [P, P, P, D, P, P]
     L.fl_invert_jvp.restype = I
     L.fl_forward.argtypes = [P, P, P, D, I, P]
@@ -261,9 +263,11 @@ class Plan:
                                ctypes.c_void_p(xi_out.data_ptr())))
         return xi_out
 
-    def vjp(self, W, u0, delta, grad_xi, want_u0=False, out=None):
-        """Cotangents of W (and u0) for the xi cotangent grad_xi (complex128);
-        into `out` = (gW, gu0 or None) when given."""
+    def vjp(self, W, u0, delta, grad_xi, want_u0=False, noalloc=False, out=None):
+        """Cotangents of W (and u0) for the xi cotangent grad_xi (complex128).
+        noalloc: call fl_invert_vjp_noalloc (workspaces in the library's
+        static device array; the cotangents go into `out` = (gW, gu0 or
+        None) when given, so that the call itself allocates nothing)."""
         import torch
         self._check_inputs(W, u0)
         if out is not None:
@@ -281,7 +285,8 @@ class Plan:
         g = grad_xi
         if not (g.is_cuda and g.dtype == torch.complex128 and g.is_contiguous()):
             g = grad_xi.to(W.device, torch.complex128).contiguous()
-        _check(lib().fl_invert_vjp(self._h, ctypes.c_void_p(W.data_ptr()),
+        fn = lib().fl_invert_vjp_noalloc if noalloc else lib().fl_invert_vjp
+        _check(fn(self._h, ctypes.c_void_p(W.data_ptr()),
                                    ctypes.c_void_p(u0.data_ptr()), float(delta),
                                    ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(gW.data_ptr()),
                                    ctypes.c_void_p(gu.data_ptr() if gu is not None else None)))
