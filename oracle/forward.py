@@ -81,10 +81,12 @@ def fixed_point_field(p, f, xi, u0_f, tol=1e-13, maxit=500):
     return u, maxit
 
 
-def synthesize(p, xi, u0, born=False, tol=1e-12, maxit=500):
+def synthesize(p, xi, u0, born=False, tol=1e-12, maxit=500, zconv=False):
     """Noise-free data W (n_omega, nd, py, px) and the fields (u, v) in X.
 
-    born=True replaces the total field by the incident field (u = u0)."""
+    born=True replaces the total field by the incident field (u = u0);
+    zconv=True applies the data operator by the z-convolution route
+    (model.data_operator_zconv; data planes on X's z-lattice only)."""
     nf = p.n_omega
     W = np.empty((nf, p.nd, p.py, p.px), np.complex128)
     U = np.empty((nf, p.nz, p.ny, p.nx), np.complex128)
@@ -95,6 +97,7 @@ def synthesize(p, xi, u0, born=False, tol=1e-12, maxit=500):
         else:
             u, it, res = total_field(p, f, xi, u0[f], tol, maxit)
         U[f] = u
-        W[f] = model.data_operator(p, f, xi * u)
+        op = model.data_operator_zconv if zconv else model.data_operator
+        W[f] = op(p, f, xi * u)
         info.append((it, res))
     return W, U, xi[None] * U, info

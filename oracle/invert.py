@@ -136,6 +136,89 @@ def solve_sampled(p, f, W_f, delta, ms, tau=TAU, eta=ETA):
     return tikhonov_dp(A, wsys, dm, tau, eta)
 
 
+def solve_joint(p, Whats, delta, tau=TAU, eta=ETA, selected=None, chunk=512,
+                bisect_steps=240, kernel_mode=0, damping=0.0):
+    """Algorithm 2 item 1 with the equations of all frequencies solved as one
+    system (Section 4, comment c: item 1 by least squares over the
+    frequencies). For a wavenumber m the frequencies' systems form the
+    block-diagonal system diag(A_1m, ..., A_Fm) [v_1; ...; v_F] =
+    [w_1m; ...; w_Fm]; it is regularized as one system: one Tikhonov
+    parameter alpha_m, chosen by the discrepancy principle for the stacked
+    data,
+        sum_f ||A_fm v_f - w_fm||^2 = tau^2 sum_f delta_fm^2,
+    with alpha_m >= eta sum_f ||A_fm||_F^2 (the stacked matrix's floor, also
+    the value for noise-free data), and v = 0 at every frequency when
+    sum_f ||w_fm||^2 <= tau^2 sum_f delta_fm^2. The system being block
+    diagonal, v_f is frequency f's Tikhonov solution at alpha_m.
+    Whats: (n_omega, nd, py, px); selected: frequencies taking part (all by
+    default; the others get v = 0). Returns (Vhat (F, nz, py, px), alpha
+    (F, N), branch (F, N)), alpha and branch the same at every selected
+    frequency of a wavenumber."""
+    F, N = p.n_omega, p.px * p.py
+    sel = [f for f in range(F) if selected is None or selected[f]]
+    V = np.zeros((F, N, p.nz), np.complex128)
+    alpha = np.full((F, N), np.inf)
+    branch = np.zeros((F, N), np.int8)
+    if not sel:
+        return V.transpose(0, 2, 1).reshape(F, p.nz, p.py, p.px), alpha, branch
+    tabs = [model.system_table(p, f, kernel_mode, damping) for f in sel]
+    wsys = [Whats[f].reshape(p.nd, N).T for f in sel]
+    dms = np.array([system_noise_level_hat(Whats[f], delta, N) for f in sel])
+    target = tau * tau * float(np.sum(dms * dms))
+    for s0 in range(0, N, chunk):
+        ms = np.arange(s0, min(N, s0 + chunk))
+        S = len(ms)
+        wn2 = sum(np.sum(np.abs(w[ms]) ** 2, axis=1) for w in wsys)
+        live = wn2 > 0 if target == 0 else wn2 > target
+        if not np.any(live):
+            continue
+        ml = ms[live]
+        svd, fro = [], np.zeros(len(ml))
+        for k, f in enumerate(sel):
+            A = model.system_matrices(p, f, tabs[k][0], tabs[k][1], ml)
+            U, sv, Vh = np.linalg.svd(A, full_matrices=False)
+            b = np.einsum("sji,sj->si", U.conj(), wsys[k][ml])
+            rho2 = np.sum(np.abs(wsys[k][ml] - np.einsum("sji,si->sj", U, b)) ** 2, axis=1)
+            svd.append((sv, b, rho2, Vh))
+            fro += np.sum(np.abs(A) ** 2, axis=(1, 2))
+
+        def phi(a):
+            tot = np.zeros(len(a))
+            for sv, b, rho2, _ in svd:
+                t = a[:, None] / (sv * sv + a[:, None])
+                tot += np.sum(t * t * np.abs(b) ** 2, axis=1) + rho2
+            return tot
+
+        amin = eta * fro
+        al = amin.copy()
+        br = np.full(len(ml), FLOOR, np.int8)
+        need = (target > 0) & (phi(amin) < target)
+        if np.any(need):
+            i = np.nonzero(need)[0]
+            lo = np.log(amin[i])
+            smax = np.max([sv[i, 0] for sv, _, _, _ in svd], axis=0)
+            hi = np.log(smax * smax) + 1.0
+            for _ in range(2000):
+                bad = phi(np.exp(hi)) < target
+                if not np.any(bad):
+                    break
+                hi = np.where(bad, hi + 4.0, hi)
+            for _ in range(bisect_steps):
+                mid = 0.5 * (lo + hi)
+                up = phi(np.exp(mid)) >= target
+                hi = np.where(up, mid, hi)
+                lo = np.where(up, lo, mid)
+            al[i] = np.exp(0.5 * (lo + hi))
+            br[i] = ROOT
+        for k, f in enumerate(sel):
+            sv, b, _, Vh = svd[k]
+            coef = sv * b / (sv * sv + al[:, None])
+            V[f, ml] = np.einsum("sij,si->sj", Vh.conj(), coef)
+            alpha[f, ml] = al
+            branch[f, ml] = br
+    return V.transpose(0, 2, 1).reshape(F, p.nz, p.py, p.px), alpha, branch
+
+
 def system_noise_level_hat(What_f, delta, N):
     """The same delta_m computed from the transformed data via Parseval:
     ||W||^2 = ||W^||^2 / N."""
@@ -156,9 +239,16 @@ def invert(p, W, u0, delta, tau=TAU, eta=ETA, combine="lsq", rule="tikhonov",
     den = np.zeros((p.nz, p.ny, p.nx), np.float64)
     per_f = []
     keep = {k: [] for k in ("What", "Vhat", "v", "u", "alpha", "branch")}
+    joint = None
+    if rule == "joint":
+        # item 1 for all frequencies at once (one system per wavenumber)
+        joint = solve_joint(p, np.fft.fft2(W), delta, tau, eta, selected=wt > 0,
+                            kernel_mode=kernel_mode, damping=damping)
     for f in range(nf):
         What = np.fft.fft2(W[f])                                  # item 1 input
-        if wt[f] == 0:
+        if joint is not None:
+            Vhat, alpha, branch = joint[0][f], joint[1][f], joint[2][f]
+        elif wt[f] == 0:
             # not selected: no solve, v = 0
             N = p.px * p.py
             Vhat = np.zeros((p.nz, p.py, p.px), np.complex128)

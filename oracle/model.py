@@ -5,8 +5,10 @@ Follows the paper's Section 1 (eq. 1-4), Section 2 (eq. 5) and Section 5
 functions). Conventions taken here, each a reading of a passage the paper
 leaves open:
 
-* X cells are centred: x_i = (i + 1/2) h, z'_l = (l + 1/2) h, quadrature
-  weight h per direction (midpoint rule for the mu_kl of Section 5.2).
+* X cells are centred: x_i = (i + 1/2) h, z'_l = (l + 1/2) hz, quadrature
+  weight h per horizontal direction and hz vertically (midpoint rule for the
+  mu_kl of Section 5.2; hz = p.dz, equal to h unless the cells are
+  anisotropic, as on the paper's grids).
 * The horizontal plane is a Px x Py torus; X's nx x ny window sits at offset
   o = ((Px - nx) // 2, (Py - ny) // 2). Horizontal distances use the minimum
   image, so for points inside the window the torus sum equals the infinite
@@ -16,10 +18,11 @@ leaves open:
   invariant); the inverse carries 1/(Px Py).
 * Ĝ_zeta[m] = h^2 * DFT(G sampled on the torus at height zeta) (Section 5:
   the discrete G~ comes from the FFT of sampled G).
-* A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu = h).
+* A_m[j, l] = omega^2 * hz * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu = hz).
 * The in-X volume potential of eq. (4)/(9) is the linear convolution of v
-  with kappa[d] = h^3 G(h |d|), d != 0, and at d = 0 the integral of G over
-  the ball of volume h^3 (the paper is silent on the self cell).
+  with kappa[d] = h^2 hz G(|(h d_x, h d_y, hz d_z)|), d != 0, and at d = 0
+  the integral of G over the ball of the cell's volume h^2 hz (the paper is
+  silent on the self cell).
 
 Parity: every function here is pinned (brute-force direct sums, numerical
 quadrature, closed forms) by tests/test_oracle_model.py.
@@ -48,7 +51,7 @@ def window_offset(p):
 
 
 def z_cells(p) -> np.ndarray:
-    return (np.arange(p.nz) + 0.5) * p.h
+    return (np.arange(p.nz) + 0.5) * p.dz
 
 
 def k0_of(p, f: int) -> float:
@@ -135,14 +138,14 @@ def system_table(p, f: int, kernel_mode: int = 0, damping: float = 0.0):
 def system_matrices(p, f: int, tab, idx, ms) -> np.ndarray:
     """A_m for the flat system indices ms (m = my*px + mx): (len(ms), nd, nz).
 
-    A_m[j, l] = omega^2 * h * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = h).
+    A_m[j, l] = omega^2 * hz * Ĝ_{z_j - z'_l}[m] (eq. 8 with mu_kl = hz).
     With ms = None, tab holds the sampled columns already (system_table_at)."""
     om = float(p.omegas[f])
     if ms is None:
         flat = tab
     else:
         flat = tab.reshape(tab.shape[0], -1)[:, np.asarray(ms)]   # (n_zeta, len(ms))
-    return (om * om * p.h) * flat[idx].transpose(2, 0, 1)
+    return (om * om * p.dz) * flat[idx].transpose(2, 0, 1)
 
 
 def embed(p, vX: np.ndarray) -> np.ndarray:
@@ -171,28 +174,50 @@ def data_operator(p, f: int, vX: np.ndarray, tab=None, idx=None) -> np.ndarray:
     for j in range(p.nd):
         for l in range(p.nz):
             What[j] += tab[idx[j, l]] * V[l]
-    return (om * om * p.h) * np.fft.ifft2(What)
+    return (om * om * p.dz) * np.fft.ifft2(What)
 
 
-def self_cell(k0: float, h: float) -> complex:
-    """Integral of G over the ball of volume h^3 centred at the singularity:
-    a = h (3/(4 pi))^(1/3), S = (1 - (1 - i k0 a) e^{i k0 a}) / k0^2."""
-    a = h * (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+def data_operator_zconv(p, f: int, vX: np.ndarray, tab=None, idx=None) -> np.ndarray:
+    """data_operator for data planes on X's z-lattice (the Toeplitz case,
+    idx[j, l] = j - l + nz - 1): the sum over l of Ĝ_{j-l} V_l is a linear
+    convolution along z, evaluated here by a zero-padded FFT along z instead
+    of the double loop over (j, l). Same operator, for grids where the loop
+    is too slow (pinned against data_operator)."""
+    if tab is None:
+        tab, idx = system_table(p, f)
+    jj, ll = np.meshgrid(np.arange(p.nd), np.arange(p.nz), indexing="ij")
+    if not np.array_equal(idx, jj - ll + p.nz - 1):
+        raise ValueError("data_operator_zconv needs data planes on X's z-lattice")
+    om = float(p.omegas[f])
+    V = np.fft.fft2(embed(p, vX))                  # (nz, py, px)
+    L = p.nd + 2 * p.nz - 2                        # linear convolution length
+    T = np.fft.fft(tab, n=L, axis=0)
+    T *= np.fft.fft(V, n=L, axis=0)
+    What = np.fft.ifft(T, axis=0)[p.nz - 1:p.nz - 1 + p.nd]
+    return (om * om * p.dz) * np.fft.ifft2(What)
+
+
+def self_cell(k0: float, h: float, hz: float | None = None) -> complex:
+    """Integral of G over the ball of the cell's volume h^2 hz (h^3 when hz
+    is None) centred at the singularity: a = (3 h^2 hz / (4 pi))^(1/3),
+    S = (1 - (1 - i k0 a) e^{i k0 a}) / k0^2."""
+    vol = h * h * (h if hz is None else hz)
+    a = (3.0 * vol / (4.0 * np.pi)) ** (1.0 / 3.0)
     ika = 1j * k0 * a
     return complex((1.0 - (1.0 - ika) * np.exp(ika)) / (k0 * k0))
 
 
 def conv_kernel(p, k0: float) -> np.ndarray:
     """kappa on the zero-padded (2nz, 2ny, 2nx) torus with minimum-image
-    offsets: h^3 G(h|d|) for d != 0 and the self-cell integral at d = 0."""
-    dz = min_image(2 * p.nz)
-    dy = min_image(2 * p.ny)
-    dx = min_image(2 * p.nx)
-    r = p.h * np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2
-                      + dx[None, None, :] ** 2)
+    offsets: h^2 hz G(|(h d_x, h d_y, hz d_z)|) for d != 0 and the
+    self-cell integral at d = 0."""
+    dz = p.dz * min_image(2 * p.nz)
+    dy = p.h * min_image(2 * p.ny)
+    dx = p.h * min_image(2 * p.nx)
+    r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
     r[0, 0, 0] = 1.0
-    kap = p.h ** 3 * green(r, k0)
-    kap[0, 0, 0] = self_cell(k0, p.h)
+    kap = p.h * p.h * p.dz * green(r, k0)
+    kap[0, 0, 0] = self_cell(k0, p.h, p.dz)
     return kap
 
 

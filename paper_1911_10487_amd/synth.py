@@ -57,6 +57,12 @@ class Problem:
     seed: tuple = ()
     deltas: tuple = (0.01,)
     source: tuple = field(default=(0.0, 0.0, 0.0))
+    hz: float | None = None  # vertical cell size of X; None: h (cubic cells)
+
+    @property
+    def dz(self) -> float:
+        """Vertical cell size of X (h unless the cells are anisotropic)."""
+        return self.h if self.hz is None else self.hz
 
     @property
     def n_omega(self) -> int:
@@ -70,7 +76,7 @@ class Problem:
         """Cell-centre coordinates of X, each shaped (nz, ny, nx)."""
         xs = (np.arange(self.nx) + 0.5) * self.h
         ys = (np.arange(self.ny) + 0.5) * self.h
-        zs = (np.arange(self.nz) + 0.5) * self.h
+        zs = (np.arange(self.nz) + 0.5) * self.dz
         z3, y3, x3 = np.meshgrid(zs, ys, xs, indexing="ij")
         return x3, y3, z3
 
@@ -83,15 +89,19 @@ def _planes(nz: int, nd: int, h: float) -> np.ndarray:
 
 def make_problem(name: str, nx: int, ny: int, nz: int, omegas, n_blobs: int,
                  seed: tuple, deltas=(0.01,), h: float = H, nd: int | None = None,
-                 px: int | None = None, py: int | None = None) -> Problem:
+                 px: int | None = None, py: int | None = None,
+                 hz: float | None = None) -> Problem:
+    """hz: vertical cell size (None: h); the data planes then sit two
+    vertical cells above X, hz apart."""
     nd = nz if nd is None else nd
+    dz = h if hz is None else hz
     return Problem(
         name=name, nx=nx, ny=ny, nz=nz, nd=nd, h=h,
-        planes=_planes(nz, nd, h),
+        planes=_planes(nz, nd, dz),
         omegas=np.asarray(omegas, dtype=np.float64),
         c0=C0, px=px or 2 * nx, py=py or 2 * ny, n_blobs=n_blobs,
         seed=tuple(seed), deltas=tuple(deltas),
-        source=(nx * h / 2.0, ny * h / 2.0, -1.0),
+        source=(nx * h / 2.0, ny * h / 2.0, -1.0), hz=hz,
     )
 
 
@@ -142,7 +152,7 @@ def blob_params(p: Problem):
     rng = np.random.default_rng(list(p.seed) + [0])
     sig = rng.uniform(0.15, 0.4, p.n_blobs)
     amp = rng.uniform(-0.3, 0.3, p.n_blobs)
-    ext = np.array([p.nx * p.h, p.ny * p.h, p.nz * p.h])
+    ext = np.array([p.nx * p.h, p.ny * p.h, p.nz * p.dz])
     cen = np.empty((p.n_blobs, 3))
     for b in range(p.n_blobs):
         lo = np.minimum(2.0 * sig[b], ext / 2.0)

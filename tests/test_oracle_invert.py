@@ -285,3 +285,74 @@ def test_sampled_solve_matches_the_full_solve():
         assert np.linalg.norm(V - Vref) <= 1e-12 * np.linalg.norm(Vref)
         fin = np.isfinite(al)
         assert np.allclose(al[fin], st["alpha"][f][ms][fin], rtol=1e-12, atol=0)
+
+
+def _joint_case(omegas=(2 * np.pi, 3 * np.pi), seed=(73, 0)):
+    p = synth.make_problem("joint", 12, 10, 8, list(omegas), 2, seed, (0.02,), px=24, py=20)
+    xi = synth.contrast(p)
+    u0 = synth.incident_field(p)
+    W, _, _, _ = forward.synthesize(p, xi, u0, born=True)
+    return p, synth.add_noise(p, W, 0.02), u0
+
+
+def test_joint_rule_reduces_to_the_per_system_rule_for_one_frequency():
+    p, Wd, u0 = _joint_case(omegas=(2 * np.pi,))
+    Wh = np.fft.fft2(Wd)
+    Vj, aj, bj = invert.solve_joint(p, Wh, 0.02)
+    Vs, as_, bs = invert.solve_systems(p, 0, Wh[0], 0.02)
+    assert np.array_equal(bj[0], bs)
+    fin = np.isfinite(as_)
+    assert np.allclose(aj[0][fin], as_[fin], rtol=1e-12, atol=0)
+    assert np.linalg.norm(Vj[0] - Vs) <= 1e-12 * np.linalg.norm(Vs)
+
+
+def test_joint_rule_on_a_duplicated_frequency_is_the_per_system_rule():
+    # two identical frequencies with identical data: the stacked discrepancy
+    # and its target both double, so alpha_m is the single system's
+    p, Wd, u0 = _joint_case(omegas=(2 * np.pi, 2 * np.pi))
+    Wd[1] = Wd[0]
+    Wh = np.fft.fft2(Wd)
+    Vj, aj, bj = invert.solve_joint(p, Wh, 0.02)
+    Vs, as_, bs = invert.solve_systems(p, 0, Wh[0], 0.02)
+    for f in range(2):
+        assert np.array_equal(bj[f], bs)
+        assert np.linalg.norm(Vj[f] - Vs) <= 1e-11 * np.linalg.norm(Vs)
+
+
+def test_joint_rule_meets_the_stacked_discrepancy_and_is_tikhonov():
+    from oracle import model
+    p, Wd, u0 = _joint_case()
+    Wh = np.fft.fft2(Wd)
+    N = p.px * p.py
+    Vj, aj, bj = invert.solve_joint(p, Wh, 0.02)
+    roots = np.flatnonzero(bj[0] == 2)
+    assert len(roots) > 5 and np.array_equal(bj[0], bj[1])
+    dms = [invert.system_noise_level_hat(Wh[f], 0.02, N) for f in range(2)]
+    target = 1.5 ** 2 * sum(d * d for d in dms)
+    tabs = [model.system_table(p, f) for f in range(2)]
+    for m in roots[:: max(1, len(roots) // 8)]:
+        res, al = 0.0, aj[0][m]
+        for f in range(2):
+            A = model.system_matrices(p, f, tabs[f][0], tabs[f][1], [m])[0]
+            w = Wh[f].reshape(p.nd, N)[:, m]
+            v = Vj[f].reshape(p.nz, N)[:, m]
+            res += np.linalg.norm(A @ v - w) ** 2
+            # Tikhonov at the joint alpha: augmented least squares
+            aug = np.vstack([A, np.sqrt(al) * np.eye(p.nz)])
+            ref = np.linalg.lstsq(aug, np.concatenate([w, np.zeros(p.nz)]), rcond=None)[0]
+            assert np.linalg.norm(v - ref) <= 1e-9 * np.linalg.norm(ref)
+        assert abs(res - target) <= 1e-10 * target
+    # below the stacked noise level: v = 0 at every frequency
+    zero = np.flatnonzero(bj[0] == 0)
+    assert len(zero) > 0
+    assert not np.any(Vj[:, :, :, :].reshape(2, p.nz, N)[:, :, zero])
+
+
+def test_joint_rule_end_to_end():
+    # invert(rule="joint"): stages consistent with solve_joint, xi finite
+    p, Wd, u0 = _joint_case()
+    xi, st = invert.invert(p, Wd, u0, 0.02, rule="joint", stages=True)
+    Vj, aj, bj = invert.solve_joint(p, np.fft.fft2(Wd), 0.02)
+    assert np.array_equal(st["branch"], bj)
+    assert np.linalg.norm(st["Vhat"] - Vj) == 0.0
+    assert np.all(np.isfinite(xi))

@@ -15,7 +15,8 @@ def _brute_data(p, f, vX):
     om = p.omegas[f]
     k0 = om / p.c0
     ox, oy = model.window_offset(p)
-    zx = (np.arange(p.nz) + 0.5) * p.h
+    hz = p.h if p.hz is None else p.hz
+    zx = (np.arange(p.nz) + 0.5) * hz
     W = np.zeros((p.nd, p.py, p.px), complex)
     for j in range(p.nd):
         for py in range(p.py):
@@ -31,7 +32,7 @@ def _brute_data(p, f, vX):
                             r = np.sqrt((dx * p.h) ** 2 + (dy * p.h) ** 2
                                         + (p.planes[j] - zx[l]) ** 2)
                             acc += -np.exp(1j * k0 * r) / (4 * np.pi * r) * vX[l, iy, ix]
-                W[j, py, px] = om * om * p.h ** 3 * acc
+                W[j, py, px] = om * om * p.h ** 2 * hz * acc
     return W
 
 
@@ -63,7 +64,10 @@ def test_system_matrix_is_the_data_operator_per_wavenumber():
 def _brute_volume(p, f, vX):
     om = p.omegas[f]
     k0 = om / p.c0
-    S = model.self_cell(k0, p.h)
+    hz = p.h if p.hz is None else p.hz
+    # the self cell: the ball of the cell's volume h^2 hz (quadrature-pinned
+    # below)
+    S = model.self_cell(k0, p.h, hz)
     out = np.zeros_like(vX)
     idx = [(l, iy, ix) for l in range(p.nz) for iy in range(p.ny) for ix in range(p.nx)]
     for a in idx:
@@ -73,18 +77,33 @@ def _brute_volume(p, f, vX):
             if not d.any():
                 acc += S * vX[b]
             else:
-                r = p.h * np.linalg.norm(d)
-                acc += p.h ** 3 * (-np.exp(1j * k0 * r) / (4 * np.pi * r)) * vX[b]
+                r = np.sqrt((hz * d[0]) ** 2 + (p.h * d[1]) ** 2 + (p.h * d[2]) ** 2)
+                acc += p.h ** 2 * hz * (-np.exp(1j * k0 * r) / (4 * np.pi * r)) * vX[b]
         out[a] = om * om * acc
     return out
 
 
-def test_volume_potential_matches_direct_sum():
+@pytest.mark.parametrize("hz", [None, 0.05])
+def test_volume_potential_matches_direct_sum(hz):
+    # cubic cells, and flat ones (hz < h, as on the paper's grids)
     p = synth.tiny_problem(nx=3, ny=4, nz=2)
+    p.hz = hz
     vX = synth.random_field((p.nz, p.ny, p.nx), (5, 3))
     u = model.volume_potential(p, 0, vX)
     ub = _brute_volume(p, 0, vX)
     assert np.linalg.norm(u - ub) <= 1e-13 * np.linalg.norm(ub)
+
+
+def test_data_operator_with_flat_cells_matches_direct_sum():
+    # hz != h: planes hz apart on X's vertical lattice, and off it
+    p = synth.make_problem("flat", 3, 2, 3, [2 * np.pi], 2, (99, 1), (0.0,), nd=3, px=8, py=6,
+                           hz=0.06)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 7))
+    for planes in (p.planes.copy(), p.nz * 0.06 + 0.3 + np.array([0.0, 0.011, 0.05])):
+        p.planes = planes
+        W = model.data_operator(p, 0, vX)
+        Wb = _brute_data(p, 0, vX)
+        assert np.linalg.norm(W - Wb) <= 1e-13 * np.linalg.norm(Wb)
 
 
 @pytest.mark.parametrize("k0", [0.7, 2 * np.pi, 5 * np.pi])
@@ -98,6 +117,13 @@ def test_self_cell_is_the_ball_integral(k0):
     assert abs(S - (re + 1j * im)) <= 1e-12 * abs(S)
     # the ball has the cell's volume
     assert abs(4 / 3 * np.pi * a ** 3 - h ** 3) < 1e-15
+    # a flat cell h x h x hz: the ball of volume h^2 hz
+    hz = 0.03
+    a2 = (3 * h * h * hz / (4 * np.pi)) ** (1 / 3)
+    re = integrate.quad(lambda r: (-r * np.exp(1j * k0 * r)).real, 0, a2, epsabs=1e-22, epsrel=1e-13)[0]
+    im = integrate.quad(lambda r: (-r * np.exp(1j * k0 * r)).imag, 0, a2, epsabs=1e-22, epsrel=1e-13)[0]
+    S2 = model.self_cell(k0, h, hz)
+    assert abs(S2 - (re + 1j * im)) <= 1e-12 * abs(S2)
 
 
 def test_self_cell_low_frequency_series():
@@ -255,3 +281,22 @@ def test_sampled_table_matches_the_full_table():
     A = model.system_matrices(p, 0, tab, idx, ms)
     A_s = model.system_matrices(p, 0, tab_s, idx_s, None)
     assert np.linalg.norm(A_s - A) <= 1e-13 * np.linalg.norm(A)
+
+
+def test_zconv_data_operator_matches_the_direct_one():
+    # the z-convolution route against the (j, l) double loop, and against the
+    # brute-force direct sum on a grid small enough for it
+    p = synth.tiny_problem(nx=3, ny=2, nz=3, nd=3, px=8, py=6)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 3))
+    W = model.data_operator_zconv(p, 0, vX)
+    Wb = _brute_data(p, 0, vX)
+    assert np.linalg.norm(W - Wb) <= 1e-13 * np.linalg.norm(Wb)
+    p = synth.make_problem("zc", 10, 8, 12, [2 * np.pi], 2, (5, 4), (0.0,), px=20, py=16)
+    vX = synth.random_field((p.nz, p.ny, p.nx), (5, 4))
+    W1 = model.data_operator(p, 0, vX)
+    W2 = model.data_operator_zconv(p, 0, vX)
+    assert np.linalg.norm(W2 - W1) <= 1e-13 * np.linalg.norm(W1)
+    # off the lattice (a thin layer) it refuses
+    p = synth.thin_problem("zt", 4, 4, 4, [2 * np.pi], 1, (5, 5))
+    with pytest.raises(ValueError):
+        model.data_operator_zconv(p, 0, synth.random_field((p.nz, p.ny, p.nx), (5, 6)))
