@@ -98,7 +98,17 @@ typedef struct {
                           its N systems, alpha >= eta max_m ||A_m||_F^2, v = 0
                           when sum_m ||w_m||^2 <= tau^2 N delta_m^2. Rule 1
                           keeps every phase-scaled bidiagonal (32 nz bytes per
-                          system) and has no derivatives (FL_EUNSUPPORTED) */
+                          system) and has no derivatives (FL_EUNSUPPORTED);
+                          2 = item 1 over all frequencies at once (Section 4,
+                          comment c): per wavenumber m the frequencies'
+                          systems are one block-diagonal system with one
+                          alpha_m, sum_f ||A_fm v_f - w_fm||^2 =
+                          tau^2 sum_f delta_fm^2, alpha_m >= eta sum_f
+                          ||A_fm||_F^2, v = 0 at every frequency when
+                          sum_f ||w_fm||^2 <= tau^2 sum_f delta_fm^2; needs
+                          n_omega <= 8, shared factorizations with every
+                          active orbit in the workspace, regularizer 0; no
+                          derivatives */
   int factor_per_system; /* 0 (default): the kernel G is radial, so A_m is the
                           same for wavenumbers related by the torus symmetries
                           (kx -> -kx, ky -> -ky, and kx <-> ky when px = py):
@@ -126,11 +136,18 @@ typedef struct {
                           leading singular triplets with s_i^2 > eta ||A||_F^2
                           whose residual is within tau delta_m; the ALPHA tap
                           then holds that count. For a thin data layer, and
-                          for square systems with nz <= 64 on the per-call
+                          for the square (or padded) systems on the per-call
                           orbit factorizations (factor_per_system 0,
                           alpha_rule 0, prefactor 0; FL_EUNSUPPORTED
                           otherwise). No derivatives (fl_invert_vjp / _jvp
                           return FL_EUNSUPPORTED) */
+  double hz;           /* vertical cell size of X (Section 5's grids have
+                          different horizontal and vertical steps): X's cells
+                          are h x h x hz, X = [0, nx h] x [0, ny h] x
+                          [0, nz hz], the quadrature weight of eq. (8) is hz
+                          and the volume kernel's h^2 hz; data planes hz apart
+                          with nd = nz give Toeplitz systems. 0 (default) =
+                          h */
 } fl_opts;
 
 void fl_opts_default(fl_opts *opts);
@@ -203,7 +220,6 @@ fl_status fl_invert_vjp(fl_plan *plan, const void *W, const void *u0, double del
 #define FL_NOALLOC_SCRATCH_MB 64
 fl_status fl_invert_vjp_noalloc(fl_plan *plan, const void *W, const void *u0, double delta,
                                 const void *grad_xi, void *grad_W, void *grad_u0);
-
 
 /*
  * Tangent (Jacobian-vector product): dxi ([nz][ny][nx] complex128) for the

@@ -9,13 +9,13 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
-#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/flayer.h"
 #include "adjoint.hpp"
 #include "fft.hpp"
+#include "joint.hpp"
 #include "pointwise.hpp"
 #include "solver.hpp"
 #include "tsvd.hpp"
@@ -77,6 +77,7 @@ struct fl_plan {
   int dev = 0;  // the device current at creation (the plan's memory lives there)
   int nx, ny, nz, nd, px, py, F;
   double h, c0;
+  double hz;  // vertical cell size (h unless fl_opts.hz says otherwise)
   std::vector<double> planes, omegas;
   fl_opts opts;
   hipStream_t st;
@@ -128,6 +129,10 @@ struct fl_plan {
   // thin data layer (nd <= THIN_ND planes at any heights): zt [nd][nz] the
   // height differences of the table planes
   bool thin = false;
+  // a general plane set (planes off X's lattice, or nd != nz, more than
+  // THIN_ND planes): table rows of nd x nz entries, systems zero padded to
+  // the supported size n >= max(nd, nz)
+  bool general = false;
   double* zt = nullptr;
   int *orep = nullptr, *omem = nullptr, *oflag = nullptr, *olist = nullptr, *ocount = nullptr,
       *oslot = nullptr, *ocnt = nullptr, *olist_sys = nullptr;
@@ -138,6 +143,9 @@ struct fl_plan {
   // holds (-1: none known), so that the derivative pass after a forward
   // solve re-factorizes only the chunks it no longer holds
   int* oresident = nullptr;
+  // one alpha per wavenumber over the frequencies (alpha_rule 2): the
+  // wavenumbers whose stacked system needs a solve, and their compaction
+  int *mflag = nullptr, *mlist = nullptr, *mcount = nullptr;
   z64* refl_l = nullptr;
   double* gam_l = nullptr;
   // truncated SVD of the square systems (regularizer 1): per orbit slot the
@@ -318,17 +326,19 @@ fl_status build_tables(fl_plan* p) {
   for (int f = 0; f < F; ++f) {
     const double om = p->omegas[f];
     const double k0 = om / p->c0;
-    const double zeta0 = p->planes[0] - 0.5 * p->h - (p->nz - 1) * p->h;
+    const double hz = p->hz;
+    const double zeta0 = p->planes[0] - 0.5 * hz - (p->nz - 1) * hz;
     z64* gt = p->gtab + (long)f * p->nzeta * N;
     if (p->opts.kernel_mode == 1) {
       // closed-form transform of G at the torus wavenumbers, times omega^2 h
       hipLaunchKernelGGL(k_gclosed, dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt, p->nzeta,
-                         p->px, p->py, p->h, zeta0, p->zt, k0, p->opts.damping, om * om * p->h);
+                         p->px, p->py, p->h, hz, zeta0, p->zt, k0, p->opts.damping, om * om * hz);
       LAUNCHCHK();
     } else {
       // sampled omega^2 h^3 G on every height plane, then FFT2 -> A's entries
       hipLaunchKernelGGL((k_gplanes<double>), dim3(nblk(N * p->nzeta, 256)), dim3(256), 0, p->st, gt,
-                         p->nzeta, p->px, p->py, p->h, zeta0, p->zt, k0, om * om * p->h * p->h * p->h);
+                         p->nzeta, p->px, p->py, p->h, hz, zeta0, p->zt, k0,
+                         om * om * p->h * p->h * hz);
       LAUNCHCHK();
       RUN((run_fft<double, double, double, -1>(
           rows_args(gt, gt, p->tw_x, p->px, (long)p->nzeta * p->py), p->st)));
@@ -340,7 +350,7 @@ fl_status build_tables(fl_plan* p) {
     const int nz2 = 2 * p->nz;
     z64* kt = p->ktab + (long)f * nz2 * N;
     hipLaunchKernelGGL((k_kappa<double>), dim3(nblk(N * nz2, 256)), dim3(256), 0, p->st, kt, nz2,
-                       p->px, p->py, p->h, k0, om * om / ((double)nz2 * (double)N));
+                       p->px, p->py, p->h, hz, k0, om * om / ((double)nz2 * (double)N));
     LAUNCHCHK();
     RUN((run_fft<double, double, double, -1>(rows_args(kt, kt, p->tw_x, p->px, (long)nz2 * p->py),
                                              p->st)));
@@ -424,7 +434,8 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
 #define BD(TR, TC, WPE)                                                                     \
   if (v.tr == TR && v.tc == TC && v.wpe == WPE) {                                           \
     hipLaunchKernelGGL((k_bidiag<TR, TC, NN / TR, NN / TC, double, WPE>), dim3(grid), dim3(TR * TC), 0, \
-                       p->st, p->gsys, p->TP, What, p->N, list, count, chunk0, C, o, resident); \
+                       p->st, p->gsys, p->TP, What, p->N, list, count, chunk0, C, o, resident, \
+                       p->nd, p->nz, (int)p->general);                                         \
     LAUNCHCHK();                                                                            \
     return FL_OK;                                                                           \
   }
@@ -488,7 +499,7 @@ fl_status solve_prepare(fl_plan* p, bool compact) {
   hipStream_t st = p->st;
   RUN(mark(p, FL_STAGE_CLASSIFY));
   hipLaunchKernelGGL(k_classify<double>, dim3(nblk(FN, 256)), dim3(256), 0, st, (const z64*)p->What,
-                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule == 1), freq_weights(p),
+                     p->nd, p->N, p->F, p->thr2, (int)(p->opts.alpha_rule != 0), freq_weights(p),
                      p->wn2, p->flag, p->Vh, (int)(sizeof(T) == 4), p->nz);
   LAUNCHCHK();
   if (!compact) return FL_OK;
@@ -530,6 +541,8 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
   a.count = p->count;
   a.C = p->C;
   a.n = p->n;
+  a.nd = p->nd;
+  a.nzv = p->nz;
   a.N = p->N;
   a.thr2 = p->thr2;
   a.eta = p->opts.eta;
@@ -767,40 +780,117 @@ fl_status run_thin(fl_plan* p) {
   return FL_OK;
 }
 
-// Truncated SVD of the square systems on the orbits' factorizations: the
-// bidiagonalization, the SVD of each factorization's real bidiagonal, then
-// every active system's truncated solve.
+// Truncated SVD of the square systems on the orbits' factorizations, C
+// orbits at a time: the bidiagonalization, the SVD of each factorization's
+// real bidiagonal, then every member system's truncated solve.
 template <typename T>
 fl_status solve_tsvd(fl_plan* p) {
   RUN(group_by_orbit(p));
-  RUN(run_bidiag_orbits<T>(p));
-  const long FO = (long)p->F * p->n_orb;
-  const long FN = (long)p->F * p->N;
-  RUN(mark(p, FL_STAGE_DP));
-  hipLaunchKernelGGL(k_tsvd_svd, dim3((unsigned)std::min<long>(FO, 4096)), dim3(256), 0, p->st,
-                     p->dg, p->sp, p->ocount, (int)FO, p->n, p->opts.eta, p->tsv);
+  hipLaunchKernelGGL(k_mark_resident, dim3(1), dim3(1), 0, p->st, p->oresident, p->ocount, -1);
   LAUNCHCHK();
-  TsvdArgs a{};
-  a.What = (const z64*)p->What;
-  a.list = p->olist_sys;
-  a.count = p->count;
-  a.oslot = p->oslot;
-  a.orep = p->orep;
-  a.refl_l = p->refl_l;
-  a.gam_l = p->gam_l;
-  a.refl = p->refl;
-  a.gam = p->gam;
-  a.fro = p->fro;
-  a.s = p->tsv;
+  const long FN = (long)p->F * p->N;
+  for (long o0 = 0; o0 < orbit_bound(p); o0 += p->C) {
+    RUN(run_bidiag_orbits<T>(p, o0));
+    const int C = (int)std::min<long>(p->C, orbit_bound(p) - o0);
+    RUN(mark(p, FL_STAGE_DP));
+    const unsigned gs = (unsigned)std::min<long>(C, 4096);
+    if (p->n <= 64)
+      hipLaunchKernelGGL((k_tsvd_svd<64>), dim3(gs), dim3(256), 0, p->st, p->dg, p->sp, p->ocount,
+                         (int)o0, C, p->n, p->opts.eta, p->tsv);
+    else
+      hipLaunchKernelGGL((k_tsvd_svd<128>), dim3(gs), dim3(512), 0, p->st, p->dg, p->sp,
+                         p->ocount, (int)o0, C, p->n, p->opts.eta, p->tsv);
+    LAUNCHCHK();
+    TsvdArgs a{};
+    a.What = (const z64*)p->What;
+    a.list = p->olist_sys;
+    a.count = p->count;
+    a.oslot = p->oslot;
+    a.orep = p->orep;
+    a.refl_l = p->refl_l;
+    a.gam_l = p->gam_l;
+    a.refl = p->refl;
+    a.gam = p->gam;
+    a.fro = p->fro;
+    a.s = p->tsv;
+    a.thr2 = p->thr2;
+    a.eta = p->opts.eta;
+    a.n = p->n;
+    a.nd = p->nd;
+    a.nzv = p->nz;
+    a.N = p->N;
+    a.Vh = p->Vh;
+    a.vh_single = sizeof(T) == 4;
+    a.alpha = p->alpha;
+    a.branch = p->branch;
+    a.osys0 = p->osys0;
+    a.ocount = p->ocount;
+    a.slot0 = (int)o0;
+    a.OC = p->C;
+    const unsigned gv = (unsigned)std::min<long>(FN, 16384);
+    if (p->n <= 64)
+      hipLaunchKernelGGL((k_tsvd_solve<64>), dim3(gv), dim3(64), 0, p->st, a);
+    else
+      hipLaunchKernelGGL((k_tsvd_solve<128>), dim3(gv), dim3(64), 0, p->st, a);
+    LAUNCHCHK();
+  }
+  return FL_OK;
+}
+
+// Item 1 with one alpha per wavenumber for the stacked systems of all
+// frequencies: the stacked classification, one factorization per active
+// orbit (all resident), the active wavenumbers compacted, then one wave per
+// wavenumber searches its alpha and solves its frequencies' systems.
+template <typename T>
+fl_status solve_joint(fl_plan* p) {
+  hipStream_t st = p->st;
+  const long N = p->N;
+  hipLaunchKernelGGL(k_joint_classify, dim3(nblk(N, 256)), dim3(256), 0, st, p->wn2, N, p->F,
+                     p->thr2, freq_weights(p), p->flag, p->mflag, p->Vh, (int)(sizeof(T) == 4),
+                     p->nz);
+  LAUNCHCHK();
+  RUN(group_by_orbit(p));
+  hipLaunchKernelGGL(k_mark_resident, dim3(1), dim3(1), 0, st, p->oresident, p->ocount, -1);
+  LAUNCHCHK();
+  RUN(run_bidiag_orbits<T>(p, 0));
+  const int nbm = (int)nblk(N, 1024);
+  hipLaunchKernelGGL(k_block_count, dim3(nbm), dim3(1024), 0, st, p->mflag, N, p->cnt);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, p->cnt, nbm, p->mcount, nullptr, nullptr);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_scatter, dim3(nbm), dim3(1024), 0, st, p->mflag, N, p->cnt, p->mlist);
+  LAUNCHCHK();
+  JointArgs a{};
+  a.mlist = p->mlist;
+  a.mcount = p->mcount;
+  a.flag = p->flag;
+  a.F = p->F;
+  a.n = p->n;
+  a.nd = p->nd;
+  a.nzv = p->nz;
+  a.N = N;
   a.thr2 = p->thr2;
   a.eta = p->opts.eta;
-  a.n = p->n;
-  a.N = p->N;
+  a.oslot = p->oslot;
+  a.orep = p->orep;
+  a.dg = p->dg;
+  a.sp = p->sp;
+  a.fro = p->fro;
+  a.refl = p->refl;
+  a.gam = p->gam;
+  a.refl_l = p->refl_l;
+  a.gam_l = p->gam_l;
+  a.What = (const z64*)p->What;
   a.Vh = p->Vh;
   a.vh_single = sizeof(T) == 4;
   a.alpha = p->alpha;
   a.branch = p->branch;
-  hipLaunchKernelGGL(k_tsvd_solve, dim3((unsigned)std::min<long>(FN, 16384)), dim3(64), 0, p->st, a);
+  RUN(mark(p, FL_STAGE_DP));
+  const unsigned g = (unsigned)std::min<long>(N, 16384);
+  if (p->n <= 64)
+    hipLaunchKernelGGL((k_joint_solve<64>), dim3(g), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_joint_solve<128>), dim3(g), dim3(64), 0, st, a);
   LAUNCHCHK();
   return FL_OK;
 }
@@ -811,11 +901,12 @@ fl_status solve_tsvd(fl_plan* p) {
 template <typename T>
 fl_status solve_systems(fl_plan* p) {
   const long FN = (long)p->F * p->N;
-  p->last_shared = p->opts.alpha_rule == 0 && p->orbits;
+  p->last_shared = p->opts.alpha_rule != 1 && p->orbits;
   RUN(solve_prepare<T>(p, !p->last_shared));
   if (p->thin) return run_thin<T>(p);
   if (p->tsvd_sq) return solve_tsvd<T>(p);
   if (p->opts.alpha_rule == 1) return solve_global<T>(p);
+  if (p->opts.alpha_rule == 2) return solve_joint<T>(p);
   if (p->last_shared && p->prefactored) {
     RUN(group_by_orbit(p));
     return run_dp<T>(p, 0, false, true);
@@ -1053,6 +1144,8 @@ fl_status adjoint_supported(fl_plan* p) {
   if (p->opts.alpha_rule != 0)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for the per-system alpha (alpha_rule 0)");
   if (p->thin) return fail(FL_EUNSUPPORTED, "derivatives are not implemented for a thin data layer");
+  if (p->general)
+    return fail(FL_EUNSUPPORTED, "derivatives need data planes on X's lattice with nd = nz");
   if (p->tsvd_sq)
     return fail(FL_EUNSUPPORTED, "derivatives are implemented for Tikhonov (regularizer 0)");
   return FL_OK;
@@ -1529,35 +1622,44 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   const int py = o.py > 0 ? o.py : 2 * ny;
   if (px < 2 * nx - 1 || py < 2 * ny - 1)
     return fail(FL_EINVAL, "torus %dx%d too small for window %dx%d (need >= 2n-1)", px, py, nx, ny);
-  const double top = nz * h;
+  if (!(o.hz >= 0.0) || !std::isfinite(o.hz)) return fail(FL_EINVAL, "hz must be >= 0 and finite");
+  // vertical cell size (0: cubic cells)
+  const double hz = o.hz > 0.0 ? o.hz : h;
+  const double top = nz * hz;
   bool lattice = true, above = false, below = false;
   for (int j = 0; j < nd; ++j) {
     if (!std::isfinite(planes[j])) return fail(FL_EINVAL, "planes[%d] not finite", j);
     if (planes[j] >= 0.0 && planes[j] <= top)
       return fail(FL_EINVAL, "data plane %d at z=%g lies inside X = [0, %g]", j, planes[j], top);
-    lattice = lattice && std::fabs(planes[j] - (planes[0] + j * h)) <= 1e-9 * h;
+    lattice = lattice && std::fabs(planes[j] - (planes[0] + j * hz)) <= 1e-9 * hz;
     above = above || planes[j] > top;
     below = below || planes[j] < 0.0;
   }
   if (above && below) return fail(FL_EINVAL, "data planes straddle X");
   // a thin data layer: a few planes at any heights (wide systems)
-  const bool thin = nd <= THIN_ND && !(lattice && nd == nz);
-  if (!thin) {
-    if (!lattice) return fail(FL_EINVAL, "data planes must be spaced h apart (nd > %d)", THIN_ND);
-    if (nd != nz)
-      return fail(FL_EUNSUPPORTED, "nd (%d) != nz (%d) needs nd <= %d (thin layer)", nd, nz,
-                  THIN_ND);
-  } else if (nd > nz) {
-    return fail(FL_EUNSUPPORTED, "thin layer: nd (%d) > nz (%d) is not supported", nd, nz);
-  }
+  // Plane sets: nd = nz planes on X's lattice (square Toeplitz systems, A
+  // from one table row of 2 nz - 1 heights) when nz is one of the solver
+  // sizes; a thin layer (nd <= THIN_ND <= ... planes at any heights, nd <=
+  // nz: wide systems); otherwise a general set: A_m of nd x nz entries from
+  // a table of nd nz heights, zero padded to the smallest solver size n >=
+  // max(nd, nz).
+  static const int kSizes[] = {16, 32, 48, 64, 80, 96, 128};
+  auto solver_size = [&](int need) {
+    for (int s : kSizes)
+      if (s >= need) return s;
+    return 0;
+  };
+  const bool toeplitz = lattice && nd == nz && solver_size(nz) == nz;
+  const bool thin = !toeplitz && nd <= THIN_ND && nd <= nz;
+  const bool general = !toeplitz && !thin;
+  if (general && solver_size(std::max(nd, nz)) == 0)
+    return fail(FL_EUNSUPPORTED, "systems of %d data planes x %d X planes: the solver takes at "
+                                 "most 128 of each", nd, nz);
   if (!smooth235(px) || !smooth235(py) || !smooth235(2 * nz) || px > 1024 || py > 1024 ||
       2 * nz > 1024)
     return fail(FL_EUNSUPPORTED, "FFT sizes %d, %d, %d need factors 2, 3, 5 only and <= 1024", px,
                 py, 2 * nz);
   if (thin && nz > 128) return fail(FL_EUNSUPPORTED, "thin layer: nz = %d > 128", nz);
-  if (!thin &&
-      !(nz == 16 || nz == 32 || nz == 48 || nz == 64 || nz == 80 || nz == 96 || nz == 128))
-    return fail(FL_EUNSUPPORTED, "nz = %d: the library solves nz in {16,32,48,64,80,96,128}", nz);
   if (o.precision != 0 && o.precision != 1) return fail(FL_EUNSUPPORTED, "precision must be 0 or 1");
   if (o.kernel_mode != 0 && o.kernel_mode != 1) return fail(FL_EINVAL, "kernel_mode must be 0 or 1");
   if (!(o.damping >= 0) || !std::isfinite(o.damping)) return fail(FL_EINVAL, "damping must be >= 0");
@@ -1579,7 +1681,14 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   }
   if (o.input_dtype != 0 && o.input_dtype != 1) return fail(FL_EINVAL, "input_dtype must be 0 or 1");
   if (o.combine != 0 && o.combine != 1) return fail(FL_EINVAL, "combine must be 0 or 1");
-  if (o.alpha_rule != 0 && o.alpha_rule != 1) return fail(FL_EINVAL, "alpha_rule must be 0 or 1");
+  if (o.alpha_rule < 0 || o.alpha_rule > 2) return fail(FL_EINVAL, "alpha_rule must be 0, 1 or 2");
+  if (o.alpha_rule == 2) {
+    if (o.factor_per_system || o.prefactor || o.regularizer)
+      return fail(FL_EUNSUPPORTED, "alpha_rule 2 needs factor_per_system 0, prefactor 0 and "
+                                   "regularizer 0");
+    if (n_omega > JOINT_FMAX)
+      return fail(FL_EUNSUPPORTED, "alpha_rule 2 stacks at most %d frequencies", JOINT_FMAX);
+  }
   if (o.factor_per_system != 0 && o.factor_per_system != 1)
     return fail(FL_EINVAL, "factor_per_system must be 0 or 1");
   if (o.forward_method != 0 && o.forward_method != 1)
@@ -1589,11 +1698,9 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     return fail(FL_EUNSUPPORTED, "prefactor needs shared factorizations (factor_per_system 0, "
                                  "alpha_rule 0)");
   if (thin && (o.alpha_rule || o.prefactor))
-    return fail(FL_EUNSUPPORTED, "thin layer: alpha_rule 1 and prefactor are not supported");
+    return fail(FL_EUNSUPPORTED, "thin layer: alpha_rule 1 or 2 and prefactor are not supported");
   if (o.regularizer != 0 && o.regularizer != 1) return fail(FL_EINVAL, "regularizer must be 0 or 1");
   if (o.regularizer == 1 && !thin) {
-    if (nz > TSVD_NMAX)
-      return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) of square systems needs nz <= %d", TSVD_NMAX);
     if (o.factor_per_system || o.alpha_rule || o.prefactor)
       return fail(FL_EUNSUPPORTED, "TSVD (regularizer 1) of square systems needs shared "
                                    "factorizations per call (factor_per_system 0, alpha_rule 0, "
@@ -1613,6 +1720,7 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   p->py = py;
   p->F = n_omega;
   p->h = h;
+  p->hz = hz;
   p->c0 = c0;
   p->planes.assign(planes, planes + nd);
   p->omegas.assign(omegas, omegas + n_omega);
@@ -1622,11 +1730,12 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   p->st = (hipStream_t)o.stream;
   p->N = (long)px * py;
   p->thin = thin;
-  p->nzeta = thin ? nd * nz : nd + nz - 1;
-  p->TP = thin ? nd * nz : 2 * nz;
+  p->general = general;
+  p->nzeta = toeplitz ? nd + nz - 1 : nd * nz;
+  p->TP = toeplitz ? 2 * nz : nd * nz;
   p->ox = (px - nx) / 2;
   p->oy = (py - ny) / 2;
-  p->n = thin ? nd : nz;
+  p->n = thin ? nd : general ? solver_size(std::max(nd, nz)) : nz;
   p->prec = o.precision;
   auto bail = [&](fl_status s) {
     fl_plan_destroy(p);
@@ -1651,11 +1760,11 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     }
   }
   PALLOC(p->gtab, F * p->nzeta * N);
-  if (thin) {
+  if (!toeplitz) {
     // height differences z_j - z'_l, index j nz + l
     std::vector<double> zt((size_t)nd * nz);
     for (int j = 0; j < nd; ++j)
-      for (int l = 0; l < nz; ++l) zt[(size_t)j * nz + l] = planes[j] - (l + 0.5) * h;
+      for (int l = 0; l < nz; ++l) zt[(size_t)j * nz + l] = planes[j] - (l + 0.5) * hz;
     PALLOC(p->zt, nd * nz);
     hipError_t e = hipMemcpy(p->zt, zt.data(), zt.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bail(fail(FL_EDEVICE, "heights: %s", hipGetErrorString(e)));
@@ -1728,35 +1837,38 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   // keep the left reflectors: n^2 complex per slot): up to 80 GiB and 40 %
   // of the free device memory, so that every orbit of the 256^2 x 128 grid
   // with seven frequencies (61 GB) has a slot and one launch factorizes them.
-  const bool shared = o.factor_per_system == 0 && o.alpha_rule == 0 && !thin;
+  const bool shared = o.factor_per_system == 0 && o.alpha_rule != 1 && !thin;
+  const int ns = p->n;  // solver system size (nz, or the padded size of a general set)
   {
     size_t fr = 0, tot = 0;
     long budget = 80L << 30;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min<long>(budget, (long)(fr / 5 * 2));
-    const long slot = (long)sizeof(z64) * (tri_size(nz, 1) + (shared ? tri_size(nz, 0) : 0));
+    long slot = (long)sizeof(z64) * (tri_size(ns, 1) + (shared ? tri_size(ns, 0) : 0));
+    // the truncated SVD keeps both singular vector sets of every slot
+    if (o.regularizer == 1 && !thin) slot += 2L * ns * ns * (long)sizeof(double);
     long cap = std::max<long>(1024, budget / slot);
     if (o.max_chunk > 0) cap = std::min<long>(cap, o.max_chunk);
     // the thin solver needs no workspace
     p->C = thin ? 1 : (int)std::min<long>(shared ? FO : FN, cap);
   }
   const long C = p->C;
-  PALLOC(p->dg, C * nz);
-  PALLOC(p->sp, C * nz);
-  PALLOC(p->q, C * nz);
+  PALLOC(p->dg, C * ns);
+  PALLOC(p->sp, C * ns);
+  PALLOC(p->q, C * ns);
   PALLOC(p->fro, C);
   PALLOC(p->wnc, C);
-  PALLOC(p->refl, C * tri_size(nz, 1));
-  PALLOC(p->gam, C * nz);
-  PALLOC(p->bd_d, C * nz);
-  PALLOC(p->bd_e, C * nz);
-  PALLOC(p->bd_dr, C * nz);
+  PALLOC(p->refl, C * tri_size(ns, 1));
+  PALLOC(p->gam, C * ns);
+  PALLOC(p->bd_d, C * ns);
+  PALLOC(p->bd_e, C * ns);
+  PALLOC(p->bd_dr, C * ns);
   PALLOC(p->alpha, FN);
   PALLOC(p->branch, FN);
   if (o.alpha_rule == 1) {
     p->gB = (int)std::min<long>(2048, N);
-    PALLOC(p->gd, FN * nz);
-    PALLOC(p->ge, FN * nz);
-    PALLOC(p->gq, FN * nz);
+    PALLOC(p->gd, FN * ns);
+    PALLOC(p->ge, FN * ns);
+    PALLOC(p->gq, FN * ns);
     PALLOC(p->gfro, FN);
     PALLOC(p->gf, FN);
     PALLOC(p->gstart, F + 1);
@@ -1770,6 +1882,14 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     if (o.prefactor && FO > C)
       return bail(fail(FL_EUNSUPPORTED,
                        "prefactor needs a workspace of all %ld orbits (max_chunk)", FO));
+    if (o.alpha_rule == 2 && FO > C)
+      return bail(fail(FL_EUNSUPPORTED,
+                       "alpha_rule 2 needs a workspace of all %ld orbits (max_chunk)", FO));
+    if (o.alpha_rule == 2) {
+      PALLOC(p->mflag, N);
+      PALLOC(p->mlist, N);
+      PALLOC(p->mcount, 1);
+    }
     if (p->orbits) {
       PALLOC(p->orep, N);
       PALLOC(p->omem, N * 8);
@@ -1781,24 +1901,20 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
       PALLOC(p->olist_sys, FN);
       PALLOC(p->osys0, FO + 1);
       PALLOC(p->oresident, 1);
-      PALLOC(p->refl_l, C * tri_size(nz, 0));
-      PALLOC(p->gam_l, C * nz);
+      PALLOC(p->refl_l, C * tri_size(ns, 0));
+      PALLOC(p->gam_l, C * ns);
       hipError_t e = hipMemcpy(p->orep, orep_h.data(), N * sizeof(int), hipMemcpyHostToDevice);
       if (e == hipSuccess)
         e = hipMemcpy(p->omem, omem_h.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
       if (e != hipSuccess) return bail(fail(FL_EDEVICE, "orbit tables: %s", hipGetErrorString(e)));
     }
     if (o.regularizer == 1 && !thin) {
-      if (!p->orbits || FO > C)
-        return bail(fail(FL_EUNSUPPORTED,
-                         "TSVD (regularizer 1) of square systems needs every orbit of the %ld in "
-                         "one workspace (max_chunk)", FO));
       p->tsvd_sq = true;
-      PALLOC(p->tsv.sig, FO * nz);
-      PALLOC(p->tsv.P, FO * nz * nz);
-      PALLOC(p->tsv.Qc, FO * nz * nz);
-      PALLOC(p->tsv.cdl, FO * nz);
-      PALLOC(p->tsv.dr, FO * nz);
+      PALLOC(p->tsv.sig, C * ns);
+      PALLOC(p->tsv.P, C * ns * ns);
+      PALLOC(p->tsv.Qc, C * ns * ns);
+      PALLOC(p->tsv.cdl, C * ns);
+      PALLOC(p->tsv.dr, C * ns);
     }
   }
 #undef PALLOC
@@ -2074,6 +2190,8 @@ fl_status fl_plan_tune(fl_plan* p, const void* W, const void* u0, double delta, 
   if (!(delta >= 0) || !std::isfinite(delta)) return fail(FL_EINVAL, "delta must be >= 0 and finite");
   if (p->thin) return fail(FL_EUNSUPPORTED, "a thin data layer has no solver schedule to tune");
   if (p->tsvd_sq) return fail(FL_EUNSUPPORTED, "the TSVD solver has no schedule to tune");
+  if (p->opts.alpha_rule == 2)
+    return fail(FL_EUNSUPPORTED, "the one-alpha-per-wavenumber solver has no schedule to tune");
   if (reps < 1) reps = 1;
   fl_tuning keep{p->bd_var, p->bd_grid, p->dp_grid, p->dp_spw};
   RUN(fl_invert(p, W, u0, delta, xi_scratch));
@@ -2229,7 +2347,7 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
   RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));
   hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
-                     w1, nd, nz, N, F, (int)p->thin, w2);
+                     w1, nd, nz, N, F, (int)(p->thin || p->general), w2);
   LAUNCHCHK();
   FftArgs c = cols_args(w2, w2, p->tw_y, py, px, F * nd);
   RUN((run_fft<double, double, double, 1>(c, st)));

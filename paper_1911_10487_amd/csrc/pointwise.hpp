@@ -11,8 +11,9 @@ __device__ __forceinline__ int min_image(int p, int P) { return p <= P / 2 ? p :
 // with minimum-image horizontal offsets. zeta_d = zeta0 + d h.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nzeta, int px, int py,
-                                                 double h, double zeta0, const double* __restrict__ zt,
-                                                 double k0, double wgt) {
+                                                 double h, double hz, double zeta0,
+                                                 const double* __restrict__ zt, double k0,
+                                                 double wgt) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long N = (long)px * py;
   if (idx >= N * nzeta) return;
@@ -20,8 +21,8 @@ __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nz
   long p = idx - (long)d * N;
   int iy = (int)(p / px), ix = (int)(p - (long)iy * px);
   double dx = h * min_image(ix, px), dy = h * min_image(iy, py);
-  // height difference d: zeta0 + d h on X's lattice, else from the list zt
-  double z = zt ? zt[d] : zeta0 + d * h;
+  // height difference d: zeta0 + d hz on X's lattice, else from the list zt
+  double z = zt ? zt[d] : zeta0 + d * hz;
   double r = sqrt(dx * dx + dy * dy + z * z);
   double s, c;
   sincos(k0 * r, &s, &c);
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_gplanes(cx<T>* __restrict__ out, int nz
 // signed DFT index m (the continuous 2D transform of G at the torus
 // wavenumbers).
 __global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzeta, int px, int py,
-                                                 double h, double zeta0,
+                                                 double h, double hz, double zeta0,
                                                  const double* __restrict__ zt, double k0,
                                                  double damping, double wgt) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzet
     sr = -sr;
     si = -si;
   }
-  const double z = fabs(zt ? zt[d] : zeta0 + d * h);
+  const double z = fabs(zt ? zt[d] : zeta0 + d * hz);
   double sn, cs;
   sincos(sr * z, &sn, &cs);
   const double ex = exp(-si * z);
@@ -77,9 +78,10 @@ __global__ __launch_bounds__(256) void k_gclosed(z64* __restrict__ out, int nzet
 // Volume kernel on the (2nz) x py x px torus with minimum-image offsets:
 // h^3 G(h |d|) for d != 0 and the integral of G over the ball of volume h^3 at
 // d = 0, all times wgt.
+// h: horizontal cell size, hz: vertical (cells h x h x hz).
 template <typename T>
 __global__ __launch_bounds__(256) void k_kappa(cx<T>* __restrict__ out, int nz2, int px, int py,
-                                               double h, double k0, double wgt) {
+                                               double h, double hz, double k0, double wgt) {
   long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long N = (long)px * py;
   if (idx >= N * nz2) return;
@@ -89,8 +91,9 @@ __global__ __launch_bounds__(256) void k_kappa(cx<T>* __restrict__ out, int nz2,
   double dz = min_image(kz, nz2), dy = min_image(iy, py), dx = min_image(ix, px);
   double re, im;
   if (kz == 0 && iy == 0 && ix == 0) {
-    // (1 - (1 - i k0 a) e^{i k0 a}) / k0^2, a = h (3 / (4 pi))^(1/3)
-    double a = h * cbrt(3.0 / (4.0 * M_PI));
+    // (1 - (1 - i k0 a) e^{i k0 a}) / k0^2 over the ball of the cell's
+    // volume: a = (3 h^2 hz / (4 pi))^(1/3)
+    double a = cbrt(3.0 * h * h * hz / (4.0 * M_PI));
     double s, c;
     sincos(k0 * a, &s, &c);
     double ka = k0 * a;
@@ -98,10 +101,10 @@ __global__ __launch_bounds__(256) void k_kappa(cx<T>* __restrict__ out, int nz2,
     re = (1.0 - (c + ka * s)) / (k0 * k0);
     im = -(s - ka * c) / (k0 * k0);
   } else {
-    double r = h * sqrt(dx * dx + dy * dy + dz * dz);
+    double r = sqrt(h * h * (dx * dx + dy * dy) + hz * hz * dz * dz);
     double s, c;
     sincos(k0 * r, &s, &c);
-    double a = -h * h * h / (4.0 * M_PI * r);
+    double a = -h * h * hz / (4.0 * M_PI * r);
     re = a * c;
     im = a * s;
   }

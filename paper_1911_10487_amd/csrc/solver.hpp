@@ -505,7 +505,8 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
                                                    const cx<TW>* __restrict__ What, long N,
                                                    const int* __restrict__ list,
                                                    const int* __restrict__ count, int chunk0, int C,
-                                                   BidiagOut o, const int* __restrict__ resident) {
+                                                   BidiagOut o, const int* __restrict__ resident,
+                                                   int nd, int nzv, int gen) {
   constexpr int n = TR * NA;
   static_assert(TR * NA == TC * NB, "square system");
   static_assert(TR == 16 || TR == 32 || TR == 64, "row classes form aligned lane groups");
@@ -529,9 +530,14 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
     const long m = fm % N;
     const int f = (int)(fm / N);
     const z64* trow = gsys + ((long)f * N + m) * tpitch;
-    for (int t = tid; t < 2 * n - 1; t += NT) S.tb[t] = trow[t];
+    if (!gen)
+      for (int t = tid; t < 2 * n - 1; t += NT) S.tb[t] = trow[t];
     __syncthreads();
 
+    // A from the Toeplitz row (planes on X's lattice, nd = nz = n), or, for a
+    // general plane set, entry (i, j) of the nd x nzv table row, zero padded
+    // to n x n (zero rows and columns leave the regularized solution of the
+    // unpadded system unchanged)
     z64 A[NA][NB];
     double fr = 0.0;
 #pragma unroll
@@ -539,7 +545,10 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int i = r + TR * a, j = c + TC * b;
-        A[a][b] = S.tb[i - j + n - 1];
+        if (gen)
+          A[a][b] = (i < nd && j < nzv) ? trow[(long)i * nzv + j] : mk(0.0, 0.0);
+        else
+          A[a][b] = S.tb[i - j + n - 1];
         fr += nrm2(A[a][b]);
       }
     // q = U^H w (starts as w), rows r + TR a kept by the column-class-0
@@ -548,7 +557,8 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
     if (doq && c == 0) {
 #pragma unroll
       for (int a = 0; a < NA; ++a) {
-        const z64 w = cast<double>(What[((long)f * n + r + TR * a) * N + m]);
+        const int row = r + TR * a;
+        const z64 w = row < nd ? cast<double>(What[((long)f * nd + row) * N + m]) : mk(0.0, 0.0);
         S.qv[r + TR * a] = w;
         wq += nrm2(w);
       }
@@ -632,6 +642,8 @@ struct DpArgs {
   const int* list;
   const int* count;
   int chunk0, C, n;
+  int nd, nzv;         // data planes (rows of W^) and X planes (of V^); n for
+                       // square Toeplitz systems, else n >= both (zero padding)
   long N;
   const double* thr2;  // per frequency: (tau delta_m)^2, < 0 for noise-free data
   double eta;
@@ -850,10 +862,12 @@ __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, doub
 // Returns the branch (1 floor, 2 root) and writes alpha, the same on every
 // lane of the group. The groups' control flow may diverge; the evaluations
 // are per lane, and ballots and shuffles stay inside the group.
-template <int W>
-__device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* sd, const double* se,
-                                               const z64* sq, double T, double fro, double eta,
-                                               double* alpha_out) {
+// PHI: the discrepancy as a function of alpha (evaluated per lane); fro:
+// ||A||_F^2 of the (stacked) system, which sets the floor eta ||A||_F^2 and
+// the first spread.
+template <int W, typename PHI>
+__device__ __forceinline__ int dp_choose_alpha_f(int lane_w, PHI phi, double T, double fro,
+                                                 double eta, double* alpha_out) {
   static_assert(W == 16 || W == 32 || W == 64, "a group is 16 or 32 lanes or the wave");
   const int lane = lane_w & (W - 1);  // lane within the group
   const int hb = lane_w & (64 - W);   // the group's first lane in the wave
@@ -874,7 +888,7 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* 
     const double h0 = log(fro) + 1.0;
     double lo = log(amin);
     const double st0 = (h0 - lo) / (double)(W - 1);
-    double ph = phi_fwd(sd, se, sq, n, exp(lane == 0 ? lo : lo + st0 * lane));
+    double ph = phi(exp(lane == 0 ? lo : lo + st0 * lane));
     unsigned long long bal = gballot(ph >= T);
     if (!(bal & 1ull)) {
       br = 2;
@@ -892,7 +906,7 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* 
         // the root lies above: probe upward in steps of 4
         lo = h0;
         flo = gshfl(ph, W - 1);
-        const double pu = phi_fwd(sd, se, sq, n, exp(h0 + 4.0 * (lane + 1)));
+        const double pu = phi(exp(h0 + 4.0 * (lane + 1)));
         const unsigned long long bu = gballot(pu >= T);
         if (bu) {
           const int l1 = __ffsll((long long)bu) - 1;
@@ -927,7 +941,7 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* 
         }
         // W points in (a0, a1]: the last one is a1 unless a1 = hi (phi(hi) is known)
         const double step = (a1 - a0) / (a1 < hi ? (double)W : (double)(W + 1));
-        const double pl = phi_fwd(sd, se, sq, n, exp(a0 + step * (lane + 1)));
+        const double pl = phi(exp(a0 + step * (lane + 1)));
         const unsigned long long b2 = gballot(pl >= T);
         if (b2) {
           const int l1 = __ffsll((long long)b2) - 1;
@@ -978,6 +992,14 @@ __device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* 
   }
   *alpha_out = al;
   return br;
+}
+
+template <int W>
+__device__ __forceinline__ int dp_choose_alpha(int n, int lane_w, const double* sd, const double* se,
+                                               const z64* sq, double T, double fro, double eta,
+                                               double* alpha_out) {
+  return dp_choose_alpha_f<W>(
+      lane_w, [&](double al) { return phi_fwd(sd, se, sq, n, al); }, T, fro, eta, alpha_out);
 }
 
 // Householder reflectors applied to one vector by a group of G lanes
@@ -1078,12 +1100,12 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       }
       if (a.oslot) {
         // q = U^H w = H_{n-2} ... H_0 w from the orbit's left reflectors
-        const z64* w = a.What + (long)f * n * a.N + m;
+        const z64* w = a.What + (long)f * a.nd * a.N + m;
         z64 x[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const int i = gl + G * e;
-          x[e] = i < n ? w[(long)i * a.N] : mk(0.0, 0.0);
+          x[e] = i < a.nd ? w[(long)i * a.N] : mk(0.0, 0.0);
         }
         group_reflect<G, E, RG>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, gl, 0, n - 1, 1,
                                 0);
@@ -1165,10 +1187,10 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       const int fm = a.list[gs];
       if (br == 0) {
         // one alpha per frequency with the data inside the noise level: v^ = 0
-        const long o0 = (long)f * n * a.N + m;
+        const long o0 = (long)f * a.nzv * a.N + m;
         for (int e = 0; e < E; ++e) {
           const int i = gl + G * e;
-          if (i < n) {
+          if (i < a.nzv) {
             if (a.vh_single)
               ((z32*)a.Vh)[o0 + (long)i * a.N] = mk(0.f, 0.f);
             else
@@ -1188,11 +1210,11 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
           y[e] = i < n ? sdr[grp][i] * sy[grp][i] : mk(0.0, 0.0);
         }
         group_reflect<G, E, RG>(y, a.refl + fs * tri_size(n, 1), a.gam + fs * n, n, gl, n - 3, -1, -1, 1);
-        const long o0 = (long)f * n * a.N + m;
+        const long o0 = (long)f * a.nzv * a.N + m;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
           const int i = gl + G * e;
-          if (i < n) {
+          if (i < a.nzv) {
             if (a.vh_single)
               ((z32*)a.Vh)[o0 + (long)i * a.N] = cast<float>(y[e]);
             else

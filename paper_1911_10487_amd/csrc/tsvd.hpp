@@ -21,8 +21,7 @@
 
 namespace fl {
 
-constexpr int TSVD_NMAX = 64;
-constexpr int TSVD_PITCH = TSVD_NMAX + 1;  // LDS column pitch (bank spread)
+constexpr int TSVD_NMAX = 128;  // largest n (the kernels are instantiated for 64 and 128)
 
 struct TsvdOut {
   double* sig;  // [slots][n] singular values of B' (unsorted)
@@ -51,19 +50,24 @@ __device__ __forceinline__ void rr_pair(int m2, int r, int p, int& i, int& j) {
   }
 }
 
-// grid-stride over the factorization slots [0, *count); 256 threads: the
-// eight threads of pair p (lanes 8p .. 8p + 7) share its column dot products
-// and rotations, rows h, h + 8, ... each
-__global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
-                                                  const z64* __restrict__ sp,
-                                                  const int* __restrict__ count, int C, int n,
-                                                  double eta, TsvdOut o) {
-  __shared__ double M[TSVD_NMAX * TSVD_PITCH];  // column c at M[c * PITCH + r]
-  __shared__ double sd[TSVD_NMAX], se[TSVD_NMAX];
-  __shared__ z64 sq[TSVD_NMAX], srr[TSVD_NMAX], sy[TSVD_NMAX], sdr[TSVD_NMAX];
+// grid-stride over the factorization slots [slot0, min(*count, slot0 + C))
+// into workspace slots 0..; 4 NMAX threads: the eight threads of pair p
+// (lanes 8p .. 8p + 7) share its column dot products and rotations, rows
+// h, h + 8, ... each. The dense B' (NMAX x NMAX + 1 doubles: 33 KB at 64,
+// 132 KB at 128) lives in LDS.
+template <int NMAX>
+__global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ dg,
+                                                       const z64* __restrict__ sp,
+                                                       const int* __restrict__ count, int slot0,
+                                                       int C, int n, double eta, TsvdOut o) {
+  constexpr int PITCH = NMAX + 1;  // LDS column pitch (bank spread)
+  constexpr int NT = 4 * NMAX, NWV = NT / 64;
+  __shared__ double M[NMAX * PITCH];  // column c at M[c * PITCH + r]
+  __shared__ double sd[NMAX], se[NMAX];
+  __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
   __shared__ double sth;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int total = min(*count, C);
+  const int total = min(*count - slot0, C);
   const int m2 = n + (n & 1);  // a zero column pads an odd n
   const double tol = 2.2e-16 * n;
   for (int sl = blockIdx.x; sl < total; sl += gridDim.x) {
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
     }
     __syncthreads();
     // sq becomes conj(D_L), sdr D_R
-    if (wv == 0) dp_phase_scale<TSVD_NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
+    if (wv == 0) dp_phase_scale<NMAX>(n, lane, sd, se, sq, srr, sy, sdr);
     __syncthreads();
     if (wv == 0) {
       double f = 0.0;
@@ -84,8 +88,8 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
       f = lanes_sum<64>(f);
       if (lane == 0) sth = eta * f / n;
     }
-    for (int t = tid; t < m2 * TSVD_PITCH; t += 256) {
-      const int c = t / TSVD_PITCH, r = t - c * TSVD_PITCH;
+    for (int t = tid; t < m2 * PITCH; t += NT) {
+      const int c = t / PITCH, r = t - c * PITCH;
       double b = 0.0;
       if (c < n && r < n) b = (r == c) ? sd[c] : (r + 1 == c ? se[r] : 0.0);
       M[t] = b;
@@ -102,15 +106,15 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
     // rows h + 8 s of both columns: the rows past n are zero in M, so
     // every thread handles its eight rows with no bound test and all loads of
     // a round are in flight together
-    constexpr int RPT = TSVD_NMAX / 8;
+    constexpr int RPT = NMAX / 8;
     for (int sweep = 0; sweep < 40; ++sweep) {
       int rot = 0;
       for (int rd = 0; rd < m2 - 1; ++rd) {
         if (p < m2 / 2) {
           int i, j;
           rr_pair(m2, rd, p, i, j);
-          double* Mi = M + i * TSVD_PITCH + h;
-          double* Mj = M + j * TSVD_PITCH + h;
+          double* Mi = M + i * PITCH + h;
+          double* Mj = M + j * PITCH + h;
           double x[RPT], y[RPT];
 #pragma unroll
           for (int s2 = 0; s2 < RPT; ++s2) {
@@ -153,8 +157,8 @@ __global__ __launch_bounds__(256) void k_tsvd_svd(const z64* __restrict__ dg,
     }
     // sigma_j = ||M_j||, P_j = M_j / sigma_j, Q_j = B'^T M_j / sigma_j^2 (zero
     // for a zero column)
-    for (int j = wv; j < n; j += 4) {
-      const double* Mj = M + j * TSVD_PITCH;
+    for (int j = wv; j < n; j += NWV) {
+      const double* Mj = M + j * PITCH;
       double s = 0.0;
       for (int r = lane; r < n; r += 64) s = fma(Mj[r], Mj[r], s);
       s = lanes_sum<64>(s);
@@ -194,102 +198,182 @@ struct TsvdArgs {
   const double* thr2;  // per frequency (tau delta_m)^2, < 0 for noise-free data
   double eta;
   int n;
+  int nd, nzv;         // data planes and X planes (n for square Toeplitz systems)
   long N;
-  void* Vh;            // [F][n][N] output
+  void* Vh;            // [F][nzv][N] output
   int vh_single;
   double* alpha;       // [F N]: the truncation index k
   signed char* branch; // [F N]: 0
+  // orbit chunks (NULL: every active orbit has a slot)
+  const int* osys0;
+  const int* ocount;
+  int slot0, OC;
 };
 
-// grid-stride over the active systems, one wave each
+// One wave per system, each lane holding entries lane + 64 e (E of them);
+// with orbit chunks (osys0 not NULL) the systems of compacted orbits
+// [slot0, slot0 + OC), factorizations in workspace slots oslot - slot0.
+template <int NMAX>
 __global__ __launch_bounds__(64) void k_tsvd_solve(TsvdArgs a) {
-  __shared__ z64 sqp[TSVD_NMAX];
-  __shared__ z64 sc[TSVD_NMAX];
-  __shared__ double ssig[TSVD_NMAX], sb2[TSVD_NMAX];
+  constexpr int E = NMAX / 64;
+  __shared__ z64 sqp[NMAX];
+  __shared__ z64 sc[NMAX], sbeta[NMAX];
+  __shared__ double ssig[NMAX], sb2[NMAX];
+  __shared__ int slead[NMAX];
   const int lane = threadIdx.x, n = a.n;
   const int total = *a.count;
-  const bool on = lane < n;
-  for (int sl = blockIdx.x; sl < total; sl += gridDim.x) {
-    const int fm = a.list[sl];
+  int c0;
+  const int nsys = launch_range(a.osys0, a.ocount, a.slot0, a.OC, 0, total, total, &c0);
+  bool on[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) on[e] = lane + 64 * e < n;
+  for (int sl = blockIdx.x; sl < nsys; sl += gridDim.x) {
+    const int fm = a.list[c0 + sl];
     const int f = (int)(fm / a.N);
     const long m = fm - (long)f * a.N;
-    const long fs = a.oslot[(long)f * a.N + a.orep[m]];
+    const long fs = a.oslot[(long)f * a.N + a.orep[m]] - a.slot0;
     // q = U^H w
-    z64 x[1];
-    x[0] = on ? a.What[((long)f * n + lane) * a.N + m] : mk(0.0, 0.0);
-    group_reflect<64, 1, 4>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, lane, 0, n - 1, 1, 0);
-    const z64 qp = on ? a.s.cdl[fs * n + lane] * x[0] : mk(0.0, 0.0);
-    const double sg = on ? a.s.sig[fs * n + lane] : 0.0;
-    sqp[lane] = qp;
-    ssig[lane] = sg;
+    z64 x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      x[e] = lane + 64 * e < a.nd ? a.What[((long)f * a.nd + lane + 64 * e) * a.N + m]
+                                  : mk(0.0, 0.0);
+    group_reflect<64, E, 4>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, lane, 0, n - 1,
+                            1, 0);
+    z64 qp[E];
+    double sg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = lane + 64 * e;
+      qp[e] = on[e] ? a.s.cdl[fs * n + i] * x[e] : mk(0.0, 0.0);
+      sg[e] = on[e] ? a.s.sig[fs * n + i] : 0.0;
+      if (on[e]) {
+        sqp[i] = qp[e];
+        ssig[i] = sg[e];
+      }
+    }
     __syncthreads();
-    // beta_j = sum_r P[r][j] q'_r (lane j)
-    z64 beta = mk(0.0, 0.0);
+    // beta_j = sum_r P[r][j] q'_r (j = lane + 64 e)
     const double* P = a.s.P + fs * n * n;
-    if (on)
-      for (int r = 0; r < n; ++r) {
-        const double pr = P[(long)r * n + lane];
-        const z64 qr = sqp[r];
-        beta.x = fma(pr, qr.x, beta.x);
-        beta.y = fma(pr, qr.y, beta.y);
-      }
-    const double b2 = on ? nrm2(beta) : 0.0;
-    // rank of sigma_j in decreasing order (ties by index)
-    int rank = 0;
-    if (on)
-      for (int i = 0; i < n; ++i) {
-        const double si = ssig[i];
-        rank += (si > sg || (si == sg && i < lane)) ? 1 : 0;
-      }
-    if (on) sb2[rank] = b2;
-    const double wn = lanes_sum<64>(nrm2(qp));
+    z64 beta[E];
+    double b2[E];
+    int rank[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int j = lane + 64 * e;
+      z64 bt = mk(0.0, 0.0);
+      if (on[e])
+        for (int r = 0; r < n; ++r) {
+          const double pr = P[(long)r * n + j];
+          const z64 qr = sqp[r];
+          bt.x = fma(pr, qr.x, bt.x);
+          bt.y = fma(pr, qr.y, bt.y);
+        }
+      beta[e] = bt;
+      b2[e] = on[e] ? nrm2(bt) : 0.0;
+      // rank of sigma_j in decreasing order (ties by index)
+      int rk = 0;
+      if (on[e])
+        for (int i = 0; i < n; ++i) {
+          const double si = ssig[i];
+          rk += (si > sg[e] || (si == sg[e] && i < j)) ? 1 : 0;
+        }
+      rank[e] = rk;
+      if (on[e]) sb2[rk] = b2[e];
+    }
     const double fro = a.fro[fs];
-    const int kmax = __popcll(__ballot(on && sg * sg > a.eta * fro));
-    // the nb columns with sigma^2 >= 2 eta ||A||_F^2 / n (at least the
-    // factorization's threshold for rotating a pair) are orthonormal to
-    // every other column; the rest, zero columns included, may not be
-    // orthogonal among themselves, so their share of ||q'||^2 (with the part
-    // outside the range) is taken as a whole: ||q'||^2 minus the leading share
-    const int nb = __popcll(__ballot(on && sg * sg >= 2.0 * a.eta * fro / n));
-    const double bh = lanes_sum<64>((on && rank < nb) ? b2 : 0.0);
-    const double gs = nb < n ? fmax(0.0, wn - bh) : 0.0;
+    int kmax = 0, nb = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      kmax += __popcll(__ballot(on[e] && sg[e] * sg[e] > a.eta * fro));
+      // the nb columns with sigma^2 >= 2 eta ||A||_F^2 / n (at least the
+      // factorization's threshold for rotating a pair) are orthonormal to
+      // every other column
+      nb += __popcll(__ballot(on[e] && sg[e] * sg[e] >= 2.0 * a.eta * fro / n));
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (on[e]) {
+        sbeta[lane + 64 * e] = beta[e];
+        slead[lane + 64 * e] = rank[e] < nb;
+      }
     __syncthreads();
-    // residual after keeping the k = lane leading triplets: the |beta|^2 of
-    // the rest of the leading nb summed from the smallest singular value up,
-    // plus that share (kmax <= nb, so every count that can be chosen sees
-    // the leading terms one by one)
-    double acc = 0.0;
-    for (int t = nb - 1; t >= lane; --t) acc += sb2[t];
-    const double tail = acc + gs;
+    // The other columns, zero columns included, may not be orthogonal among
+    // themselves, so their share of ||q'||^2 (with the part outside the
+    // range) is taken as a whole, as the squared norm of the residual
+    // r = q' - sum_lead beta_j P_j (formed explicitly: a difference of
+    // squared norms would carry an error of u ||q'||^2, far above
+    // (tau delta_m)^2 for small delta).
+    double gs = 0.0;
+    if (nb < n) {
+      double rr = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        z64 r = qp[e];
+        if (on[e])
+          for (int j = 0; j < n; ++j)
+            if (slead[j]) {
+              const double pr = P[(long)(lane + 64 * e) * n + j];
+              const z64 bj = sbeta[j];
+              r.x = fma(-pr, bj.x, r.x);
+              r.y = fma(-pr, bj.y, r.y);
+            }
+        rr += on[e] ? nrm2(r) : 0.0;
+      }
+      gs = lanes_sum<64>(rr);
+    }
+    // residual after keeping the k leading triplets (k = lane + 64 e): the
+    // |beta|^2 of the rest of the leading nb summed from the smallest
+    // singular value up, plus that share (kmax <= nb, so every count that
+    // can be chosen sees the leading terms one by one)
     // noise-free data: the residual must vanish
     const double T = fmax(a.thr2[f], 0.0);
-    const unsigned long long okb = __ballot(on && tail <= T);
-    int k = okb ? __ffsll((long long)okb) - 1 : n;
+    int k = n;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+      const int kk = lane + 64 * e;
+      double acc = 0.0;
+      for (int t = nb - 1; t >= kk; --t) acc += sb2[t];
+      const unsigned long long okb = __ballot(kk < n && acc + gs <= T);
+      if (okb) k = 64 * e + __ffsll((long long)okb) - 1;
+    }
     k = min(k, kmax);
-    const bool keep = on && rank < k;
-    sc[lane] = (keep && sg > 0.0) ? mk(beta.x / sg, beta.y / sg) : mk(0.0, 0.0);
-    __syncthreads();
-    // y = D_R Q c (lane r), then v^ = V y
-    z64 y[1];
-    y[0] = mk(0.0, 0.0);
-    const double* Qc = a.s.Qc + fs * n * n;
-    if (on) {
-      for (int j = 0; j < n; ++j) {
-        const double qj = Qc[(long)j * n + lane];
-        const z64 cj_ = sc[j];
-        y[0].x = fma(qj, cj_.x, y[0].x);
-        y[0].y = fma(qj, cj_.y, y[0].y);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (on[e]) {
+        const bool keep = rank[e] < k;
+        sc[lane + 64 * e] =
+            (keep && sg[e] > 0.0) ? mk(beta[e].x / sg[e], beta[e].y / sg[e]) : mk(0.0, 0.0);
       }
-      y[0] = a.s.dr[fs * n + lane] * y[0];
+    __syncthreads();
+    // y = D_R Q c (entry r = lane + 64 e), then v^ = V y
+    z64 y[E];
+    const double* Qc = a.s.Qc + fs * n * n;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = lane + 64 * e;
+      y[e] = mk(0.0, 0.0);
+      if (on[e]) {
+        for (int j = 0; j < n; ++j) {
+          const double qj = Qc[(long)j * n + r];
+          const z64 cj_ = sc[j];
+          y[e].x = fma(qj, cj_.x, y[e].x);
+          y[e].y = fma(qj, cj_.y, y[e].y);
+        }
+        y[e] = a.s.dr[fs * n + r] * y[e];
+      }
     }
-    group_reflect<64, 1, 4>(y, a.refl + fs * tri_size(n, 1), a.gam + fs * n, n, lane, n - 3, -1, -1, 1);
-    if (on) {
-      const long o = ((long)f * n + lane) * a.N + m;
-      if (a.vh_single)
-        ((z32*)a.Vh)[o] = cast<float>(y[0]);
-      else
-        ((z64*)a.Vh)[o] = y[0];
-    }
+    group_reflect<64, E, 4>(y, a.refl + fs * tri_size(n, 1), a.gam + fs * n, n, lane, n - 3, -1,
+                            -1, 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (lane + 64 * e < a.nzv) {
+        const long o = ((long)f * a.nzv + lane + 64 * e) * a.N + m;
+        if (a.vh_single)
+          ((z32*)a.Vh)[o] = cast<float>(y[e]);
+        else
+          ((z64*)a.Vh)[o] = y[e];
+      }
     if (lane == 0) {
       a.alpha[fm] = (double)k;
       a.branch[fm] = 0;

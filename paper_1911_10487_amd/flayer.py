@@ -41,6 +41,7 @@ class FlOpts(ctypes.Structure):
         ("alpha_rule", ctypes.c_int), ("factor_per_system", ctypes.c_int),
         ("forward_method", ctypes.c_int), ("prefactor", ctypes.c_int),
         ("regularizer", ctypes.c_int),
+        ("hz", ctypes.c_double),
     ]
 
 
@@ -171,7 +172,7 @@ class Plan:
     def __init__(self, nx, ny, nz, nd, h, planes, omegas, c0=1.0, px=0, py=0, precision=0,
                  tau=1.5, eta=1e-10, combine=0, input_dtype=0, stream=None, max_chunk=0,
                  kernel_mode=0, damping=0.0, alpha_rule=0, factor_per_system=0,
-                 forward_method=0, prefactor=0, regularizer=0):
+                 forward_method=0, prefactor=0, regularizer=0, hz=0.0):
         o = default_opts()
         o.px, o.py, o.precision = px, py, precision
         o.tau, o.eta, o.combine, o.input_dtype = tau, eta, combine, input_dtype
@@ -180,6 +181,7 @@ class Plan:
         o.alpha_rule, o.factor_per_system = alpha_rule, factor_per_system
         o.forward_method, o.prefactor = forward_method, prefactor
         o.regularizer = regularizer
+        o.hz = hz
         o.stream = stream if stream is not None else _stream_handle()
         planes = np.ascontiguousarray(planes, np.float64)
         omegas = np.ascontiguousarray(omegas, np.float64)
@@ -221,6 +223,8 @@ class Plan:
 
     @classmethod
     def from_problem(cls, p, **kw):
+        if getattr(p, "hz", None) is not None:
+            kw.setdefault("hz", p.hz)
         return cls(p.nx, p.ny, p.nz, p.nd, p.h, p.planes, p.omegas, p.c0, p.px, p.py, **kw)
 
     def info(self) -> FlPlanInfo:

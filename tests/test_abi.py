@@ -58,11 +58,10 @@ def _create(nx=32, ny=32, nz=16, nd=16, h=0.125, planes=None, omegas=(2 * np.pi,
     (dict(omegas=(0.0,)), flayer.FL_EINVAL, "omegas"),
     (dict(omegas=(np.nan,)), flayer.FL_EINVAL, "omegas"),
     (dict(planes=1.0 + 0.125 * np.arange(16)), flayer.FL_EINVAL, "inside X"),
-    (dict(planes=2.25 + 0.13 * np.arange(16)), flayer.FL_EINVAL, "spaced h"),
     (dict(px=40), flayer.FL_EINVAL, "too small"),
-    (dict(nd=8, planes=2.25 + 0.125 * np.arange(8)), flayer.FL_EUNSUPPORTED, "nd"),
     (dict(px=77), flayer.FL_EUNSUPPORTED, "FFT sizes"),
-    (dict(nz=20, nd=20, planes=3.0 + 0.125 * np.arange(20)), flayer.FL_EUNSUPPORTED, "nz"),
+    (dict(nz=160, nd=160, planes=21.0 + 0.125 * np.arange(160)), flayer.FL_EUNSUPPORTED,
+     "at most 128"),
     (dict(precision=7), flayer.FL_EUNSUPPORTED, "precision"),
 ])
 def test_invalid_arguments_are_rejected_on_the_host(kw, status, needle):
@@ -104,8 +103,14 @@ def test_closed_form_kernel_needs_damping_on_the_k0_circle():
 
 
 def test_alpha_rule_is_validated():
-    st, msg, out = _create(alpha_rule=2)
+    st, msg, out = _create(alpha_rule=3)
     assert st == flayer.FL_EINVAL and "alpha_rule" in msg and not out.value
+    # one alpha per wavenumber over the frequencies: shared factorizations,
+    # Tikhonov, at most 8 frequencies
+    for kw in (dict(factor_per_system=1), dict(prefactor=1), dict(regularizer=1),
+               dict(omegas=np.linspace(1.0, 9.0, 9))):
+        st, msg, out = _create(alpha_rule=2, **kw)
+        assert st == flayer.FL_EUNSUPPORTED and "alpha_rule 2" in msg and not out.value, kw
 
 
 def test_forward_method_is_validated():
@@ -130,21 +135,20 @@ def test_thin_layer_validation():
     assert st == flayer.FL_EUNSUPPORTED and "thin" in msg and not out.value
     st, msg, out = _create(nd=2, planes=thin, prefactor=1)
     assert st == flayer.FL_EUNSUPPORTED and not out.value
-    st, msg, out = _create(nz=2, nd=3, planes=3.0 + 0.01 * np.arange(3))
-    assert st == flayer.FL_EUNSUPPORTED and "nd (3) > nz (2)" in msg
     st, msg, out = _create(nd=2, planes=np.array([-1.0, 3.0]))
     assert st == flayer.FL_EINVAL and "straddle" in msg
-    st, msg, out = _create(nd=6, planes=3.0 + 0.01 * np.arange(6))
-    assert st == flayer.FL_EINVAL and "spaced h" in msg
+    # a general plane set (off the lattice, or nd != nz) is padded to a solver
+    # size of at most 128
+    st, msg, out = _create(nd=130, planes=3.0 + 0.01 * np.arange(130))
+    assert st == flayer.FL_EUNSUPPORTED and "at most 128" in msg and not out.value
 
 
 def test_tsvd_validation():
-    # square systems: TSVD runs on the per-call orbit factorizations only
+    # square systems (any supported nz): TSVD runs on the per-call orbit
+    # factorizations only
     for kw in (dict(factor_per_system=1), dict(alpha_rule=1), dict(prefactor=1)):
         st, msg, out = _create(regularizer=1, **kw)
         assert st == flayer.FL_EUNSUPPORTED and "TSVD" in msg and not out.value, kw
-    st, msg, out = _create(nz=80, nd=80, planes=10.25 + 0.125 * np.arange(80), regularizer=1)
-    assert st == flayer.FL_EUNSUPPORTED and "nz <= 64" in msg and not out.value
     st, msg, out = _create(regularizer=3)
     assert st == flayer.FL_EINVAL and "regularizer" in msg
 
@@ -157,3 +161,12 @@ def test_binding_refuses_host_and_misshaped_tensors():
         flayer._need("W", t, (2, 3), (torch.complex128,))
     with pytest.raises(TypeError):
         flayer._need("W", np.zeros((2, 3)), (2, 3), (torch.complex128,))
+
+
+def test_vertical_cell_size_is_validated():
+    for hz in (-0.1, float("nan"), float("inf")):
+        st, msg, out = _create(hz=hz)
+        assert st == flayer.FL_EINVAL and "hz" in msg and not out.value
+    # planes inside X = [0, nz hz] are refused with the vertical size
+    st, msg, out = _create(hz=0.2, planes=2.25 + 0.125 * np.arange(16))
+    assert st == flayer.FL_EINVAL and "inside X" in msg

@@ -9,12 +9,11 @@ floor where that is higher: the 320^2 and 512^2 tori, where swapping the
 oracle's FFT library alone moves xi by 0.6-1.0e-10), mixed within 1e-4 on
 xi.
 
-Full sizes: the 5-frequency configuration against the whole oracle; the
-uneven batch (mixed) against per-instance FP64 GPU plans and its two
-smaller instances against the oracle; the 256x256x128 configuration by
-properties that hold at any size (mixed within 1e-4 of the FP64 GPU path,
-the JVP / VJP dot-product identity, central differences of the FP64 path,
-monotone power iteration). The oracle never sees a value the GPU computed.
+Every bidiagonalization schedule of the n = 80 and n = 96 systems against
+the oracle. Full sizes (the oracle comparisons are in test_gpu_fullsize.py):
+the 256x256x128 configuration by properties that hold at any size (mixed
+within 1e-4 of the FP64 GPU path, the JVP / VJP dot-product identity,
+central differences of the FP64 path, monotone power iteration).
 """
 import sys
 
@@ -136,67 +135,45 @@ def test_configuration_kernel_shapes_match_oracle(shape, monkeypatch):
     assert e <= MIXED_TOL
 
 
-@pytest.mark.slow
-def test_five_frequency_configuration_full_size():
-    p = synth.workload("multi5")[0]
-    delta = p.deltas[0]
-    say("multi5", p.nx, p.nz, "omegas", p.n_omega, "delta", delta)
-    W, u0 = born(p, delta)
-    ref_xi, ref = invert.invert(p, W, u0, delta, stages=True)
-    xi, st = gpu_invert(p, W, u0, delta)
-    check_fp64(ref_xi, ref, xi, st)
-    xm, stm = gpu_invert(p, W, u0, delta, precision=1)
-    errs = {k: rel(stm[k], ref[k]) for k in ("Vhat", "v", "u")}
-    errs["xi"] = rel(xm, ref_xi)
-    say("multi5 mixed errors", errs)
-    assert errs["xi"] <= MIXED_TOL
-
-
-@pytest.mark.slow
-def test_uneven_batch_full_size():
+@pytest.mark.parametrize("name", ["n80", "n96"])
+def test_every_solver_schedule_matches_oracle(name, monkeypatch):
+    """Each bidiagonalization schedule (thread grid and register budget) of
+    the n = 80 and n = 96 systems against the oracle: the schedules sum in
+    different orders, so they agree with it to rounding, not bitwise."""
     import torch
-    from paper_1911_10487_amd.flayer import Batch, Plan
-    insts = synth.workload("uneven")
-    data = []
-    for p in insts:
-        say("instance", p.name, p.nx, p.nz, "delta", p.deltas[0])
-        if p.nz <= 48:
-            W, u0 = born(p, p.deltas[0])
-        else:
-            # the two larger instances: data from the GPU's Born operator (no
-            # oracle involved in their checks)
-            g = Plan.from_problem(p)
-            Wt = g.forward(torch.from_numpy(synth.contrast(p)).cuda(),
-                           torch.from_numpy(synth.incident_field(p)).cuda())
-            torch.cuda.synchronize()
-            W = synth.add_noise(p, Wt.cpu().numpy(), p.deltas[0])
-            g.close()
-            del Wt
-            u0 = synth.incident_field(p)
-        data.append((W, u0))
-    plans = [Plan.from_problem(p, precision=1) for p in insts]
-    Ws = [torch.from_numpy(W).cuda() for W, _ in data]
-    us = [torch.from_numpy(u).cuda() for _, u in data]
-    xis = [torch.empty((p.nz, p.ny, p.nx), dtype=torch.complex128, device="cuda") for p in insts]
-    b = Batch(plans)
-    b.invert(Ws, us, [p.deltas[0] for p in insts], xis)
-    torch.cuda.synchronize()
-    b.close()
-    mixed = [x.cpu().numpy() for x in xis]
-    for pl in plans:
-        pl.close()
-    for i, p in enumerate(insts):
-        p64 = Plan.from_problem(p)
-        x64 = p64.invert(Ws[i], us[i], p.deltas[0]).cpu().numpy()
-        p64.close()
-        e = rel(mixed[i], x64)
-        say(p.name, "batched mixed vs FP64 GPU", e)
-        assert e <= MIXED_TOL
-        if p.nz <= 48:
-            ref = invert.invert(p, data[i][0], data[i][1], p.deltas[0])
-            e64, em = rel(x64, ref), rel(mixed[i], ref)
-            say(p.name, "vs oracle: FP64", e64, "mixed", em)
-            assert e64 <= TOL and em <= MIXED_TOL
+    from paper_1911_10487_amd.flayer import Plan
+    shape = next(s for s in SHAPES if s[0] == name)
+    _, nx, ny, nz, px, py, om, seed, what = shape
+    p = synth.make_problem(name, nx, ny, nz, TWO_PI * np.array(om), 3, (seed, nz),
+                           (SHAPE_DELTA,), px=px, py=py)
+    d = SHAPE_DELTA
+    W, u0 = born(p, d)
+    ref_xi, ref = invert.invert(p, W, u0, d, stages=True)
+    floor = oracle_rounding_floor(p, W, u0, d, ref_xi, ref, monkeypatch)
+    plan = Plan.from_problem(p)
+    variants = plan.tuning_variants()
+    plan.close()
+    assert len(variants) >= 2
+    for v, sched in enumerate(variants):
+        say(name, "schedule", v, sched)
+        plan = Plan.from_problem(p)
+        plan.set_tuning(bidiag_variant=v)
+        xi = plan.invert(torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda(), d)
+        torch.cuda.synchronize()
+        from paper_1911_10487_amd.flayer import (TAP_ALPHA, TAP_BRANCH, TAP_U, TAP_V, TAP_VHAT,
+                                                 TAP_WHAT)
+        F, N = p.n_omega, p.px * p.py
+        st = {
+            "What": plan.tap(TAP_WHAT, np.complex128, (F, p.nd, p.py, p.px)),
+            "Vhat": plan.tap(TAP_VHAT, np.complex128, (F, p.nz, p.py, p.px)),
+            "v": plan.tap(TAP_V, np.complex128, (F, p.nz, p.ny, p.nx)),
+            "u": plan.tap(TAP_U, np.complex128, (F, p.nz, p.ny, p.nx)),
+            "alpha": plan.tap(TAP_ALPHA, np.float64, (F, N)),
+            "branch": plan.tap(TAP_BRANCH, np.int8, (F, N)),
+        }
+        xi = xi.cpu().numpy()
+        plan.close()
+        check_fp64(ref_xi, ref, xi, st, floor)
 
 
 @pytest.mark.slow

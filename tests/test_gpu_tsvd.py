@@ -10,7 +10,7 @@ import pytest
 from oracle import invert
 from paper_1911_10487_amd import synth
 
-from test_gpu_parity import _global_case, gpu_run, rel, tol_for
+from test_gpu_parity import TOL, _global_case, gpu_run, rel, tol_for
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,8 @@ def say(*a):
 
 
 @pytest.mark.parametrize("case,delta", [("small", 0.01), ("small", 0.0), ("ragged", 0.02),
-                                        ("ragged", 0.5)])
+                                        ("ragged", 0.5), ("small", 1e-5), ("small", 1e-7),
+                                        ("ragged", 1e-7)])
 def test_square_tsvd_matches_oracle(case, delta):
     p, W, u0 = _global_case(case)
     Wd = synth.add_noise(p, W, delta)
@@ -114,3 +115,43 @@ def test_square_tsvd_closed_form_rank_one():
     e = {"Vhat": rel(st["Vhat"], ref["Vhat"]), "xi": rel(xi, ref_xi)}
     say("closed form", np.unique(k_ref[act], return_counts=True), e)
     assert all(v <= tol_for(delta) for v in e.values()), e
+
+
+@pytest.mark.parametrize("name", ["n80", "n96", "n128"])
+def test_square_tsvd_large_systems_match_oracle(name):
+    """Truncated SVD of the n = 80, 96 and 128 systems (the uneven batch's
+    and the 256^2 x 128 grid's sizes) on grids the oracle inverts whole: the
+    same truncation count for every solved system, v^ and xi within 1e-10."""
+    from test_gpu_configs import SHAPES, SHAPE_DELTA, TWO_PI, born
+    _, nx, ny, nz, px, py, om, seed, what = next(s for s in SHAPES if s[0] == name)
+    p = synth.make_problem(name, nx, ny, nz, TWO_PI * np.array(om), 3, (seed, nz),
+                           (SHAPE_DELTA,), px=px, py=py)
+    d = SHAPE_DELTA
+    W, u0 = born(p, d)
+    ref_xi, ref = invert.invert(p, W, u0, d, rule="tsvd", stages=True)
+    xi, st = gpu_run(p, W, u0, d, regularizer=1)
+    k_ref = ref["alpha"].reshape(st["alpha"].shape)
+    act = np.isfinite(st["alpha"])
+    mism = np.count_nonzero(st["alpha"][act] != k_ref[act])
+    assert mism == 0, f"{mism} truncation counts differ"
+    e = {k: rel(st[k], ref[k]) for k in ("Vhat", "v", "u")}
+    e["xi"] = rel(xi, ref_xi)
+    say(name, "counts", np.unique(k_ref[act], return_counts=True), e)
+    assert all(v <= TOL for v in e.values()), e
+
+
+def test_square_tsvd_orbit_chunks_match_resident():
+    # the orbits taken a few dozen at a time give bitwise the same result
+    import torch
+    from paper_1911_10487_amd.flayer import Plan
+    p, W, u0 = _global_case("small")
+    Wd = synth.add_noise(p, W, 0.01)
+    out = []
+    for mc in (0, 29):
+        plan = Plan.from_problem(p, regularizer=1, max_chunk=mc)
+        xi = plan.invert(torch.from_numpy(Wd).cuda(), torch.from_numpy(u0).cuda(), 0.01)
+        out.append(xi.cpu().numpy())
+        n_orb = plan.factorized_systems()
+        plan.close()
+    assert n_orb > 2 * 29
+    assert np.array_equal(out[0], out[1])
