@@ -95,12 +95,19 @@ def stage_units(p, active, factorized, n, b, spw):
     return u
 
 
+def counters_path(workload):
+    """profiles/counters_<workload>_<nx>x<ny>x<nz>.json"""
+    from paper_1911_10487_amd import synth
+    p = synth.workload(workload)[0]
+    return os.path.join(ROOT, "profiles", f"counters_{workload}_{p.nx}x{p.ny}x{p.nz}.json")
+
+
 def profiled_traffic(workload, prec, kernel):
     """HBM bytes per step of `kernel` from the committed FETCH_SIZE /
     WRITE_SIZE profile of this workload (scaled by the calibration factors),
     or None when there is none or the HIP sources changed since."""
     from paper_1911_10487_amd.build import source_sha256
-    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    path = counters_path(workload)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -113,6 +120,91 @@ def profiled_traffic(workload, prec, kernel):
     return {"bytes": k["fetch_bytes"] + k["write_bytes"], "fetch_bytes": k["fetch_bytes"],
             "write_bytes": k["write_bytes"], "profiled_avg_us": k["avg_us"],
             "source": os.path.relpath(path, ROOT)}
+
+
+def _short_kernel_name(name):
+    """'void fl::k_bidiag<32, 16, 4, 8, double, 1>(fl::...)' ->
+    'k_bidiag<32, 16, 4, 8, double, 1>'."""
+    s = name.strip()
+    if s.startswith("void "):
+        s = s[5:]
+    depth = 0
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            s = s[:i]
+            break
+    return s[4:] if s.startswith("fl::") else s
+
+
+def ingest_counters(fetch_csv, write_csv, stats_csv, workload, prec, copy_mb):
+    """Per-dispatch HBM bytes of every fl:: kernel from two rocprofv3 --pmc
+    CSVs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), scaled by what the same
+    counters read for the run's calibration kernels (a fill and a sum over
+    copy_mb MiB), merged into profiles/counters_<workload>.json under the
+    digest of the current HIP sources."""
+    import csv
+    from collections import defaultdict
+
+    from paper_1911_10487_amd.build import source_sha256
+    nb_kib = copy_mb * 1024.0
+    raw = {}
+    calib = {}
+    for cname, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != cname:
+                    continue
+                full, v = r["Kernel_Name"], float(r["Counter_Value"])
+                if "FillFunctor<double>" in full:
+                    calib[f"fill_kernel_{cname}_KiB"] = v
+                elif "reduce_kernel" in full and "ReduceOp<double" in full:
+                    calib[f"sum_kernel_{cname}_KiB"] = v
+                elif "fl::" in full:
+                    per[_short_kernel_name(full)].append(v)
+        raw[cname] = per
+    fetch_factor = nb_kib / calib["sum_kernel_FETCH_SIZE_KiB"]
+    write_factor = nb_kib / calib["fill_kernel_WRITE_SIZE_KiB"]
+    avg_us = {}
+    if stats_csv:
+        with open(stats_csv) as fh:
+            for r in csv.DictReader(fh):
+                avg_us[_short_kernel_name(r["Name"])] = float(r["AverageNs"]) * 1e-3
+    kernels = {}
+    for k, vals in raw["FETCH_SIZE"].items():
+        w = raw["WRITE_SIZE"].get(k)
+        if not w:
+            continue
+        kernels[k] = {"calls": len(vals),
+                      "fetch_bytes": float(np.mean(vals)) * 1024.0 * fetch_factor,
+                      "write_bytes": float(np.mean(w)) * 1024.0 * write_factor,
+                      "avg_us": avg_us.get(k)}
+    path = counters_path(workload)
+    digest = source_sha256()
+    js = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            js = json.load(fh)
+        if js.get("source_sha256") != digest:
+            js = {}
+    from paper_1911_10487_amd import synth
+    p = synth.workload(workload)[0]
+    js["source_sha256"] = digest
+    js["workload"] = f"{workload}: {WORKLOAD_TEXT[workload]}"
+    js.setdefault("calibration", {})[prec] = dict(calib, fetch_factor=fetch_factor,
+                                                  write_factor=write_factor,
+                                                  calibration_bytes=copy_mb << 20)
+    js.setdefault("kernels", {})[prec] = kernels
+    js["grid"] = [p.nx, p.ny, p.nz, p.n_omega]
+    with open(path, "w") as fh:
+        json.dump(js, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(f"wrote {os.path.relpath(path, ROOT)}: {len(kernels)} kernels ({prec}), "
+          f"fetch x{fetch_factor:.4f}, write x{write_factor:.4f}")
 
 
 # ------------------------------------------------------------------ data
@@ -569,7 +661,19 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device fill, sum and copy of this many MiB before "
                          "timing (known-size kernels for scaling HBM counters)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 --pmc CSVs (FETCH_SIZE, WRITE_SIZE) "
+                         "of a run with --calibrate-copy-mb into the workload's counters "
+                         "profile (precision from --only)")
+    ap.add_argument("--ingest-stats", metavar="KERNEL_STATS_CSV", default=None,
+                    help="with --ingest-counters: rocprofv3 --stats kernel CSV for avg_us")
     args = ap.parse_args()
+    if args.ingest_counters:
+        if not args.only or not args.calibrate_copy_mb:
+            ap.error("--ingest-counters needs --only and --calibrate-copy-mb")
+        ingest_counters(*args.ingest_counters, args.ingest_stats, args.workload, args.only,
+                        args.calibrate_copy_mb)
+        return
     if args.gpus != 1:
         print(f"bench.py: the inversion runs on a single GPU; --gpus {args.gpus} is not "
               "supported (the sharding design is in DESIGN.md)", file=sys.stderr)

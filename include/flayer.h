@@ -362,8 +362,8 @@ void fl_batch_destroy(fl_batch *batch);
  *                   a TR x TC thread grid per system (each thread holds an
  *                   (n/TR) x (n/TC) block of the matrix in registers) and a
  *                   waves-per-SIMD register budget (fl_tuning_describe)
- *   bidiag_grid     workgroups of the persistent bidiagonalization launch
- *                   (0 = 8192 for n <= 64, else 2048)
+ *   bidiag_grid     unused (kept for the layout): the bidiagonalization
+ *                   launches one workgroup per factorization
  *   dp_grid         one-wave workgroups of the discrepancy launch (0 = 16384)
  *   dp_systems_per_wave  systems w one discrepancy wave takes, each in a
  *                   group of 64 / w lanes for the reflector passes and the

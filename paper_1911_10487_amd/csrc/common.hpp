@@ -161,6 +161,51 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// value of lane l (uniform) of the wave, whatever the execution mask
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cx<double> lane_read(cx<double> v, int l) {
+  return mk(lane_read(v.x, l), lane_read(v.y, l));
+}
+
+// ---- reduce-scatter steps: of the pair (lo, hi) of values held by every
+// lane, the lanes on the lower side of a lane pairing end with lo summed over
+// the pair and the lanes on the upper side with hi summed over the pair, so
+// each sum is formed once and the values to carry halve.
+
+// pairing i <-> i ^ 16 (lower side: bit 4 clear). The swap leaves the lower
+// lane (lo, partner's lo) and the upper lane (partner's hi, hi).
+__device__ __forceinline__ double rs_xor16(double lo, double hi) {
+  const auto rl = __builtin_amdgcn_permlane16_swap(__double2loint(lo), __double2loint(hi), false, false);
+  const auto rh = __builtin_amdgcn_permlane16_swap(__double2hiint(lo), __double2hiint(hi), false, false);
+  return __hiloint2double(rh[0], rl[0]) + __hiloint2double(rh[1], rl[1]);
+}
+// pairing i <-> i ^ 32 (lower side: bit 5 clear)
+__device__ __forceinline__ double rs_xor32(double lo, double hi) {
+  const auto rl = __builtin_amdgcn_permlane32_swap(__double2loint(lo), __double2loint(hi), false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(__double2hiint(lo), __double2hiint(hi), false, false);
+  return __hiloint2double(rh[0], rl[0]) + __hiloint2double(rh[1], rl[1]);
+}
+// A DPP pairing inside each row of 16 lanes whose lower side is the lanes of
+// the DPP banks (groups of four lanes) in LOWER: row_mirror (i <-> 15 - i,
+// lower = banks 0 and 1) or row_half_mirror (i <-> 7 - i within eight,
+// lower = banks 0 and 2). A DPP move writes only the lanes of its enabled
+// banks, so the lower lanes take their partner's lo and keep their own, the
+// upper lanes their partner's hi.
+template <int CTRL, int LOWER>
+__device__ __forceinline__ double rs_dpp(double lo, double hi) {
+  const int ll = __double2loint(lo), lh = __double2hiint(lo);
+  const int hl = __double2loint(hi), hh = __double2hiint(hi);
+  const int tl = __builtin_amdgcn_update_dpp(hl, ll, CTRL, 0xF, LOWER, false);
+  const int th = __builtin_amdgcn_update_dpp(hh, lh, CTRL, 0xF, LOWER, false);
+  const int ul = __builtin_amdgcn_update_dpp(ll, hl, CTRL, 0xF, 0xF ^ LOWER, false);
+  const int uh = __builtin_amdgcn_update_dpp(lh, hh, CTRL, 0xF, 0xF ^ LOWER, false);
+  return __hiloint2double(th, tl) + __hiloint2double(uh, ul);
+}
+
 // Sum over aligned groups of W lanes (W = 16, 32, 64).
 template <int W>
 __device__ __forceinline__ double lanes_sum(double v) {

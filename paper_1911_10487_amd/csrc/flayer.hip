@@ -424,7 +424,10 @@ const std::vector<BdVariant>& bd_variants(int n) {
 
 template <typename T>
 fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk0, int C,
-                        unsigned grid, BidiagOut& o, const int* resident = nullptr) {
+                        BidiagOut& o, const int* resident = nullptr) {
+  // one workgroup per slot of the chunk; slots past the active count end at once
+  if (C <= 0) return FL_OK;
+  const unsigned grid = (unsigned)C;
   const int n = p->n;
   const z64* What = (const z64*)p->What;
   const auto& vs = bd_variants(n);
@@ -518,10 +521,8 @@ fl_status solve_prepare(fl_plan* p, bool compact) {
 template <typename T>
 fl_status run_bidiag(fl_plan* p, long c0) {
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, nullptr, nullptr};
-  const long gdef = p->n <= 64 ? 8192 : 2048;
-  const unsigned gb = (unsigned)std::min<long>(p->C, p->bd_grid > 0 ? p->bd_grid : gdef);
   RUN(mark(p, FL_STAGE_BIDIAG));
-  return launch_bidiag<T>(p, p->list, p->count, (int)c0, p->C, gb, o);
+  return launch_bidiag<T>(p, p->list, p->count, (int)c0, p->C, o);
 }
 
 // Systems per wave of the discrepancy kernel (fl_tuning.dp_systems_per_wave;
@@ -696,10 +697,8 @@ fl_status run_bidiag_orbits(fl_plan* p, long o0 = 0, bool reuse = false) {
   const long FO = orbit_bound(p);
   const int C = (int)std::min<long>(p->C, FO - o0);
   BidiagOut o{p->dg, p->sp, p->q, p->fro, p->wnc, p->refl, p->gam, p->refl_l, p->gam_l};
-  const long gdef = p->n <= 64 ? 8192 : 2048;
-  const unsigned gb = (unsigned)std::min<long>(C, p->bd_grid > 0 ? p->bd_grid : gdef);
   RUN(mark(p, FL_STAGE_BIDIAG));
-  RUN(launch_bidiag<T>(p, p->olist, p->ocount, (int)o0, C, gb, o,
+  RUN(launch_bidiag<T>(p, p->olist, p->ocount, (int)o0, C, o,
                        reuse ? p->oresident : nullptr));
   if (p->prefactored) return FL_OK;
   hipLaunchKernelGGL(k_mark_resident, dim3(1), dim3(1), 0, p->st, p->oresident, p->ocount, (int)o0);
@@ -1367,22 +1366,19 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
   };
   fl_status st = FL_OK;
   float bt = 1e30f;
-  const int grids[] = {1024, 2048, 4096, 8192};
   const int nv = (int)bd_variants(p->n).size();
-  for (int v = 0; v < nv && st == FL_OK; ++v)
-    for (int g : grids) {
-      p->bd_var = v;
-      p->bd_grid = g;
-      float ms = 0.f;
-      st = time_it([&] { return p->last_shared ? run_bidiag_orbits<T>(p) : run_bidiag<T>(p, 0); },
-                   &ms);
-      if (st != FL_OK) break;
-      if (ms < bt) {
-        bt = ms;
-        best->bidiag_variant = v;
-        best->bidiag_grid = g;
-      }
+  best->bidiag_grid = 0;
+  for (int v = 0; v < nv && st == FL_OK; ++v) {
+    p->bd_var = v;
+    float ms = 0.f;
+    st = time_it([&] { return p->last_shared ? run_bidiag_orbits<T>(p) : run_bidiag<T>(p, 0); },
+                 &ms);
+    if (st != FL_OK) break;
+    if (ms < bt) {
+      bt = ms;
+      best->bidiag_variant = v;
     }
+  }
   p->bd_var = best->bidiag_variant;
   p->bd_grid = best->bidiag_grid;
   float dt = 1e30f;

@@ -287,6 +287,80 @@ struct BidiagOut {
   double* gam_l;
 };
 
+constexpr int pow2ceil(int v) { return v <= 1 ? 1 : 2 * pow2ceil((v + 1) / 2); }
+
+// Sums of the VP complex values v over each aligned group of TR lanes (TR =
+// 16, 32 or 64; VP a power of two): reduce-scatter over the group's lane bits
+// 5..2 while a lane carries more than one value (each sum is formed once), a
+// full butterfly over the remaining bits, then every lane of the group reads
+// the VP totals from the group's VP slots gat of LDS. A wave's LDS accesses
+// complete in order, so the exchange needs no barrier.
+template <int TR, int VP>
+__device__ __forceinline__ void group_sums(z64 (&v)[VP], z64* gat, int lane) {
+  double d[2 * VP];
+#pragma unroll
+  for (int i = 0; i < VP; ++i) {
+    d[2 * i] = v[i].x;
+    d[2 * i + 1] = v[i].y;
+  }
+  int idx = 0;  // first of the values this lane carries
+  // bit 5 (i ^ 32)
+  constexpr int C5 = (TR == 64 && VP >= 2) ? VP / 2 : VP;
+  if constexpr (TR == 64) {
+    if constexpr (VP >= 2) {
+#pragma unroll
+      for (int i = 0; i < 2 * C5; ++i) d[i] = rs_xor32(d[i], d[i + 2 * C5]);
+      if (lane & 32) idx += C5;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2 * C5; ++i) d[i] = add_xor32(d[i]);
+    }
+  }
+  // bit 4 (i ^ 16)
+  constexpr int C4 = (TR >= 32 && C5 >= 2) ? C5 / 2 : C5;
+  if constexpr (TR >= 32) {
+    if constexpr (C5 >= 2) {
+#pragma unroll
+      for (int i = 0; i < 2 * C4; ++i) d[i] = rs_xor16(d[i], d[i + 2 * C4]);
+      if (lane & 16) idx += C4;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2 * C4; ++i) d[i] = add_xor16(d[i]);
+    }
+  }
+  // bit 3 (row_mirror, i <-> 15 - i)
+  constexpr int C3 = C4 >= 2 ? C4 / 2 : C4;
+  if constexpr (C4 >= 2) {
+#pragma unroll
+    for (int i = 0; i < 2 * C3; ++i) d[i] = rs_dpp<0x140, 0x3>(d[i], d[i + 2 * C3]);
+    if (lane & 8) idx += C3;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2 * C3; ++i) d[i] += dpp_d<0x140>(d[i]);
+  }
+  // bit 2 (row_half_mirror, i <-> 7 - i within eight)
+  constexpr int C2 = C3 >= 2 ? C3 / 2 : C3;
+  if constexpr (C3 >= 2) {
+#pragma unroll
+    for (int i = 0; i < 2 * C2; ++i) d[i] = rs_dpp<0x141, 0x5>(d[i], d[i + 2 * C2]);
+    if (lane & 4) idx += C2;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2 * C2; ++i) d[i] += dpp_d<0x141>(d[i]);
+  }
+  // bits 1 and 0 (quad_perm [2,3,0,1], [1,0,3,2])
+#pragma unroll
+  for (int i = 0; i < 2 * C2; ++i) {
+    d[i] += dpp_d<0x4E>(d[i]);
+    d[i] += dpp_d<0xB1>(d[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < C2; ++i) gat[idx + i] = mk(d[2 * i], d[2 * i + 1]);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+  for (int i = 0; i < VP; ++i) v[i] = gat[i];
+}
+
 // Exchange areas of one bidiagonalization workgroup (index = step parity).
 template <int n, int NW>
 struct BdShared {
@@ -300,6 +374,7 @@ struct BdShared {
   double gm[n];
   double gl[n];       // left gamma of every step
   double red[2][NW];
+  z64 cg[NW][64];     // per wave: the column sums of its lane groups
 };
 
 // One Householder step k (left reflector from column k, right reflector
@@ -326,16 +401,16 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
           if (b == kb) col[a] = A[a][b];
       }
       double s = 0.0;
-      z64 piv = mk(0.0, 0.0);
+      z64 pc = mk(0.0, 0.0);
 #pragma unroll
       for (int a = SA; a < NA; ++a) {
         const int i = r + TR * a;
         if (i >= k) s += nrm2(col[a]);
-        if (a == ka && r == kr) piv = col[a];
+        if (a == ka) pc = col[a];
       }
       s = lanes_sum<TR>(s);
-      piv.x = lanes_sum<TR>(piv.x);
-      piv.y = lanes_sum<TR>(piv.y);
+      // the pivot A(k, k) from its holder's lane of this wave
+      const z64 piv = lane_read(pc, (kr + TR * kc) & 63);
       const double xn = s > 0.0 ? s * rsq_nr(s) : 0.0;
       const double a2 = nrm2(piv);
       const double iap = a2 > 0.0 ? rsq_nr(a2) : 0.0;
@@ -371,14 +446,23 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
       const int i = r + TR * a;
       ur[a] = (i >= k) ? S.ul[par][i] : mk(0.0, 0.0);
     }
+    // u^H A for the live column slots, summed over the row classes of each
+    // column class at once
+    constexpr int V = NB - SB, VP = pow2ceil(V);
+    z64 sm[VP];
+#pragma unroll
+    for (int b = 0; b < VP; ++b) {
+      z64 t = mk(0.0, 0.0);
+      if (b < V) {
+#pragma unroll
+        for (int a = SA; a < NA; ++a) t = cfmac(t, ur[a], A[a][SB + b]);
+      }
+      sm[b] = t;
+    }
+    group_sums<TR, VP>(sm, &S.cg[wv][(lane / TR) * VP], lane);
 #pragma unroll
     for (int b = SB; b < NB; ++b) {
-      z64 sm = mk(0.0, 0.0);
-#pragma unroll
-      for (int a = SA; a < NA; ++a) sm = cfmac(sm, ur[a], A[a][b]);
-      sm.x = lanes_sum<TR>(sm.x);
-      sm.y = lanes_sum<TR>(sm.y);
-      const z64 w = g * sm;
+      const z64 w = g * sm[b - SB];
       const int j = c + TC * b;
       if (j > k) {
 #pragma unroll
@@ -440,14 +524,47 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
       S.gm[k] = g;
       S.sp[k] = cj(beta);
     }
+    // z = A v on the live row slots; the column classes of this wave are
+    // summed with each row sum formed once, and a lane writes the rows it
+    // ends with
+    {
+      constexpr int V = NA - SA, VP = pow2ceil(V);
+      z64 t[VP];
 #pragma unroll
-    for (int a = SA; a < NA; ++a) {
-      z64 t = mk(0.0, 0.0);
+      for (int a = 0; a < VP; ++a) {
+        z64 x = mk(0.0, 0.0);
+        if (a < V) {
 #pragma unroll
-      for (int b = SB; b < NB; ++b) t = cfma(t, A[a][b], vr[b]);
-      t.x = strided_sum<TR>(t.x);
-      t.y = strided_sum<TR>(t.y);
-      if (lane < TR) S.zp[par][wv][r + TR * a] = t;
+          for (int b = SB; b < NB; ++b) x = cfma(x, A[SA + a][b], vr[b]);
+        }
+        t[a] = x;
+      }
+      constexpr int K5 = (TR <= 32 && VP >= 2) ? VP / 2 : VP;
+      constexpr int K4 = (TR <= 16 && K5 >= 2) ? K5 / 2 : K5;
+      int idx = 0;
+      if constexpr (TR <= 32) {
+        if constexpr (VP >= 2) {
+#pragma unroll
+          for (int i = 0; i < K5; ++i)
+            t[i] = mk(rs_xor32(t[i].x, t[i + K5].x), rs_xor32(t[i].y, t[i + K5].y));
+          if (lane & 32) idx += K5;
+        } else {
+          t[0] = mk(add_xor32(t[0].x), add_xor32(t[0].y));
+        }
+      }
+      if constexpr (TR <= 16) {
+        if constexpr (K5 >= 2) {
+#pragma unroll
+          for (int i = 0; i < K4; ++i)
+            t[i] = mk(rs_xor16(t[i].x, t[i + K4].x), rs_xor16(t[i].y, t[i + K4].y));
+          if (lane & 16) idx += K4;
+        } else {
+          t[0] = mk(add_xor16(t[0].x), add_xor16(t[0].y));
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < K4; ++i)
+        if (idx + i < V) S.zp[par][wv][r + TR * (SA + idx + i)] = t[i];
     }
     __syncthreads();
     // ---------- D. A <- A (I - g v v^H) on rows > k, columns > k
@@ -523,9 +640,13 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
   // solve made them from the same tables)
   if (resident && *resident == chunk0) return;
 
-  for (int sl = blockIdx.x; sl < C; sl += gridDim.x) {
+  // one factorization per workgroup: with no loop over slots the compiler
+  // keeps the per-element index and address arithmetic of the epilogue out
+  // of the step loops (hoisted out of a slot loop it spilled to scratch)
+  {
+    const int sl = blockIdx.x;
     const int gs = chunk0 + sl;
-    if (gs >= total) break;
+    if (sl >= C || gs >= total) return;
     const int fm = list[gs];
     const long m = fm % N;
     const int f = (int)(fm / N);
