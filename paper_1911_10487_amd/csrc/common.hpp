@@ -6,8 +6,9 @@
 
 namespace fl {
 
+// aligned to its size, so that a complex double moves in one 16-byte access
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 

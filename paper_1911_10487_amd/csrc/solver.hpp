@@ -289,6 +289,12 @@ struct BidiagOut {
 
 constexpr int pow2ceil(int v) { return v <= 1 ? 1 : 2 * pow2ceil((v + 1) / 2); }
 
+// threads per row for summing the wave partials of z: the largest power of
+// two P <= min(NW, 8) with n P <= NT
+constexpr int bd_rows_threads(int n, int NT, int NW, int P = 8) {
+  return (P <= NW && n * P <= NT) || P == 1 ? P : bd_rows_threads(n, NT, NW, P / 2);
+}
+
 // Sums of the VP complex values v over each aligned group of TR lanes (TR =
 // 16, 32 or 64; VP a power of two): reduce-scatter over the group's lane bits
 // 5..2 while a lane carries more than one value (each sum is formed once), a
@@ -368,6 +374,7 @@ struct BdShared {
   z64 ul[2][n];       // left reflector u (entries k..n-1)
   z64 xr[2][n];       // row k after the left update (entries k+1..n-1)
   z64 zp[2][NW][n];   // per-wave partial z = A v
+  z64 zs[n];          // g z, summed over the waves (when they are many)
   double lg[2];       // left gamma
   z64 dg[n], sp[n];
   z64 qv[n];          // q = U^H w (row i kept by the column-class-0 thread of row class i % TR)
@@ -567,15 +574,37 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
         if (idx + i < V) S.zp[par][wv][r + TR * (SA + idx + i)] = t[i];
     }
     __syncthreads();
+    // With eight or more waves the wave partials of z are summed once per
+    // row, by P consecutive threads (NW / P partials each, then a butterfly
+    // over the P lanes), instead of by every holder of the row.
+    constexpr bool COOP = NW >= 8;
+    if constexpr (COOP) {
+      constexpr int P = bd_rows_threads(n, TR * TC, NW), WP = NW / P;
+      if (tid < n * P) {
+        const int i = tid / P, part = tid % P;
+        z64 z = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < WP; ++w) z = z + S.zp[par][part * WP + w][i];
+        if constexpr (P >= 2) z = mk(z.x + dpp_d<0xB1>(z.x), z.y + dpp_d<0xB1>(z.y));
+        if constexpr (P >= 4) z = mk(z.x + dpp_d<0x4E>(z.x), z.y + dpp_d<0x4E>(z.y));
+        if constexpr (P >= 8) z = mk(z.x + dpp_d<0x141>(z.x), z.y + dpp_d<0x141>(z.y));
+        if (part == 0) S.zs[i] = g * z;
+      }
+      __syncthreads();
+    }
     // ---------- D. A <- A (I - g v v^H) on rows > k, columns > k
 #pragma unroll
     for (int a = SA; a < NA; ++a) {
       const int i = r + TR * a;
       if (i > k) {
         z64 z = mk(0.0, 0.0);
+        if constexpr (COOP) {
+          z = S.zs[i];
+        } else {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) z = z + S.zp[par][w][i];
-        z = g * z;
+          for (int w = 0; w < NW; ++w) z = z + S.zp[par][w][i];
+          z = g * z;
+        }
 #pragma unroll
         for (int b = SB; b < NB; ++b) A[a][b] = cfmsc(A[a][b], z, vr[b]);
       } else if (i == k) {
