@@ -366,11 +366,13 @@ void fl_batch_destroy(fl_batch *batch);
  *                   launches one workgroup per factorization
  *   dp_grid         one-wave workgroups of the discrepancy launch (0 = 16384)
  *   dp_systems_per_wave  systems w one discrepancy wave takes, each in a
- *                   group of 64 / w lanes for the reflector passes and the
- *                   Elden solve; with w = 2 or 4 the groups also search their
- *                   systems' alpha at once (64 / w points per round), with
- *                   w = 1 the whole wave searches; 1, 2, 4 (4 for nz <= 64
- *                   only), 0 = 4 for nz <= 64, else 2
+ *                   group of 64 / w lanes for the alpha search (64 / w
+ *                   points per round) and the Elden solve; 1, 2 or 4. With
+ *                   shared orbit factorizations (the default) the
+ *                   reflector passes run orbit by orbit and 0 = 4; with
+ *                   one factorization per system the groups also apply the
+ *                   reflectors, 0 = 4 for nz <= 64, else 2, and 4 counts
+ *                   as 2 above nz = 64
  * Schedules sum in different orders, so their results agree to rounding, not
  * bitwise; a plan starts with schedule {0, 0, 0, 0}.
  */

@@ -14,6 +14,7 @@
 
 #include "../../include/flayer.h"
 #include "adjoint.hpp"
+#include "dp_orbit.hpp"
 #include "fft.hpp"
 #include "joint.hpp"
 #include "pointwise.hpp"
@@ -147,6 +148,8 @@ struct fl_plan {
   // wavenumbers whose stacked system needs a solve, and their compaction
   int *mflag = nullptr, *mlist = nullptr, *mcount = nullptr;
   z64* refl_l = nullptr;
+  z64* qy = nullptr;  // orbit-batched solve: q', then D_R y, per system of a chunk
+  int* opos = nullptr;  // plan-time orbits: first system of every (f, m) position
   double* gam_l = nullptr;
   // truncated SVD of the square systems (regularizer 1): per orbit slot the
   // SVD of the phase-scaled real bidiagonal
@@ -525,9 +528,14 @@ fl_status run_bidiag(fl_plan* p, long c0) {
   return launch_bidiag<T>(p, p->list, p->count, (int)c0, p->C, o);
 }
 
-// Systems per wave of the discrepancy kernel (fl_tuning.dp_systems_per_wave;
-// 0 = 4 for n <= 64, else 2).
-int dp_spw_of(const fl_plan* p) { return p->dp_spw > 0 ? p->dp_spw : (p->n <= 64 ? 4 : 2); }
+// Systems per wave of the per-system discrepancy kernel
+// (fl_tuning.dp_systems_per_wave; 0 = 4 for n <= 64, else 2; 4 is taken as 2
+// above n = 64). The orbit-by-orbit search kernel takes the value as given
+// (0 = 4).
+int dp_spw_of(const fl_plan* p) {
+  const int w = p->dp_spw > 0 ? p->dp_spw : (p->n <= 64 ? 4 : 2);
+  return (w == 4 && p->n > 64) ? 2 : w;
+}
 
 // Discrepancy root, Tikhonov solve and back-transform of the same chunk;
 // fixed: take alpha and the branch per frequency from the global search.
@@ -572,17 +580,46 @@ fl_status run_dp(fl_plan* p, long c0, bool fixed = false, bool shared = false) {
     a.What = (const z64*)p->What;
     a.refl_l = p->refl_l;
     a.gam_l = p->gam_l;
-    if (!p->prefactored) {
-      a.osys0 = p->osys0;
-      a.ocount = p->ocount;
-      a.slot0 = (int)c0;
-      a.OC = p->C;
-    }
+    // orbits [c0, c0 + C) of the compacted list in slots 0..; with plan-time
+    // factorizations every orbit holds its own slot (c0 = 0)
+    a.osys0 = p->osys0;
+    a.ocount = p->ocount;
+    a.slot0 = (int)c0;
+    a.OC = p->C;
   }
   const int spw = dp_spw_of(p);
   const long ngr = ((long)a.C + spw - 1) / spw;
   const unsigned gd = (unsigned)std::min<long>(ngr, p->dp_grid > 0 ? p->dp_grid : 16384);
   RUN(mark(p, FL_STAGE_DP));
+  if (a.osys0 && !fixed) {
+    // orbit by orbit: phase scaling and q' per orbit, the searches per
+    // system, the back-transforms per orbit; B' and the right phases per
+    // slot in bd_d, bd_e, bd_dr
+    a.qy = p->qy;
+    const unsigned go = (unsigned)a.OC;
+    const int ospw = p->dp_spw > 0 ? p->dp_spw : 4;
+    const unsigned gs = (unsigned)std::min<long>(((long)DPO_MEMBERS * a.OC + ospw - 1) / ospw,
+                                                 p->dp_grid > 0 ? p->dp_grid : 16384);
+#define DPO(NM)                                                                        \
+  hipLaunchKernelGGL((k_dpo_prep<NM>), dim3(go), dim3(64), 0, p->st, a);               \
+  LAUNCHCHK();                                                                         \
+  if (ospw == 4)                                                                       \
+    hipLaunchKernelGGL((k_dpo_search<NM, 4>), dim3(gs), dim3(64), 0, p->st, a);        \
+  else if (ospw == 2)                                                                  \
+    hipLaunchKernelGGL((k_dpo_search<NM, 2>), dim3(gs), dim3(64), 0, p->st, a);        \
+  else                                                                                 \
+    hipLaunchKernelGGL((k_dpo_search<NM, 1>), dim3(gs), dim3(64), 0, p->st, a);        \
+  LAUNCHCHK();                                                                         \
+  hipLaunchKernelGGL((k_dpo_back<NM>), dim3(go), dim3(64), 0, p->st, a);               \
+  LAUNCHCHK();
+    if (p->n <= 64) {
+      DPO(64)
+    } else {
+      DPO(128)
+    }
+#undef DPO
+    return FL_OK;
+  }
   if (p->n <= 64) {
     if (spw == 4)
       hipLaunchKernelGGL((k_dp_solve<64, 4>), dim3(gd), dim3(64), 0, p->st, a);
@@ -679,8 +716,16 @@ fl_status group_by_orbit(fl_plan* p) {
   hipLaunchKernelGGL(k_orbit_scatter, dim3(p->nb_scan), dim3(1024), 0, st, p->oflag, FN, p->omem,
                      p->flag, p->N, p->cnt, p->ocnt, p->prefactored ? nullptr : p->olist,
                      p->prefactored ? nullptr : p->oslot, p->olist_sys,
-                     p->prefactored ? nullptr : p->osys0);
+                     p->prefactored ? nullptr : p->osys0, p->prefactored ? p->opos : nullptr);
   LAUNCHCHK();
+  if (p->prefactored) {
+    // every orbit holds a slot: the slots' member ranges for the
+    // orbit-by-orbit solve
+    const int fo = (int)((long)p->F * p->n_orb);
+    hipLaunchKernelGGL(k_slot_ranges, dim3(nblk(fo, 256)), dim3(256), 0, st, p->olist, fo, p->opos,
+                       p->osys0);
+    LAUNCHCHK();
+  }
   return FL_OK;
 }
 
@@ -1385,7 +1430,6 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
   const int dgrids[] = {2048, 4096, 8192, 16384};
   const int spws[] = {1, 2, 4};
   for (int w : spws) {
-    if (w == 4 && p->n > 64) continue;
     for (int g : dgrids) {
       if (st != FL_OK) break;
       p->dp_grid = g;
@@ -1840,6 +1884,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
     long budget = 80L << 30;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess) budget = std::min<long>(budget, (long)(fr / 5 * 2));
     long slot = (long)sizeof(z64) * (tri_size(ns, 1) + (shared ? tri_size(ns, 0) : 0));
+    // the orbit-batched solve keeps q' and then D_R y of up to eight members
+    if (shared) slot += (long)sizeof(z64) * DPO_MEMBERS * ns;
     // the truncated SVD keeps both singular vector sets of every slot
     if (o.regularizer == 1 && !thin) slot += 2L * ns * ns * (long)sizeof(double);
     long cap = std::max<long>(1024, budget / slot);
@@ -1899,6 +1945,8 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
       PALLOC(p->oresident, 1);
       PALLOC(p->refl_l, C * tri_size(ns, 0));
       PALLOC(p->gam_l, C * ns);
+      PALLOC(p->qy, std::min<long>(DPO_MEMBERS * C, FN) * ns);
+      if (o.prefactor) PALLOC(p->opos, FN + 1);
       hipError_t e = hipMemcpy(p->orep, orep_h.data(), N * sizeof(int), hipMemcpyHostToDevice);
       if (e == hipSuccess)
         e = hipMemcpy(p->omem, omem_h.data(), N * 8 * sizeof(int), hipMemcpyHostToDevice);
@@ -2157,8 +2205,8 @@ fl_status fl_tuning_set(fl_plan* p, const fl_tuning* t) {
     return fail(FL_EINVAL, "bidiag_variant %d out of range [0, %d)", t->bidiag_variant, nv);
   if (t->bidiag_grid < 0 || t->dp_grid < 0) return fail(FL_EINVAL, "grid sizes must be >= 0");
   const int w = t->dp_systems_per_wave;
-  if (!(w == 0 || w == 1 || w == 2 || (w == 4 && p->n <= 64)))
-    return fail(FL_EINVAL, "dp_systems_per_wave %d: 0, 1, 2 (and 4 for nz <= 64)", w);
+  if (!(w == 0 || w == 1 || w == 2 || w == 4))
+    return fail(FL_EINVAL, "dp_systems_per_wave %d: 0, 1, 2 or 4", w);
   p->bd_var = t->bidiag_variant;
   p->bd_grid = t->bidiag_grid;
   p->dp_grid = t->dp_grid;

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ 
                                                         int* __restrict__ olist,
                                                         int* __restrict__ oslot,
                                                         int* __restrict__ list,
-                                                        int* __restrict__ osys0) {
+                                                        int* __restrict__ osys0,
+                                                        int* __restrict__ opos) {
   __shared__ int wsum[16];
   __shared__ int wpre[16];
   const long i = (long)blockIdx.x * 1024 + threadIdx.x;
@@ -169,6 +170,12 @@ __global__ __launch_bounds__(1024) void k_orbit_scatter(const int* __restrict__ 
   __syncthreads();
   // no active orbit at all still leaves an empty first range
   if (osys0 && blockIdx.x == 0 && threadIdx.x == 0) osys0[0] = 0;
+  // first system of every position (orbits fixed at plan creation)
+  if (opos && i < n) {
+    const int pos0 = cntw[blockIdx.x] + incl - c;
+    opos[i] = pos0;
+    if (i == n - 1) opos[n] = pos0 + c;
+  }
   if (c > 0) {
     const int pos0 = cntw[blockIdx.x] + incl - c;
     if (olist) {
@@ -770,6 +777,16 @@ __global__ __launch_bounds__(TR* TC, WPE) void k_bidiag(const z64* __restrict__ 
   }
 }
 
+// Orbits fixed at plan creation (slot s = orbit olist[s], in position
+// order): the systems of slot s are [osys0[s], osys0[s + 1]).
+__global__ void k_slot_ranges(const int* __restrict__ olist, int FO, const int* __restrict__ opos,
+                              int* __restrict__ osys0) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= FO) return;
+  osys0[s] = opos[olist[s]];
+  if (s == FO - 1) osys0[FO] = opos[olist[s] + 1];
+}
+
 // After the factorization of orbit chunk [chunk0, chunk0 + C): the
 // workspace holds it if the chunk had an active orbit (a chunk past the
 // last active orbit factorizes nothing and leaves the previous one).
@@ -808,7 +825,7 @@ struct DpArgs {
   z64* bd_dr;
   const double* alpha_fixed;       // per frequency, or NULL: alpha given (one per
   const signed char* branch_fixed; // frequency) instead of the per-system search
-  // shared factorizations (NULL: one per system): system (f, m) uses slot
+  // shared factorizations (k_dpo_*): system (f, m) uses slot
   // oslot[f N + orep[m]] of dg, sp, fro, refl, gam, and q = U^H w from the
   // slot's left reflectors and w in What
   const int* oslot;
@@ -822,6 +839,9 @@ struct DpArgs {
   const int* osys0;
   const int* ocount;
   int slot0, OC;
+  // orbit-batched solve (k_dpo_*): per system of the launch, q' and then
+  // D_R y; bd_d, bd_e, bd_dr then hold each slot's B' and right phases
+  z64* qy;
 };
 
 // The compacted systems [*first, *first + return value) that one solver
@@ -913,11 +933,13 @@ __device__ void elden_solve(const double* d, const double* e, const z64* q, int 
 
 // Phase scaling of one system's complex bidiagonal (sy: diagonal, srr:
 // superdiagonal, sq: q in LDS) to B = D_L B' D_R^H with B' real and
-// nonnegative: writes sd, se (B'), sdr (right phases) and q' = D_L^H q into sq.
+// nonnegative: writes sd, se (B'), sdr (right phases) and q' = D_L^H q into sq
+// (sq may be NULL), and the left phases D_L into sdl when it is given.
 // One wave; the caller synchronizes afterwards.
 template <int NMAX>
 __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, double* se, z64* sq,
-                                               const z64* srr, const z64* sy, z64* sdr) {
+                                               const z64* srr, const z64* sy, z64* sdr,
+                                               z64* sdl = nullptr) {
   // B = D_L B' D_R^H with B' real nonnegative. The right phases obey
   // r_i = rho_i r_{i-1} (or restart at a zero entry), an affine recurrence
   // evaluated by a parallel prefix over the lanes (elements lane, lane + 64).
@@ -997,7 +1019,8 @@ __device__ __forceinline__ void dp_phase_scale(int n, int lane, double* sd, doub
       if (i < n) {
         sdr[i] = xin[h];
         const z64 dl = dz[h] ? mk(1.0, 0.0) : pd[h] * xin[h];
-        sq[i] = cmulc(dl, sq[i]);
+        if (sq) sq[i] = cmulc(dl, sq[i]);
+        if (sdl) sdl[i] = dl;
       }
     }
   }
@@ -1191,12 +1214,12 @@ __device__ __forceinline__ void group_reflect(z64 (&x)[E], const z64* __restrict
   }
 }
 
-// SPW systems per single-wave workgroup, each in a group of G = 64 / SPW
-// lanes. The phase scaling uses the whole wave for one system at a time; the
-// alpha searches (G trial alphas per round), q = U^H w (shared
-// factorizations), the Elden solve and the back-transform v^ = V (D_R y) run
-// for the SPW systems at once, each in its group, so their reductions span G
-// lanes only.
+// One factorization per system (the shared orbit factorizations go through
+// k_dpo_*): SPW systems per single-wave workgroup, each in a group of
+// G = 64 / SPW lanes. The phase scaling uses the whole wave for one system at
+// a time; the alpha searches (G trial alphas per round), the Elden solve and
+// the back-transform v^ = V (D_R y) run for the SPW systems at once, each in
+// its group, so their reductions span G lanes only.
 template <int NMAX, int SPW>
 __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   constexpr int G = 64 / SPW;
@@ -1221,8 +1244,7 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
   const int nsys = launch_range(a.osys0, a.ocount, a.slot0, a.OC, a.chunk0, a.C, total, &c0);
   const int nact = nsys > 0 ? (nsys + SPW - 1) / SPW : 0;
   // Workgroups go to the eight XCDs in turn: XCD x (of V = min(8, grid))
-  // takes the contiguous group range [x per, (x + 1) per), so that systems
-  // sharing an orbit's reflectors meet in one L2.
+  // takes the contiguous group range [x per, (x + 1) per).
   const int NG = gridDim.x, V = NG < 8 ? NG : 8;
   const int xcd = blockIdx.x % V, nbx = (NG - xcd + V - 1) / V;
   const int per = (nact + V - 1) / V;
@@ -1239,35 +1261,14 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       const int fm = a.list[gs];
       f = (int)(fm / a.N);
       m = fm - (long)f * a.N;
-      // factorization slot: the system's own, or its orbit's
-      fs = a.oslot ? a.oslot[(long)f * a.N + a.orep[m]] - a.slot0 : sl;
+      // the system's own factorization slot
+      fs = sl;
       for (int e = 0; e < E; ++e) {
         const int i = gl + G * e;
         if (i < n) {
           sy[grp][i] = a.dg[fs * n + i];
           srr[grp][i] = a.sp[fs * n + i];
-        }
-      }
-      if (a.oslot) {
-        // q = U^H w = H_{n-2} ... H_0 w from the orbit's left reflectors
-        const z64* w = a.What + (long)f * a.nd * a.N + m;
-        z64 x[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int i = gl + G * e;
-          x[e] = i < a.nd ? w[(long)i * a.N] : mk(0.0, 0.0);
-        }
-        group_reflect<G, E, RG>(x, a.refl_l + fs * tri_size(n, 0), a.gam_l + fs * n, n, gl, 0, n - 1, 1,
-                                0);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int i = gl + G * e;
-          if (i < n) sq[grp][i] = x[e];
-        }
-      } else {
-        for (int e = 0; e < E; ++e) {
-          const int i = gl + G * e;
-          if (i < n) sq[grp][i] = a.q[(long)sl * n + i];
+          sq[grp][i] = a.q[(long)sl * n + i];
         }
       }
     }
@@ -1286,17 +1287,14 @@ __global__ __launch_bounds__(64, SPW == 2 ? 3 : 2) void k_dp_solve(DpArgs a) {
       if (sls >= nsys) break;
       const int fms = a.list[gss];
       const int fsf = (int)(fms / a.N);
-      const long ms = fms - (long)fsf * a.N;
-      const long fss = a.oslot ? a.oslot[(long)fsf * a.N + a.orep[ms]] - a.slot0 : sls;
+      const long fss = sls;
       dp_phase_scale<NMAX>(n, lane, sd[s], se[s], sq[s], srr[s], sy[s], sdr[s]);
       __syncthreads();
-      if (!a.oslot) {
-        // kept for the derivative kernels (per-system factorizations only)
-        for (int i = lane; i < n; i += 64) {
-          a.bd_d[(long)sls * n + i] = sd[s][i];
-          a.bd_e[(long)sls * n + i] = se[s][i];
-          a.bd_dr[(long)sls * n + i] = sdr[s][i];
-        }
+      // kept for the derivative kernels
+      for (int i = lane; i < n; i += 64) {
+        a.bd_d[(long)sls * n + i] = sd[s][i];
+        a.bd_e[(long)sls * n + i] = se[s][i];
+        a.bd_dr[(long)sls * n + i] = sdr[s][i];
       }
       if constexpr (!GROUPED) {
         double al;
