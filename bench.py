@@ -284,7 +284,9 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev, workload, prefactor
     stages = plan.profile_read()
     plan.profile(False)
     esz = 8 if prec else 16
-    spw = tuning["dp_systems_per_wave"] or (4 if p.nz <= 64 else 2)
+    # systems per search wave: the orbit-by-orbit solve (shared
+    # factorizations, the default) takes 4 unless tuned
+    spw = tuning["dp_systems_per_wave"] or 4
     units = stage_units(p, active, factorized, p.nz, esz, spw)
     per_step = {k: v[0] / args.steps for k, v in stages.items()}
     dom = max(per_step, key=per_step.get)
@@ -301,7 +303,7 @@ def time_precision(p, prec, Wd, u0, delta, args, torch, dev, workload, prefactor
         tr, tc, wpe = tuning["schedule"]
         kname = f"k_bidiag<{tr}, {tc}, {p.nz // tr}, {p.nz // tc}, double, {wpe}>"
     elif dom == "dp":
-        kname = f"k_dp_solve<{64 if p.nz <= 64 else 128}, {spw}>"
+        kname = f"k_dpo_search<{64 if p.nz <= 64 else 128}, {spw}>"
     tr_ = profiled_traffic(workload, prec, kname)
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": tr_["bytes"] if tr_ else None,
