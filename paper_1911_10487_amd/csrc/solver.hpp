@@ -643,7 +643,7 @@ __device__ __forceinline__ void bd_blocks(z64 (&A)[NA][NB],
                                           BdShared<TR * NA, (TR * TC + 63) / 64>& S, int r, int c,
                                           int tid, int lane, int wv, bool doq) {
   constexpr int n = TR * NA;
-  constexpr int KB = TR > TC ? TR : TC;
+  constexpr int KB = TR < TC ? TR : TC;
   if constexpr (Q * KB < n) {
     constexpr int SA = Q * KB / TR, SB = Q * KB / TC;
     for (int k = Q * KB; k < (Q + 1) * KB && k < n; ++k)
