@@ -646,6 +646,19 @@ __device__ __forceinline__ void p2_store(const FftArgs& g, const cx<T> (&e)[P2<L
   }
 }
 
+// Block (bx, by) of a 2D grid, renumbered so that each XCD takes a
+// contiguous range of the blocks in linear order (workgroups go to the eight
+// XCDs in turn by linear block id): neighbouring groups of columns, which at
+// 8 bytes per element share 128-byte lines, then meet in one L2.
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+  const long G = gridDim.x, T = G * gridDim.y;
+  const long lin = blockIdx.x + blockIdx.y * G;
+  const long q = T / 8, r = T % 8, x = lin % 8, j = lin / 8;
+  const long lp = x * q + (x < r ? x : r) + j;
+  bx = (int)(lp % G);
+  by = (int)(lp / G);
+}
+
 template <typename T, int L>
 __device__ __forceinline__ void p2_stage_twiddles(const cx<T>* __restrict__ tw, cx<T>* tws, int nt) {
   for (int i = threadIdx.x; i < L; i += nt) tws[i] = tw[i];
@@ -658,9 +671,10 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_p2(Fft
   constexpr int CB = p2_cb<L, T>(), NT = CB * (L / P2<L>::E);
   __shared__ cx<T> tws[L];
   __shared__ typename P2Lds<T>::type lds[CB * p2_row<L>()];
-  int t, bl;
+  int t, bl, bx, by;
   p2_map<L, CB>(g.in_kfast, t, bl);
-  const int b = blockIdx.x * CB + bl, plane = blockIdx.y;
+  xcd_block(bx, by);
+  const int b = bx * CB + bl, plane = by;
   p2_stage_twiddles<T, L>((const cx<T>*)g.tw, tws, NT);
   cx<T> e[P2<L>::E];
   p2_load<TI, T, L>(g, e, b, plane, t);
@@ -688,9 +702,10 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_conv_p
   constexpr int CB = p2_cb<L, T>(), E = P2<L>::E, TT = L / E, NT = CB * TT;
   __shared__ cx<T> tws[L];
   __shared__ typename P2Lds<T>::type lds[CB * p2_row<L>()];
-  int t, bl;
+  int t, bl, bx, by;
   p2_map<L, CB>(0, t, bl);
-  const int b = blockIdx.x * CB + bl, plane = blockIdx.y;
+  xcd_block(bx, by);
+  const int b = bx * CB + bl, plane = by;
   p2_stage_twiddles<T, L>((const cx<T>*)g.tw, tws, NT);
   cx<T> e[E];
   p2_load<T, T, L>(g, e, b, plane, t);

@@ -410,8 +410,8 @@ const std::vector<BdVariant>& bd_variants(int n) {
   static const std::vector<BdVariant> v48{{16, 8, 2}, {16, 16, 1}, {16, 8, 1}};
   static const std::vector<BdVariant> v64{{16, 8, 2}, {16, 16, 3}, {16, 16, 2}, {16, 8, 1}};
   static const std::vector<BdVariant> v80{{16, 16, 1}, {16, 8, 1}};
-  static const std::vector<BdVariant> v96{{16, 16, 1}, {32, 16, 1}};
-  static const std::vector<BdVariant> v128{{32, 16, 1}};
+  static const std::vector<BdVariant> v96{{16, 16, 1}, {32, 16, 1}, {16, 32, 1}};
+  static const std::vector<BdVariant> v128{{16, 32, 1}, {32, 16, 1}};
   static const std::vector<BdVariant> none{};
   switch (n) {
     case 16: return v16;
@@ -473,12 +473,12 @@ fl_status launch_bidiag(fl_plan* p, const int* list, const int* count, int chunk
     }
     case 96: {
       constexpr int NN = 96;
-      BD(16, 16, 1) BD(32, 16, 1)
+      BD(16, 16, 1) BD(32, 16, 1) BD(16, 32, 1)
       break;
     }
     case 128: {
       constexpr int NN = 128;
-      BD(32, 16, 1)
+      BD(16, 32, 1) BD(32, 16, 1)
       break;
     }
     default:
