@@ -1828,6 +1828,14 @@ fl_status fl_plan_create(int nx, int ny, int nz, int nd, double h, const double*
   PALLOC(p->u0w, F * nvox);
   PALLOC(p->wn2, FN);
   PALLOC(p->flag, FN);
+  {
+    // v^ is zero for every system without a solve and stays so between
+    // calls: k_classify zeroes only the systems that were solved last time
+    // and are not now
+    hipError_t e = hipMemset(p->flag, 0, (size_t)FN * sizeof(int));
+    if (e == hipSuccess) e = hipMemset(p->Vh, 0, (size_t)(F * nz * N) * esz);
+    if (e != hipSuccess) return bail(fail(FL_EDEVICE, "plan memset: %s", hipGetErrorString(e)));
+  }
   p->nb_scan = (int)nblk(FN, 1024);
   PALLOC(p->cnt, p->nb_scan);
   PALLOC(p->list, FN);

@@ -26,7 +26,10 @@ namespace fl {
 
 // ---------------------------------------------------------------- classify
 
-// thread per (f, m): wn2 = sum_j |W^[f][j][m]|^2; flag = system needs a solve
+// thread per (f, m): wn2 = sum_j |W^[f][j][m]|^2; flag = system needs a solve.
+// v^ of a system without a solve is zero: the plan starts with v^ = 0 and
+// flag = 0, the solvers write v^ of every flagged system, and this kernel
+// zeroes v^ of a system flagged by the previous call and not by this one.
 template <typename T>
 __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What, int nd, long N,
                                                   int F, const double* __restrict__ thr2,
@@ -61,9 +64,9 @@ __global__ __launch_bounds__(256) void k_classify(const cx<T>* __restrict__ What
   double t = thr2[f];
   // a frequency of weight 0 in the least-squares xi is not solved
   const int act = (fw && fw[f] == 0.0) ? 0 : (solve_all || t < 0.0) ? (s > 0.0) : (s > t);
+  const int was = flag[fm];
   flag[fm] = act;
-  // v^ = 0 for a system without a solve (the solver writes the others)
-  if (!act) {
+  if (!act && was) {
     const long o0 = (long)f * nz * N + m;
     if (vh_single)
       for (int j = 0; j < nz; ++j) ((cx<float>*)Vh)[o0 + (long)j * N] = mk(0.f, 0.f);

@@ -551,6 +551,42 @@ def test_plan_time_factorization_matches_per_call(case, delta):
     assert rel(outs[1][0], ref) <= tol_for(delta)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reused_plan_zeroes_systems_no_longer_solved(precision):
+    """v^ of a system without a solve is zero also when the previous call on
+    the plan solved it (the classification zeroes only such systems): a plan
+    that inverted low-noise data first (many systems solved) gives, on
+    high-noise data (fewer solved), bitwise the v^, branches and xi of a
+    fresh plan, and the oracle's xi."""
+    torch = torch_mod()
+    from paper_1911_10487_amd.flayer import TAP_BRANCH, TAP_VHAT, Plan
+    p, W, u0 = _global_case("small")
+    F, N = p.n_omega, p.px * p.py
+    cw = np.complex64 if precision else np.complex128
+    ut = torch.from_numpy(u0).cuda()
+    W1, W2 = synth.add_noise(p, W, 0.002), synth.add_noise(p, W, 0.2)
+    reused = Plan.from_problem(p, precision=precision)
+    reused.invert(torch.from_numpy(W1).cuda(), ut, 0.002)
+    first = reused.active_systems()
+    x_r = reused.invert(torch.from_numpy(W2).cuda(), ut, 0.2).cpu().numpy()
+    v_r = reused.tap(TAP_VHAT, cw, (F, p.nz, N))
+    b_r = reused.tap(TAP_BRANCH, np.int8, (F, N))
+    second = reused.active_systems()
+    reused.close()
+    fresh = Plan.from_problem(p, precision=precision)
+    x_f = fresh.invert(torch.from_numpy(W2).cuda(), ut, 0.2).cpu().numpy()
+    v_f = fresh.tap(TAP_VHAT, cw, (F, p.nz, N))
+    b_f = fresh.tap(TAP_BRANCH, np.int8, (F, N))
+    fresh.close()
+    say("solved systems", first, "then", second)
+    assert second < first
+    assert np.array_equal(b_r, b_f) and np.array_equal(v_r, v_f) and np.array_equal(x_r, x_f)
+    for f in range(F):
+        assert not np.any(v_r[f][:, b_r[f] == 0])
+    ref = invert.invert(p, W2, u0, 0.2)
+    assert rel(x_r, ref) <= (1e-4 if precision else tol_for(0.2))
+
+
 def test_odd_square_torus_orbits_match_oracle():
     # a 45 x 45 torus: odd lengths, so the mirror images (px - mx) % px have
     # no self-paired Nyquist line, and every orbit of the swap and mirrors
