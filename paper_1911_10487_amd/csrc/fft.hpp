@@ -712,10 +712,15 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_conv_p
   typename P2Lds<T>::type* row = lds + bl * p2_row<L>();
   p2_fft<T, -1, L, false>(e, row, tws, t);
   if (b < g.B) {
+    // The kernel of the z-convolution is even in z (the sampled kernel at
+    // -d equals the one at d), so its transform is even in k: entry L - k
+    // is read as entry k, which another thread of the same transform reads
+    // at the same time, halving the table's HBM reads.
     const cx<T>* K = (const cx<T>*)mul + (long)plane * mul_sp + b;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-      cx<T> kk = K[(long)(t + TT * s) * mul_sk];
+      const int k = t + TT * s;
+      cx<T> kk = K[(long)(k <= L / 2 ? k : L - k) * mul_sk];
       if (conj_mul) kk.y = -kk.y;
       e[s] = e[s] * kk;
     }
