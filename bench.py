@@ -709,6 +709,7 @@ def main():
         r = runs[args.only]
         print(json.dumps({"metric": "voxel-frequencies inverted/s", "precision": args.only,
                           "value": vf / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                          "schedule": r["tuning"],
                           "roofline": r["roofline"], "fft_stages": r["fft_stages"],
                           "hbm_stages": r["hbm_stages"], "stages_ms_per_step": r["stages"]}),
               flush=True)

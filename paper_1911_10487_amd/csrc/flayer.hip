@@ -2398,8 +2398,12 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   LAUNCHCHK();
   RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
   RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));
-  hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
-                     w1, nd, nz, N, F, (int)(p->thin || p->general), w2);
+  if (!p->thin && !p->general && nz % 16 == 0)
+    hipLaunchKernelGGL(k_apply_toeplitz<16>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
+                       w1, nz, N, F, w2);
+  else
+    hipLaunchKernelGGL(k_apply_systems<double>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st,
+                       p->gtab, w1, nd, nz, N, F, (int)(p->thin || p->general), w2);
   LAUNCHCHK();
   FftArgs c = cols_args(w2, w2, p->tw_y, py, px, F * nd);
   RUN((run_fft<double, double, double, 1>(c, st)));

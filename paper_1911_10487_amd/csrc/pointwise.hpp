@@ -290,6 +290,47 @@ __global__ __launch_bounds__(256) void k_apply_systems(const cx<T>* __restrict__
   }
 }
 
+// The same on X's lattice (nd = nz, table entry j - l + nz - 1), nz a
+// multiple of JB: one thread per (f, m) takes JB rows j at a time. The JB
+// table entries those rows need at one l are the ones of the previous l
+// shifted by one, so they stay in registers as a circular buffer (one new
+// entry per l): every v^ entry and table entry is loaded once per row block
+// instead of once per row.
+template <int JB>
+__global__ __launch_bounds__(256) void k_apply_toeplitz(const z64* __restrict__ gtab,
+                                                        const z64* __restrict__ Vh, int nz, long N,
+                                                        int F, z64* __restrict__ Wh) {
+  const long fm = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (fm >= (long)F * N) return;
+  const int f = (int)(fm / N);
+  const long m = fm - (long)f * N;
+  const z64* g = gtab + (long)f * (2 * nz - 1) * N + m;
+  const z64* v = Vh + (long)f * nz * N + m;
+  for (int j0 = 0; j0 < nz; j0 += JB) {
+    // slot (i - l) mod JB holds entry j0 + i - l + nz - 1 at step l
+    z64 c[JB], acc[JB];
+#pragma unroll
+    for (int i = 0; i < JB; ++i) {
+      c[i] = g[(long)(j0 + i + nz - 1) * N];
+      acc[i] = mk(0.0, 0.0);
+    }
+    for (int l0 = 0; l0 < nz; l0 += JB) {
+#pragma unroll
+      for (int lp = 0; lp < JB; ++lp) {
+        const int l = l0 + lp;
+        const z64 vl = v[(long)l * N];
+#pragma unroll
+        for (int i = 0; i < JB; ++i) acc[i] = cfma(acc[i], c[(i - lp) & (JB - 1)], vl);
+        // step l + 1 needs entry j0 - l + nz - 2 for row j0, in the slot row
+        // j0 + JB - 1 has just finished with
+        if (l + 1 < nz) c[(JB - 1 - lp) & (JB - 1)] = g[(long)(j0 + nz - 2 - l) * N];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < JB; ++i) Wh[((long)f * nz + j0 + i) * N + m] = acc[i];
+  }
+}
+
 }  // namespace fl
 
 namespace fl {
