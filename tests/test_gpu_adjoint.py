@@ -129,17 +129,26 @@ def test_power_iteration_matches_oracle(case):
 
 
 def test_mixed_precision_derivatives(case):
+    """Mixed precision (FP32 stage (c) transforms): VJP and JVP against the
+    oracle within 1e-4, and the dot-product identity of the two GPU maps
+    within the same bound."""
     import torch
     p, W, u0, d = case
     g = synth.random_field((p.nz, p.ny, p.nx), (44,))
+    dW = synth.random_field(W.shape, (45,))
     plan = _plan(p, precision=1)
-    gW, _ = plan.vjp(torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda(), d,
-                     torch.from_numpy(g).cuda())
+    Wt, ut = torch.from_numpy(W).cuda(), torch.from_numpy(u0).cuda()
+    gW, _ = plan.vjp(Wt, ut, d, torch.from_numpy(g).cuda())
     gW = gW.cpu().numpy()
+    jv = plan.jvp(Wt, ut, d, torch.from_numpy(dW).cuda()).cpu().numpy()
     plan.close()
     rW, _ = adjoint.vjp(p, W, u0, d, g)
-    say("mixed vjp rel err", rel(gW, rW))
-    assert rel(gW, rW) <= 1e-4
+    rj = adjoint.jvp(p, W, u0, d, dW)
+    say("mixed vjp rel err", rel(gW, rW), "jvp", rel(jv, rj))
+    assert rel(gW, rW) <= 1e-4 and rel(jv, rj) <= 1e-4
+    lhs = np.real(np.vdot(g, jv))
+    rhs = np.real(np.vdot(gW, dW))
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
