@@ -66,6 +66,7 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
   __shared__ double sd[NMAX], se[NMAX];
   __shared__ z64 sq[NMAX], srr[NMAX], sy[NMAX], sdr[NMAX];
   __shared__ double sth;
+  __shared__ double cn[NMAX];  // squared column norms of M
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int total = min(*count - slot0, C);
   const int m2 = n + (n & 1);  // a zero column pads an odd n
@@ -95,13 +96,23 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
       M[t] = b;
     }
     __syncthreads();
+    for (int cc = tid; cc < m2; cc += NT) {
+      double f = 0.0;
+      for (int r = 0; r < n; ++r) f = fma(M[cc * PITCH + r], M[cc * PITCH + r], f);
+      cn[cc] = f;
+    }
+    __syncthreads();
     // Pairs of columns whose squared norms are both below th = eta ||B'||_F^2 / n
     // are not rotated: at convergence every other pair is orthogonal, so the
     // columns below th span a subspace whose largest singular value squared
     // is below their summed squared norms, < n th, the floor under which no
     // triplet is kept; the kept triplets are unchanged and their sweeps end
-    // in about half the count
-    const double th = sth;
+    // in about half the count. The squared column norms are kept in cn (exact
+    // sums over the column after every load or rotation), so such a pair is
+    // not even loaded: most pairs of a sweep are (about ten of the 128 columns
+    // of a bench orbit lie above the floor). The margin keeps a column whose
+    // kept norm rounds just below th in the exact test.
+    const double th = sth, thm = th * (1.0 - 1e-9);
     const int p = tid >> 3, h = tid & 7;
     // rows h + 8 s of both columns: the rows past n are zero in M, so
     // every thread handles its eight rows with no bound test and all loads of
@@ -110,9 +121,9 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
     for (int sweep = 0; sweep < 40; ++sweep) {
       int rot = 0;
       for (int rd = 0; rd < m2 - 1; ++rd) {
-        if (p < m2 / 2) {
-          int i, j;
-          rr_pair(m2, rd, p, i, j);
+        int i = 0, j = 0;
+        if (p < m2 / 2) rr_pair(m2, rd, p, i, j);
+        if (p < m2 / 2 && (cn[i] >= thm || cn[j] >= thm)) {
           double* Mi = M + i * PITCH + h;
           double* Mj = M + j * PITCH + h;
           double x[RPT], y[RPT];
@@ -144,11 +155,27 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
             const double z2 = fma(z, z, 1.0);
             const double t = copysign(rcp_nr(fabs(z) + z2 * rsq_nr(z2)), z);
             const double cs = rsq_nr(fma(t, t, 1.0)), sn = cs * t;
+            double a2 = 0.0, b2 = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < RPT; ++s2) {
-              Mi[8 * s2] = cs * x[s2] - sn * y[s2];
-              Mj[8 * s2] = sn * x[s2] + cs * y[s2];
+              const double xr = cs * x[s2] - sn * y[s2], yr = sn * x[s2] + cs * y[s2];
+              Mi[8 * s2] = xr;
+              Mj[8 * s2] = yr;
+              a2 = fma(xr, xr, a2);
+              b2 = fma(yr, yr, b2);
             }
+            a2 += __shfl_xor(a2, 1);
+            b2 += __shfl_xor(b2, 1);
+            a2 += __shfl_xor(a2, 2);
+            b2 += __shfl_xor(b2, 2);
+            a2 += __shfl_xor(a2, 4);
+            b2 += __shfl_xor(b2, 4);
+            a = a2;
+            b = b2;
+          }
+          if (h == 0) {
+            cn[i] = a;
+            cn[j] = b;
           }
         }
         __syncthreads();
