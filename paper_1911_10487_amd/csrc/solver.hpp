@@ -299,6 +299,36 @@ struct BidiagOut {
 
 constexpr int pow2ceil(int v) { return v <= 1 ? 1 : 2 * pow2ceil((v + 1) / 2); }
 
+// Householder scalars of a vector x with s = |x|^2 and pivot entry x_k = piv:
+// beta = -(x_k / |x_k|) |x|, the entry that replaces x_k, and
+// g = 1 / (|x| (|x| + |x_k|)), so that I - g u u^H with u = x - beta e_k maps
+// x to beta e_k. One reciprocal square root of P = s |x_k|^2 gives both
+// |x| / |x_k| = s / sqrt(P) and |x| |x_k| = P / sqrt(P). A zero (or
+// negligible: P below the normal range) pivot takes phase 1; s = 0 gives
+// beta = 0 and g = 0 (no reflection).
+__device__ __forceinline__ void hh_scalars(double s, z64 piv, z64& beta, double& g) {
+  const double P = s * nrm2(piv);
+  const bool phased = P > 1e-290;
+  const double Pv = phased ? P : s;
+  const double rp = Pv > 0.0 ? rsq_nr(Pv) : 0.0;
+  const double xa = s * rp;  // |x| / |x_k|, or |x| when the pivot has no phase
+  beta = phased ? mk(-piv.x * xa, -piv.y * xa) : mk(-xa, 0.0);
+  const double den = phased ? s + P * rp : s;
+  g = den > 0.0 ? rcp_nr(den) : 0.0;
+}
+
+// Pairwise sum of v[B..E) (E > B): a tree of depth log2(E - B) instead of a
+// chain of E - B - 1 dependent additions.
+template <int B, int E, int N>
+__device__ __forceinline__ double range_sum(const double (&v)[N]) {
+  if constexpr (E - B == 1) {
+    return v[B];
+  } else {
+    constexpr int M = (B + E) / 2;
+    return range_sum<B, M>(v) + range_sum<M, E>(v);
+  }
+}
+
 // threads per row for summing the wave partials of z: the largest power of
 // two P <= min(NW, 8) with n P <= NT
 constexpr int bd_rows_threads(int n, int NT, int NW, int P = 8) {
@@ -391,6 +421,7 @@ struct BdShared {
   double gm[n];
   double gl[n];       // left gamma of every step
   double red[2][NW];
+  alignas(16) double rn[2][NW];  // per wave: its part of |row k beyond the diagonal|^2
   z64 cg[NW][64];     // per wave: the column sums of its lane groups
 };
 
@@ -417,30 +448,26 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
         for (int b = SB; b < NB; ++b)
           if (b == kb) col[a] = A[a][b];
       }
-      double s = 0.0;
+      double sq[NA];
       z64 pc = mk(0.0, 0.0);
 #pragma unroll
       for (int a = SA; a < NA; ++a) {
         const int i = r + TR * a;
-        if (i >= k) s += nrm2(col[a]);
+        sq[a] = (i >= k) ? nrm2(col[a]) : 0.0;
         if (a == ka) pc = col[a];
       }
-      s = lanes_sum<TR>(s);
+      const double s = lanes_sum<TR>(range_sum<SA, NA>(sq));
       // the pivot A(k, k) from its holder's lane of this wave
       const z64 piv = lane_read(pc, (kr + TR * kc) & 63);
-      const double xn = s > 0.0 ? s * rsq_nr(s) : 0.0;
-      const double a2 = nrm2(piv);
-      const double iap = a2 > 0.0 ? rsq_nr(a2) : 0.0;
-      const double ap = a2 * iap;
-      const z64 ph = a2 > 0.0 ? mk(piv.x * iap, piv.y * iap) : mk(1.0, 0.0);
-      const z64 beta = mk(-ph.x * xn, -ph.y * xn);
+      z64 beta;
+      double gl;
+      hh_scalars(s, piv, beta, gl);
 #pragma unroll
       for (int a = SA; a < NA; ++a) {
         const int i = r + TR * a;
         if (i >= k) S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
       }
       if (r == kr) {
-        const double gl = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
         S.lg[par] = gl;
         S.gl[k] = gl;
         S.dg[k] = beta;
@@ -502,30 +529,34 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
   }
   const int rk = n - k - 1;
   if (rk >= 2) {
-    if (r == kr) {
+    // row k beyond the diagonal: its holders publish it, and each wave
+    // publishes the part of its squared norm that the wave holds
+    double rs = 0.0;
 #pragma unroll
-      for (int b = SB; b < NB; ++b) {
-        const int j = c + TC * b;
-        if (j > k) {
+    for (int a = SA; a < NA; ++a) {
+      if (a == ka) {
 #pragma unroll
-          for (int a = SA; a < NA; ++a)
-            if (a == ka) S.xr[par][j] = A[a][b];
+        for (int b = SB; b < NB; ++b) {
+          const int j = c + TC * b;
+          if (j > k) {
+            rs += nrm2(A[a][b]);
+            if (r == kr) S.xr[par][j] = A[a][b];
+          }
         }
       }
     }
+    rs = strided_sum<TR>(rs);
+    if (lane == kr) S.rn[par][wv] = rs;
     __syncthreads();
-    // ---------- C. right reflector from row k (every wave computes it)
-    double s = 0.0;
-    for (int j = k + 1 + lane; j < n; j += 64) s += nrm2(S.xr[par][j]);
-    s = lanes_sum<64>(s);
-    const double xn = s > 0.0 ? s * rsq_nr(s) : 0.0;
-    const z64 piv = cj(S.xr[par][k + 1]);
-    const double a2 = nrm2(piv);
-    const double iap = a2 > 0.0 ? rsq_nr(a2) : 0.0;
-    const double ap = a2 * iap;
-    const z64 ph = a2 > 0.0 ? mk(piv.x * iap, piv.y * iap) : mk(1.0, 0.0);
-    const z64 beta = mk(-ph.x * xn, -ph.y * xn);
-    const double g = xn > 0.0 ? rcp_nr(xn * (xn + ap)) : 0.0;
+    // ---------- C. right reflector from row k (every wave computes it, from
+    // the same partial norms in the same order)
+    double rn[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) rn[w] = S.rn[par][w];
+    const double s = range_sum<0, NW>(rn);
+    z64 beta;
+    double g;
+    hh_scalars(s, cj(S.xr[par][k + 1]), beta, g);
     z64 vr[NB];
 #pragma unroll
     for (int b = SB; b < NB; ++b) {
@@ -556,32 +587,44 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
         }
         t[a] = x;
       }
-      constexpr int K5 = (TR <= 32 && VP >= 2) ? VP / 2 : VP;
-      constexpr int K4 = (TR <= 16 && K5 >= 2) ? K5 / 2 : K5;
-      int idx = 0;
-      if constexpr (TR <= 32) {
-        if constexpr (VP >= 2) {
+      // reduce-scatter over the 2 VP doubles (real and imaginary parts as
+      // separate values), so that at small VP the last levels still halve
+      // the values a lane carries instead of summing both parts in full
+      constexpr bool L5 = TR <= 32, L4 = TR <= 16;
+      constexpr int D0 = 2 * VP;
+      constexpr int D1 = L5 ? D0 / 2 : D0;
+      constexpr int D2 = (L4 && D1 >= 2) ? D1 / 2 : D1;
+      double d[D0];
 #pragma unroll
-          for (int i = 0; i < K5; ++i)
-            t[i] = mk(rs_xor32(t[i].x, t[i + K5].x), rs_xor32(t[i].y, t[i + K5].y));
-          if (lane & 32) idx += K5;
+      for (int i = 0; i < VP; ++i) {
+        d[2 * i] = t[i].x;
+        d[2 * i + 1] = t[i].y;
+      }
+      int idx = 0;  // first of the doubles this lane ends with
+      if constexpr (L5) {
+#pragma unroll
+        for (int j = 0; j < D1; ++j) d[j] = rs_xor32(d[j], d[j + D1]);
+        if (lane & 32) idx += D1;
+      }
+      if constexpr (L4) {
+        if constexpr (D1 >= 2) {
+#pragma unroll
+          for (int j = 0; j < D2; ++j) d[j] = rs_xor16(d[j], d[j + D2]);
+          if (lane & 16) idx += D2;
         } else {
-          t[0] = mk(add_xor32(t[0].x), add_xor32(t[0].y));
+          d[0] = add_xor16(d[0]);
         }
       }
-      if constexpr (TR <= 16) {
-        if constexpr (K5 >= 2) {
+      if constexpr (D2 >= 2) {
 #pragma unroll
-          for (int i = 0; i < K4; ++i)
-            t[i] = mk(rs_xor16(t[i].x, t[i + K4].x), rs_xor16(t[i].y, t[i + K4].y));
-          if (lane & 16) idx += K4;
-        } else {
-          t[0] = mk(add_xor16(t[0].x), add_xor16(t[0].y));
+        for (int e = 0; e < D2 / 2; ++e) {
+          const int ci = idx / 2 + e;
+          if (ci < V) S.zp[par][wv][r + TR * (SA + ci)] = mk(d[2 * e], d[2 * e + 1]);
         }
+      } else {
+        const int ci = idx / 2;
+        if (ci < V) reinterpret_cast<double*>(&S.zp[par][wv][r + TR * (SA + ci)])[idx & 1] = d[0];
       }
-#pragma unroll
-      for (int i = 0; i < K4; ++i)
-        if (idx + i < V) S.zp[par][wv][r + TR * (SA + idx + i)] = t[i];
     }
     __syncthreads();
     // With eight or more waves the wave partials of z are summed once per
@@ -592,9 +635,9 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
       constexpr int P = bd_rows_threads(n, TR * TC, NW), WP = NW / P;
       if (tid < n * P) {
         const int i = tid / P, part = tid % P;
-        z64 z = mk(0.0, 0.0);
+        z64 z = S.zp[par][part * WP][i];
 #pragma unroll
-        for (int w = 0; w < WP; ++w) z = z + S.zp[par][part * WP + w][i];
+        for (int w = 1; w < WP; ++w) z = z + S.zp[par][part * WP + w][i];
         if constexpr (P >= 2) z = mk(z.x + dpp_d<0xB1>(z.x), z.y + dpp_d<0xB1>(z.y));
         if constexpr (P >= 4) z = mk(z.x + dpp_d<0x4E>(z.x), z.y + dpp_d<0x4E>(z.y));
         if constexpr (P >= 8) z = mk(z.x + dpp_d<0x141>(z.x), z.y + dpp_d<0x141>(z.y));
