@@ -462,10 +462,12 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
       z64 beta;
       double gl;
       hh_scalars(s, piv, beta, gl);
+      // rows above k are written too (B masks them), so the stores need no
+      // branch
 #pragma unroll
       for (int a = SA; a < NA; ++a) {
         const int i = r + TR * a;
-        if (i >= k) S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
+        S.ul[par][i] = (i == k) ? (col[a] - beta) : col[a];
       }
       if (r == kr) {
         S.lg[par] = gl;
@@ -487,8 +489,11 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
     z64 ur[NA];
 #pragma unroll
     for (int a = SA; a < NA; ++a) {
+      // loads without a branch (every index is in range), so that they can
+      // be issued early; the rows above k are masked afterwards
       const int i = r + TR * a;
-      ur[a] = (i >= k) ? S.ul[par][i] : mk(0.0, 0.0);
+      const z64 u = S.ul[par][i];
+      ur[a] = (i >= k) ? u : mk(0.0, 0.0);
     }
     // u^H A for the live column slots, summed over the row classes of each
     // column class at once
@@ -506,12 +511,11 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
     group_sums<TR, VP>(sm, &S.cg[wv][(lane / TR) * VP], lane);
 #pragma unroll
     for (int b = SB; b < NB; ++b) {
-      const z64 w = g * sm[b - SB];
+      // columns up to k take w = 0, which leaves them unchanged
       const int j = c + TC * b;
-      if (j > k) {
+      const z64 w = (j > k) ? g * sm[b - SB] : mk(0.0, 0.0);
 #pragma unroll
-        for (int a = SA; a < NA; ++a) A[a][b] = cfms(A[a][b], ur[a], w);
-      }
+      for (int a = SA; a < NA; ++a) A[a][b] = cfms(A[a][b], ur[a], w);
     }
     if (doq && c == 0) {
       z64 qa[NA];
@@ -531,6 +535,7 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
   if (rk >= 2) {
     // row k beyond the diagonal: its holders publish it, and each wave
     // publishes the part of its squared norm that the wave holds
+    // (entries up to column k are written too: C masks them)
     double rs = 0.0;
 #pragma unroll
     for (int a = SA; a < NA; ++a) {
@@ -538,10 +543,8 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
 #pragma unroll
         for (int b = SB; b < NB; ++b) {
           const int j = c + TC * b;
-          if (j > k) {
-            rs += nrm2(A[a][b]);
-            if (r == kr) S.xr[par][j] = A[a][b];
-          }
+          rs += (j > k) ? nrm2(A[a][b]) : 0.0;
+          if (r == kr) S.xr[par][j] = A[a][b];
         }
       }
     }
@@ -561,12 +564,8 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
 #pragma unroll
     for (int b = SB; b < NB; ++b) {
       const int j = c + TC * b;
-      z64 v = mk(0.0, 0.0);
-      if (j > k) {
-        v = cj(S.xr[par][j]);
-        if (j == k + 1) v = v - beta;
-      }
-      vr[b] = v;
+      const z64 x = cj(S.xr[par][j]);
+      vr[b] = (j > k) ? ((j == k + 1) ? x - beta : x) : mk(0.0, 0.0);
     }
     if (tid == 0) {
       S.gm[k] = g;
@@ -648,21 +647,26 @@ __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR 
     // ---------- D. A <- A (I - g v v^H) on rows > k, columns > k
 #pragma unroll
     for (int a = SA; a < NA; ++a) {
+      // rows up to k take z = 0, which leaves them unchanged
       const int i = r + TR * a;
-      if (i > k) {
-        z64 z = mk(0.0, 0.0);
-        if constexpr (COOP) {
-          z = S.zs[i];
-        } else {
+      z64 z;
+      if constexpr (COOP) {
+        z = S.zs[i];
+      } else {
+        z = S.zp[par][0][i];
 #pragma unroll
-          for (int w = 0; w < NW; ++w) z = z + S.zp[par][w][i];
-          z = g * z;
-        }
+        for (int w = 1; w < NW; ++w) z = z + S.zp[par][w][i];
+        z = g * z;
+      }
+      z = (i > k) ? z : mk(0.0, 0.0);
 #pragma unroll
-        for (int b = SB; b < NB; ++b) A[a][b] = cfmsc(A[a][b], z, vr[b]);
-      } else if (i == k) {
-        // row k is finished: keep the right reflector in its place (LAPACK
-        // style); entries j <= k keep the left reflectors of columns j
+      for (int b = SB; b < NB; ++b) A[a][b] = cfmsc(A[a][b], z, vr[b]);
+    }
+    // row k is finished: keep the right reflector in its place (LAPACK
+    // style); entries j <= k keep the left reflectors of columns j
+#pragma unroll
+    for (int a = SA; a < NA; ++a) {
+      if (r + TR * a == k) {
 #pragma unroll
         for (int b = SB; b < NB; ++b)
           if (c + TC * b > k) A[a][b] = vr[b];
