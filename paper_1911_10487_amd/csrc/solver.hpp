@@ -428,7 +428,8 @@ struct BdShared {
 // One Householder step k (left reflector from column k, right reflector
 // from row k). Row slots a < SA and column slots b < SB hold only finished
 // rows / columns for every k of the current block and are skipped at compile
-// time; the partially finished slots keep per-element tests.
+// time; in the partially finished slots the finished rows and columns are
+// masked per element (by selects, so that the step is straight-line code).
 template <int TR, int TC, int NA, int NB, int SA, int SB>
 __device__ __forceinline__ void bd_step(z64 (&A)[NA][NB], BdShared<TR * NA, (TR * TC + 63) / 64>& S,
                                         int k, int r, int c, int tid, int lane, int wv, bool doq) {
