@@ -707,7 +707,7 @@ def main():
     vf = p.voxel_frequencies
     if args.only:
         r = runs[args.only]
-        print(json.dumps({"metric": "voxel-frequencies inverted/s", "precision": args.only,
+        print(json.dumps({"metric": "voxel-frequencies inverted/s; mixed vs FP64 plain at ξ rel-L2 ≤1e-4", "precision": args.only,
                           "value": vf / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
                           "schedule": r["tuning"],
                           "roofline": r["roofline"], "fft_stages": r["fft_stages"],
