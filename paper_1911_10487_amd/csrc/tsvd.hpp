@@ -139,15 +139,18 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
             b = fma(y[s2], y[s2], b);
             c = fma(x[s2], y[s2], c);
           }
-          a += __shfl_xor(a, 1);
-          b += __shfl_xor(b, 1);
-          c += __shfl_xor(c, 1);
-          a += __shfl_xor(a, 2);
-          b += __shfl_xor(b, 2);
-          c += __shfl_xor(c, 2);
-          a += __shfl_xor(a, 4);
-          b += __shfl_xor(b, 4);
-          c += __shfl_xor(c, 4);
+          // sums over the pair's eight lanes by DPP moves (partners lane ^ 1,
+          // lane ^ 2, then the other four of the eight), not through the LDS
+          // crossbar, which the column loads already keep busy
+          a += dpp_d<0xB1>(a);
+          b += dpp_d<0xB1>(b);
+          c += dpp_d<0xB1>(c);
+          a += dpp_d<0x4E>(a);
+          b += dpp_d<0x4E>(b);
+          c += dpp_d<0x4E>(c);
+          a += dpp_d<0x141>(a);
+          b += dpp_d<0x141>(b);
+          c += dpp_d<0x141>(c);
           if (a > 0.0 && b > 0.0 && c * c > tol * tol * (a * b) && (a >= th || b >= th)) {
             rot = 1;
             // the smaller root t of t^2 + 2 z t - 1 = 0, cos = 1 / sqrt(1 + t^2)
@@ -164,12 +167,12 @@ __global__ __launch_bounds__(4 * NMAX) void k_tsvd_svd(const z64* __restrict__ d
               a2 = fma(xr, xr, a2);
               b2 = fma(yr, yr, b2);
             }
-            a2 += __shfl_xor(a2, 1);
-            b2 += __shfl_xor(b2, 1);
-            a2 += __shfl_xor(a2, 2);
-            b2 += __shfl_xor(b2, 2);
-            a2 += __shfl_xor(a2, 4);
-            b2 += __shfl_xor(b2, 4);
+            a2 += dpp_d<0xB1>(a2);
+            b2 += dpp_d<0xB1>(b2);
+            a2 += dpp_d<0x4E>(a2);
+            b2 += dpp_d<0x4E>(b2);
+            a2 += dpp_d<0x141>(a2);
+            b2 += dpp_d<0x141>(b2);
             a = a2;
             b = b2;
           }
