@@ -678,7 +678,9 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: the inversion runs on a single GPU; --gpus {args.gpus} is not "
-              "supported (the sharding design is in DESIGN.md)", file=sys.stderr)
+              "supported (the systems are independent per frequency and wavenumber, so a "
+              "multi-GPU run would split the frequencies and all-reduce two per-voxel sums; "
+              "not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
