@@ -79,8 +79,10 @@ def stage_units(p, active, factorized, n, b, spw):
         "ifft_cols": ("GB/s", planes_n * b + rows_y * b),
         "crop_pad": ("GB/s", rows_y * b + F * nvox * 16 + rows_y * b),
         "conv_cols": ("GB/s", rows_y * b + planes_n * b),
-        # read the nz nonzero z samples and the 2 nz kernel values, write nz
-        "conv_z": ("GB/s", planes_n * b + 2 * planes_n * b + planes_n * b),
+        # read the nz nonzero z samples and the kernel's transform, write nz;
+        # the transform is even in k, so only its entries 0..nz of 2 nz are
+        # read
+        "conv_z": ("GB/s", planes_n * b + F * (nz + 1) * N * b + planes_n * b),
         "conv_icols": ("GB/s", planes_n * b + rows_y * b),
         "conv_irows": ("GB/s", rows_y * b + 2 * F * nvox * 16),
         "xi": ("GB/s", 2 * F * nvox * 16 + nvox * 16),
