@@ -239,7 +239,10 @@ fl_status fl_invert_jvp(fl_plan *plan, const void *W, const void *u0, double del
  * tol ||u0|| (tol = 0 means 1e-12); FL_ENOCONV if one has not converged
  * after maxit iterations (W_out is then untouched). The Krylov vectors
  * (eight arrays shaped like u0, complex128) are allocated by the first such
- * call and kept by the plan.
+ * call and kept by the plan. With the data planes on X's z-lattice and 2 nz
+ * a power of two, the first call also forms and keeps the z-transforms of
+ * the system table ([n_omega][2 nz][py][px] complex128), with which the
+ * data operator runs as a convolution along z.
  *   xi     [nz][ny][nx] real float64, device; u0 as in fl_invert (device)
  *   W_out  [n_omega][nd][py][px] complex128, device
  */

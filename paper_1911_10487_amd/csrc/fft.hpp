@@ -694,8 +694,10 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_p2(Fft
 
 // z-direction convolution (column map): forward transform of the
 // zero-extended input, product with mul[k * mul_sk + b] (plane offset
-// mul_sp, conjugated when conj_mul), inverse transform, pruned store.
-template <typename T, int L>
+// mul_sp, conjugated when conj_mul), inverse transform, pruned store. EVEN:
+// mul is the transform of a kernel even in z (entries 0..L/2 are read);
+// otherwise every entry is read.
+template <typename T, int L, bool EVEN = true>
 __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_conv_p2(FftArgs g, const void* mul,
                                                                               long mul_sk, long mul_sp,
                                                                               int conj_mul) {
@@ -712,15 +714,16 @@ __global__ __launch_bounds__((p2_cb<L, T>() * (L / P2<L>::E))) void k_fft_conv_p
   typename P2Lds<T>::type* row = lds + bl * p2_row<L>();
   p2_fft<T, -1, L, false>(e, row, tws, t);
   if (b < g.B) {
-    // The kernel of the z-convolution is even in z (the sampled kernel at
-    // -d equals the one at d), so its transform is even in k: entry L - k
-    // is read as entry k, which another thread of the same transform reads
-    // at the same time, halving the table's HBM reads.
+    // The volume kernel of the z-convolution is even in z (the sampled
+    // kernel at -d equals the one at d), so its transform is even in k:
+    // entry L - k is read as entry k, which another thread of the same
+    // transform reads at the same time, halving the table's HBM reads.
     const cx<T>* K = (const cx<T>*)mul + (long)plane * mul_sp + b;
 #pragma unroll
     for (int s = 0; s < E; ++s) {
       const int k = t + TT * s;
-      cx<T> kk = K[(long)(k <= L / 2 ? k : L - k) * mul_sk];
+      const int kt = EVEN ? (k <= L / 2 ? k : L - k) : k;
+      cx<T> kk = K[(long)kt * mul_sk];
       if (conj_mul) kk.y = -kk.y;
       e[s] = e[s] * kk;
     }

@@ -89,6 +89,7 @@ struct fl_plan {
   z64* gtab = nullptr;  // [F][nzeta][N]
   z64* gsys = nullptr;  // [F][N][TP]
   z64* ktab = nullptr;  // [F][2nz][N]
+  z64* ttab = nullptr;  // [F][2nz][N] z-transforms of the gtab rows (first fl_forward)
   // single-precision copies used by the mixed path
   z32 *tw_x32 = nullptr, *tw_y32 = nullptr, *tw_z32 = nullptr;
   z32* ktab32 = nullptr;
@@ -1452,6 +1453,39 @@ fl_status tune_impl(fl_plan* p, int reps, fl_tuning* best) {
 }
 // ------------------------------------------------------------ forward solve
 
+// The data operator on X's lattice as a convolution along z: W^[j] =
+// sum_l t[j - l + nz - 1] V^[l] is entry j + nz - 1 of the 2nz-point
+// circular convolution of the table row t (2nz - 1 entries, zero padded)
+// with the zero-extended V^ column, and no entry of that window wraps
+// around. The transforms of the table rows, scaled by 1 / (2nz) for the
+// unnormalized inverse, are formed by the first call that needs them.
+fl_status ensure_toeplitz_transform(fl_plan* p) {
+  if (p->ttab) return FL_OK;
+  const long N = p->N;
+  const int F = p->F, nz2 = 2 * p->nz;
+  z64* tt = nullptr;
+  ALLOC(tt, (long)F * nz2 * N);
+  FftArgs g{};
+  g.in = p->gtab;
+  g.out = tt;
+  g.tw = p->tw_z;
+  g.L = nz2;
+  g.lin = nz2 - 1;
+  g.lout = nz2;
+  g.in_sk = N;
+  g.in_sb = 1;
+  g.in_sp = (long)(nz2 - 1) * N;
+  g.out_sk = N;
+  g.out_sb = 1;
+  g.out_sp = (long)nz2 * N;
+  g.B = (int)N;
+  g.planes = F;
+  g.scale = 1.0 / nz2;
+  RUN((run_fft<double, double, double, -1>(g, p->st)));
+  p->ttab = tt;
+  return FL_OK;
+}
+
 fl_status ensure_ls_buffers(fl_plan* p) {
   if (p->has_ls) return FL_OK;
   const long F = p->F, nvox = (long)p->nx * p->ny * p->nz;
@@ -2398,7 +2432,39 @@ fl_status fl_forward(fl_plan* p, const double* xi, const void* u0, double tol, i
   LAUNCHCHK();
   RUN((run_fft<double, double, double, -1>(rows_args(w1, w1, p->tw_x, px, (long)F * nz * py), st)));
   RUN((run_fft<double, double, double, -1>(cols_args(w1, w1, p->tw_y, py, px, F * nz), st)));
-  if (!p->thin && !p->general && nz % 16 == 0)
+  if (!p->thin && !p->general && p2_supported(2 * nz)) {
+    RUN(ensure_toeplitz_transform(p));
+    FftArgs z{};
+    z.in = w1;
+    z.out = w2;
+    z.tw = p->tw_z;
+    z.L = 2 * nz;
+    z.lin = nz;
+    z.lout = nz;
+    z.out_off = nz - 1;
+    z.in_sk = N;
+    z.in_sb = 1;
+    z.in_sp = (long)nz * N;
+    z.out_sk = N;
+    z.out_sb = 1;
+    z.out_sp = (long)nz * N;
+    z.B = (int)N;
+    z.planes = F;
+    z.scale = 1.0;
+#define APPLYP2(LL)                                                                             \
+  hipLaunchKernelGGL((k_fft_conv_p2<double, LL, false>), dim3(nblk(N, p2_cb<LL, double>()), F), \
+                     dim3(p2_cb<LL, double>() * (LL / P2<LL>::E)), 0, st, z, p->ttab, (long)N,  \
+                     (long)2 * nz * N, 0)
+    switch (2 * nz) {
+      case 32: APPLYP2(32); break;
+      case 64: APPLYP2(64); break;
+      case 128: APPLYP2(128); break;
+      case 256: APPLYP2(256); break;
+      case 512: APPLYP2(512); break;
+      default: APPLYP2(1024); break;
+    }
+#undef APPLYP2
+  } else if (!p->thin && !p->general && nz % 16 == 0)
     hipLaunchKernelGGL(k_apply_toeplitz<16>, dim3(nblk((long)F * N, 256)), dim3(256), 0, st, p->gtab,
                        w1, nz, N, F, w2);
   else
