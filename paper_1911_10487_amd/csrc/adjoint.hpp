@@ -76,20 +76,31 @@ __device__ __forceinline__ z64 wdot(z64 a0, z64 a1, z64 b0, z64 b1) {
   return s;
 }
 
+// A shared slot's complex bidiagonal (cy, cs) is needed only by the phase
+// scaling, before vec, irho and off are first written: it shares their
+// storage (less LDS per workgroup, more resident waves).
 template <int NMAX>
 struct AdjShared {
   z64 t[2 * NMAX];
-  z64 vec[NMAX];
-  double d[NMAX], e[NMAX], irho[NMAX], off[NMAX];
+  union {
+    z64 vec[NMAX];
+    z64 cy[NMAX];
+  };
+  double d[NMAX], e[NMAX];
+  union {
+    struct {
+      double irho[NMAX], off[NMAX];
+    };
+    z64 cs[NMAX];
+  };
   z64 dr[NMAX];
-  z64 cy[NMAX], cs[NMAX], cq[NMAX];  // a shared slot's complex bidiagonal, scratch
 };
 
 // y = M^-1 x for the wave-distributed x (entries lane, lane + 64)
 template <int NMAX>
 __device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64& x1) {
   constexpr int E = NMAX / 64;  // elements per lane: lane, lane + 64
-  constexpr int RG = E == 1 ? 8 : 4;  // reflector rows loaded ahead
+  constexpr int RG = E == 1 ? 8 : 2;  // reflector rows loaded ahead
   const int n = a.n, lane = threadIdx.x;
   const z64* R = a.refl + (long)sl * tri_size(n, 1);
   const double* G = a.gam + (long)sl * n;
@@ -182,10 +193,9 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
       for (int i = lane; i < n; i += 64) {
         S.cy[i] = a.dg[(long)fs * n + i];
         S.cs[i] = a.sp[(long)fs * n + i];
-        S.cq[i] = mk(0.0, 0.0);
       }
       __syncthreads();
-      dp_phase_scale<NMAX>(n, lane, S.d, S.e, S.cq, S.cs, S.cy, S.dr);
+      dp_phase_scale<NMAX>(n, lane, S.d, S.e, nullptr, S.cs, S.cy, S.dr);
     } else {
       for (int i = lane; i < n; i += 64) {
         S.d[i] = a.bd_d[(long)sl * n + i];
