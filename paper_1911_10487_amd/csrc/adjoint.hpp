@@ -143,8 +143,10 @@ __device__ void minv(const AdjArgs& a, AdjShared<NMAX>& S, int sl, z64& x0, z64&
   x1 = E > 1 ? x[E - 1] : mk(0.0, 0.0);
 }
 
-// (A x)_j = sum_l t[j - l + n - 1] x_l, or (A^H x)_l = sum_j conj(t[j - l + n - 1]) x_j
-template <int NMAX, bool HERM>
+// (A x)_j = sum_l t[j - l + n - 1] x_l, or (A^H x)_l = sum_j conj(t[j - l + n - 1]) x_j,
+// each sum in P partial sums (l mod P) so that consecutive products do not
+// wait for each other; the last n mod P terms go to the first
+template <int NMAX, bool HERM, int P>
 __device__ void toeplitz(AdjShared<NMAX>& S, int n, z64& x0, z64& x1) {
   const int lane = threadIdx.x;
   if (lane < n) S.vec[lane] = x0;
@@ -155,14 +157,32 @@ __device__ void toeplitz(AdjShared<NMAX>& S, int n, z64& x0, z64& x1) {
   for (int h = 0; h < 2; ++h) {
     const int j = lane + 64 * h;
     if (j < n) {
-      z64 acc = mk(0.0, 0.0);
-      for (int l = 0; l < n; ++l) {
-        if (HERM)
-          acc = cfmac(acc, S.t[l - j + n - 1], S.vec[l]);
-        else
-          acc = cfma(acc, S.t[j - l + n - 1], S.vec[l]);
+      z64 acc[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q] = mk(0.0, 0.0);
+      const int nP = n & ~(P - 1);  // P a power of two
+      for (int l0 = 0; l0 < nP; l0 += P) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const int l = l0 + q;
+          if (HERM)
+            acc[q] = cfmac(acc[q], S.t[l - j + n - 1], S.vec[l]);
+          else
+            acc[q] = cfma(acc[q], S.t[j - l + n - 1], S.vec[l]);
+        }
       }
-      o[h] = acc;
+      for (int l = nP; l < n; ++l) {
+        if (HERM)
+          acc[0] = cfmac(acc[0], S.t[l - j + n - 1], S.vec[l]);
+        else
+          acc[0] = cfma(acc[0], S.t[j - l + n - 1], S.vec[l]);
+      }
+      if constexpr (P == 4)
+        o[h] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+      else if constexpr (P == 2)
+        o[h] = acc[0] + acc[1];
+      else
+        o[h] = acc[0];
     }
   }
   __syncthreads();
@@ -174,6 +194,8 @@ __device__ void toeplitz(AdjShared<NMAX>& S, int n, z64& x0, z64& x1) {
 template <int NMAX, int MODE>
 __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
   __shared__ AdjShared<NMAX> S;
+  // partial sums per Toeplitz product (more would cost a wave per SIMD)
+  constexpr int TP = 2;
   const int lane = threadIdx.x;
   const int n = a.n;
   const int total = *a.count;
@@ -240,9 +262,9 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
       phia = 2.0 * al * wdot(vh0, vh1, m0, m1).x;
       if (MODE == 0) sx2 = -wdot(x0i, x1i, m0, m1).x; // s = -Re(v^bar^H x2)
       z64 a0 = m0, a1 = m1;
-      toeplitz<NMAX, false>(S, n, a0, a1);            // A x2
+      toeplitz<NMAX, false, TP>(S, n, a0, a1);            // A x2
       z64 r0 = vh0, r1 = vh1;
-      toeplitz<NMAX, false>(S, n, r0, r1);            // A v^
+      toeplitz<NMAX, false, TP>(S, n, r0, r1);            // A v^
       r0 = r0 - w0;
       r1 = r1 - w1;
       q0 = 2.0 * ((-al) * a0 - r0);
@@ -251,7 +273,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
     if (MODE == 0) {
       z64 y0 = x0i, y1 = x1i;
       minv<NMAX>(a, S, fs, y0, y1);
-      toeplitz<NMAX, false>(S, n, y0, y1);            // A M^-1 v^bar
+      toeplitz<NMAX, false, TP>(S, n, y0, y1);            // A M^-1 v^bar
       double c = 0.0;
       if (root) {
         c = sx2 / phia;
@@ -264,7 +286,7 @@ __global__ __launch_bounds__(64) void k_sys_adjoint(AdjArgs a) {
       if (lane == 0) a.cm[fm] = c;
     } else {
       z64 b0 = x0i, b1 = x1i;
-      toeplitz<NMAX, true>(S, n, b0, b1);             // A^H w'
+      toeplitz<NMAX, true, TP>(S, n, b0, b1);             // A^H w'
       if (root) {
         const double ad = (a.Tdot[f] - wdot(q0, q1, x0i, x1i).x) / phia;
         b0 = b0 - ad * vh0;
