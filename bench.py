@@ -521,6 +521,8 @@ def time_variants(p, Wd, u0, delta, args, torch, dev, iters):
     vf = p.voxel_frequencies
     reps = max(1, min(args.steps, 5))
     for label, prec in (("fp64", 0), ("mixed", 1)):
+        if args.only and label != args.only:
+            continue
         plan = Plan.from_problem(p, precision=prec)
         g = torch.randn((p.nz, p.ny, p.nx), dtype=torch.complex128, device=dev)
         dW = torch.randn(Wd.shape, dtype=Wd.dtype, device=dev)
@@ -652,7 +654,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None,
-                    help="time one precision only (profiling runs)")
+                    help="time one precision only (profiling runs; its derivative "
+                         "figures too unless --no-variants)")
     ap.add_argument("--eager", action="store_true",
                     help="time eager fl_invert calls instead of graph replays")
     ap.add_argument("--tune", action="store_true",
@@ -711,11 +714,16 @@ def main():
     vf = p.voxel_frequencies
     if args.only:
         r = runs[args.only]
+        # the derivative figures of this precision too, unless --no-variants
+        var = (None if args.no_variants else
+               time_variants(p, res["Wd"], res["u0"], delta, args, torch, dev,
+                             args.power_iterations))
         print(json.dumps({"metric": "voxel-frequencies inverted/s; mixed vs FP64 plain at ξ rel-L2 ≤1e-4", "precision": args.only,
                           "value": vf / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
                           "schedule": r["tuning"],
                           "roofline": r["roofline"], "fft_stages": r["fft_stages"],
-                          "hbm_stages": r["hbm_stages"], "stages_ms_per_step": r["stages"]}),
+                          "hbm_stages": r["hbm_stages"], "stages_ms_per_step": r["stages"],
+                          "variants": var}),
               flush=True)
         return
     variants = None
